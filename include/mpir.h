@@ -1,0 +1,175 @@
+/*
+ * mpir.h -- C ABI of an MI355X (gfx950) library for mixed-precision
+ * iterative refinement (IR) of dense linear systems A x = b.
+ *
+ * Method (Kelley, "Using MultiPrecisionArrays.jl: Iterative Refinement in
+ * Julia", arXiv:2311.14616, Algorithm IR): copy A from the working precision
+ * TW into the factorization precision TF (A_F = I_W^F(A)), factor
+ * A_F = P^T L U with partial pivoting, then repeat  d = U^{-1} L^{-1} r,
+ * x <- x + d,  r = b - A x  (residual in precision TR)  until a termination
+ * rule of section "Terminating the while loop" fires.
+ *
+ * Conventions shared by every entry point:
+ *  - Matrices and vectors passed as `d*` are DEVICE pointers owned by the
+ *    caller.  A is column-major (LAPACK / Julia layout) with leading
+ *    dimension lda >= n.  Host pointers are named without the `d` prefix.
+ *  - Precisions: TW in {F64, F32}; TF in {F32, F16} below TW, or TF == TW;
+ *    TR in {TW, F64} (section "Evaluating the residual in extended
+ *    precision").  BF16 is reserved and rejected.
+ *  - Every call is ordered on the HIP stream given to mpir_factor (a
+ *    hipStream_t passed as void*, NULL = the default stream) and returns
+ *    only when its results are in place (it synchronises that stream).
+ *  - Errors are returned as mpir_status; nothing aborts.  A failed call
+ *    leaves caller-owned outputs unspecified and owned handles valid.
+ *  - One handle must not be used by two host threads at once.
+ */
+#ifndef MPIR_H
+#define MPIR_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define MPIR_HIST_MAX 64
+
+typedef enum { MPIR_F64 = 0, MPIR_F32 = 1, MPIR_F16 = 2, MPIR_BF16 = 3 } mpir_prec;
+
+typedef enum {
+    MPIR_OK = 0,
+    MPIR_ERR_SINGULAR = 1,      /* exact zero pivot; *info = its 1-based column */
+    MPIR_ERR_ARG = -1,          /* bad size, pointer or precision triple */
+    MPIR_ERR_ALLOC = -2,        /* device allocation failed */
+    MPIR_ERR_HIP = -3,          /* a HIP runtime call failed */
+    MPIR_ERR_NONFINITE = -4,    /* NaN or infinity in A or b */
+    MPIR_ERR_RANGE = -5,        /* an entry of A overflows in TF (e.g. |a| >= 65520 for F16) */
+    MPIR_ERR_DEVICE = -7        /* a kernel's bounded inter-workgroup wait expired */
+} mpir_status;
+
+typedef enum {
+    MPIR_STOP_CONVERGED = 0,    /* eq. residterm or eq. term satisfied (or r == 0) */
+    MPIR_STOP_STAGNATED = 1,    /* eq. stag: ||r_new|| >= Rmax ||r_old|| */
+    MPIR_STOP_DSTAGNATED = 2,   /* eq. wilkterm: ||d_new|| >= Rmax ||d_old|| (TR wider than TW) */
+    MPIR_STOP_LITMAX = 3,       /* litmax corrections done */
+    MPIR_STOP_NONFINITE = 4     /* a residual or correction became NaN/Inf */
+} mpir_stop;
+
+/* Termination parameters: the paper's TERM structure (Cr, Ce, Rmax, litmax)
+ * plus the choice between eq. residterm (residterm = 1) and eq. term
+ * (residterm = 0).  tol_rel > 0 replaces the factor C*u_w of either test
+ * (u_w = eps(TW): 2^-52 for F64, 2^-23 for F32). */
+typedef struct {
+    double Cr, Ce, Rmax;
+    int32_t litmax;             /* 1 .. MPIR_HIST_MAX-1 */
+    int32_t residterm;
+    double tol_rel;
+} mpir_term;
+
+/* Iteration statistics (the paper's reporting=true output: rhist, dhist).
+ * n_iter = number of corrections; rhist[0] = ||b||, rhist[k] = ||r|| after
+ * correction k; dhist[k-1] = ||d_k||.  All norms are infinity norms. */
+typedef struct {
+    int32_t n_iter, stop, n_hist, reserved;
+    double rhist[MPIR_HIST_MAX], dhist[MPIR_HIST_MAX];
+    double relres;              /* ||b - A x|| / ||b|| of the returned x, FP64 */
+    double bwd_err;             /* ||b - A x|| / (||A|| ||x|| + ||b||), FP64 */
+    double anorm_inf, bnorm_inf, xnorm_inf;
+    int64_t info;
+    double t_factor_ms, t_ir_ms;
+} mpir_report;
+
+typedef struct mpir_fact_s *mpir_fact;
+
+/* Defaults of the paper's term_parms_default: Cr = Ce = 1, Rmax = .5,
+ * litmax = 10, residterm = 1, tol_rel = 0. */
+void mpir_term_default(mpir_term *t);
+
+/* mplu (section "Options and data structures for mplu"): build the
+ * multiprecision factorization of the n x n matrix dA (column-major, TW,
+ * lda).  Computes A_F = I_W^F(A) and ||A||_inf (FP64), then the blocked
+ * right-looking LU with partial pivoting of A_F in TF.
+ *  - The handle BORROWS dA: it must stay allocated and unchanged until
+ *    mpir_refactor or mpir_destroy (the residual reads it).
+ *  - The handle OWNS the TF copy, the pivots and all workspace.
+ *  - F16 factorization: binary16 L and U, binary32 trailing matrix (each U
+ *    row rounded to binary16 when it becomes final, each multiplier rounded
+ *    to binary16 when formed; MFMA products of binary16 operands accumulate
+ *    in binary32).
+ *  - *out receives the handle also on MPIR_ERR_SINGULAR (*info = first zero
+ *    pivot, 1-based, LAPACK semantics: the factorization is completed);
+ *    on any other error *out is NULL. */
+mpir_status mpir_factor(int64_t n, const void *dA, int64_t lda, mpir_prec tw,
+                        mpir_prec tf, mpir_prec tr, void *hip_stream,
+                        mpir_fact *out, int64_t *info);
+
+/* mplu!(MPF, B): refactor a matrix of the same size and precisions into an
+ * existing handle, reusing its storage.  dA is borrowed as above. */
+mpir_status mpir_refactor(mpir_fact f, const void *dA, int64_t lda, int64_t *info);
+
+/* One low-precision solve (eqs. vdlow / promotevd):
+ * dx = sigma * I_F^W( U^{-1} L^{-1} I_W^F(P db / sigma) ), sigma the power
+ * of two with ||db||/sigma in (1/2, 1].  db, dx: n entries in TW. */
+mpir_status mpir_solve(mpir_fact f, const void *db, void *dx);
+
+/* Algorithm IR from x = 0 on the factorization f.  db, dx: n entries in TW
+ * (dx output only).  t = NULL uses mpir_term_default.  rep (host) may be
+ * NULL.  Non-convergence is MPIR_OK with rep->stop != CONVERGED. */
+mpir_status mpir_ir_solve(mpir_fact f, const void *db, void *dx,
+                          const mpir_term *t, mpir_report *rep);
+
+/* Batched IR for `batch` independent systems of uneven sizes n[k] (host
+ * array).  dA[k], db[k], dx[k]: host arrays of device pointers; lda[k] >= n[k].
+ * Same precisions for every system; reps: host array of `batch` reports.
+ * Every system is factored and refined on the device in one persistent
+ * launch; the call returns the first failing status (per-system status in
+ * reps[k].info: 0, or the first zero pivot). */
+mpir_status mpir_ir_solve_batched(int32_t batch, const int64_t *n,
+                                  const void *const *dA, const int64_t *lda,
+                                  const void *const *db, void *const *dx,
+                                  mpir_prec tw, mpir_prec tf, mpir_prec tr,
+                                  const mpir_term *t, mpir_report *reps,
+                                  void *hip_stream);
+
+/* Release a handle (NULL is allowed). */
+void mpir_destroy(mpir_fact f);
+
+/* Text of a status code (static storage). */
+const char *mpir_status_str(mpir_status s);
+
+/* ---- Inspection entry points, for testing each step against a reference.
+ * They run the same kernels as the calls above. ---- */
+
+/* The interprecision copy A_F = I_W^F(A) (section "Introduction", notation
+ * after Algorithm IR): dAF receives fl_F(a_ij) in ROW-major order (n*n
+ * entries of TF: double, float or binary16), *anorm (host) = ||A||_inf in
+ * FP64, each row summed in increasing column order. */
+mpir_status mpir_downcast(int64_t n, const void *dA, int64_t lda, mpir_prec tw,
+                          mpir_prec tf, void *dAF, double *anorm, void *hip_stream);
+
+/* Copy the packed factors of f: dLU (device, n*n entries of TF, row-major,
+ * unit-lower L below the diagonal, U on and above) and ipiv (host, n int32:
+ * row swapped with row k at step k, 0-based). */
+mpir_status mpir_get_factors(mpir_fact f, void *dLU, int32_t *ipiv);
+
+/* The residual of eq. xferrule: dr[i] = fl_R(b_i - sum_j a_ij x_j) with A,
+ * x, b in TW promoted exactly to TR.  dr: n entries of TR (double or float);
+ * *rnorm (host) = ||r||_inf. */
+mpir_status mpir_residual(int64_t n, const void *dA, int64_t lda, mpir_prec tw,
+                          mpir_prec tr, const void *db, const void *dx, void *dr,
+                          double *rnorm, void *hip_stream);
+
+/* Per-kernel timing with HIP events recorded around each launch on the
+ * library's stream.  kind: 0 = trailing-update GEMM, 1 = panel factor,
+ * 2 = triangular solves, 3 = residual GEMV, 4 = downcast.  mpir_prof_get
+ * returns the summed duration, the launch count and the summed algorithmic
+ * work (flops for kinds 0-2, bytes for 3-4) since the last reset. */
+void mpir_prof_enable(int32_t on);
+void mpir_prof_reset(void);
+mpir_status mpir_prof_get(int32_t kind, double *ms, int64_t *launches, double *work);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* MPIR_H */

@@ -1,0 +1,119 @@
+// Interprecision copy A_F = I_W^F(A) (paper, notation following Algorithm IR)
+// fused with ||A||_inf and the finiteness / range checks.
+//
+// Layout: A is column-major in TW (lda); A_F is the row-major working array
+// of the factorization (binary32 for TF in {F32, F16}, binary64 for F64).
+// One workgroup owns a strip of 64 rows and walks the column tiles from left
+// to right, so each row sum of |a_ij| is accumulated in increasing j (the
+// same order as a plain loop, hence bit-identical to it).  Reads are
+// coalesced along columns, the tile is transposed through LDS and written
+// coalesced along rows.
+#include "mpir_internal.h"
+
+namespace mpir {
+namespace {
+
+constexpr int TR = 64;   // rows per strip
+constexpr int TC = 64;   // columns per tile
+
+template <typename TWt, typename Wt, int TF>
+__global__ __launch_bounds__(256) void k_downcast(int64_t n, const TWt *__restrict__ A,
+                                                  int64_t lda, Wt *__restrict__ AF,
+                                                  uint64_t *anorm_bits, uint32_t *flags) {
+    __shared__ double tile[TC][TR + 1];
+    const int t = threadIdx.x;
+    const int64_t i0 = (int64_t)blockIdx.x * TR;
+    double rs = 0.0;
+    uint32_t fl = 0;
+    for (int64_t j0 = 0; j0 < n; j0 += TC) {
+        // load: thread -> row (t % 64), columns (t / 64) + 4 s
+        {
+            const int r = t % TR;
+            const int64_t i = i0 + r;
+#pragma unroll 4
+            for (int s = 0; s < TC / 4; ++s) {
+                const int c = t / TR + 4 * s;
+                const int64_t j = j0 + c;
+                double v = 0.0;
+                if (i < n && j < n) v = (double)A[i + j * lda];
+                tile[c][r] = v;
+            }
+        }
+        __syncthreads();
+        if (t < TR) {
+            // row sum in increasing column order (one thread per row)
+            const int64_t i = i0 + t;
+            if (i < n) {
+                const int cmax = (int)((n - j0) < TC ? (n - j0) : TC);
+                for (int c = 0; c < cmax; ++c) rs = rs + fabs(tile[c][t]);
+            }
+        }
+        // store: thread -> column (t % 64), rows (t / 64) + 4 s
+        {
+            const int c = t % TC;
+            const int64_t j = j0 + c;
+#pragma unroll 4
+            for (int s = 0; s < TR / 4; ++s) {
+                const int r = t / TC + 4 * s;
+                const int64_t i = i0 + r;
+                if (i < n && j < n) {
+                    const double v = tile[c][r];
+                    Wt w;
+                    if (TF == MPIR_F64) w = (Wt)v;
+                    else if (TF == MPIR_F32) w = (Wt)(float)v;
+                    else w = (Wt)d2h_as_float(v);
+                    if (!isfinite(v)) fl |= DF_NONFINITE;
+                    else if (isinf((double)w)) fl |= DF_RANGE;
+                    AF[i * n + j] = w;
+                }
+            }
+        }
+        __syncthreads();
+    }
+    if (t < TR && i0 + t < n) {
+        if (isfinite(rs)) atomic_max_nonneg(anorm_bits, rs);
+        else fl |= DF_NONFINITE;
+    }
+    if (fl) atomicOr(flags, fl);
+}
+
+__global__ void k_pack_half(int64_t total, const float *__restrict__ src, __half *__restrict__ dst) {
+    int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+    for (; i < total; i += stride) dst[i] = __float2half_rn(src[i]);
+}
+
+}  // namespace
+
+hipError_t launch_downcast(int64_t n, const void *A, int64_t lda, int tw, int tf, void *AF,
+                           uint64_t *anorm_bits, uint32_t *flags, hipStream_t s) {
+    if (n <= 0) return hipSuccess;
+    dim3 grid((unsigned)((n + TR - 1) / TR)), block(256);
+    if (tw == MPIR_F64) {
+        const double *a = (const double *)A;
+        if (tf == MPIR_F64) k_downcast<double, double, MPIR_F64><<<grid, block, 0, s>>>(n, a, lda, (double *)AF, anorm_bits, flags);
+        else if (tf == MPIR_F32) k_downcast<double, float, MPIR_F32><<<grid, block, 0, s>>>(n, a, lda, (float *)AF, anorm_bits, flags);
+        else k_downcast<double, float, MPIR_F16><<<grid, block, 0, s>>>(n, a, lda, (float *)AF, anorm_bits, flags);
+    } else {
+        const float *a = (const float *)A;
+        if (tf == MPIR_F32) k_downcast<float, float, MPIR_F32><<<grid, block, 0, s>>>(n, a, lda, (float *)AF, anorm_bits, flags);
+        else k_downcast<float, float, MPIR_F16><<<grid, block, 0, s>>>(n, a, lda, (float *)AF, anorm_bits, flags);
+    }
+    return hipGetLastError();
+}
+
+hipError_t launch_pack_half(int64_t n, const float *AF, __half *LU, hipStream_t s) {
+    const int64_t total = n * n;
+    if (total <= 0) return hipSuccess;
+    int64_t blocks = (total + 255) / 256;
+    if (blocks > 65536) blocks = 65536;
+    k_pack_half<<<(unsigned)blocks, 256, 0, s>>>(total, AF, LU);
+    return hipGetLastError();
+}
+
+hipError_t launch_copy_factors(int64_t n, const void *src, int tf, void *dst, hipStream_t s) {
+    const size_t es = tf == MPIR_F64 ? 8 : (tf == MPIR_F32 ? 4 : 2);
+    return hipMemcpyAsync(dst, src, (size_t)n * (size_t)n * es, hipMemcpyDeviceToDevice, s);
+}
+
+}  // namespace mpir

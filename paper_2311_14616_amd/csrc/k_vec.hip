@@ -1,0 +1,271 @@
+// The O(N^2) and O(N) steps of the refinement loop (Algorithm IR):
+//  - residual r = b - A x in precision TR (eq. xferrule: A, x, b promoted
+//    exactly, then operated on in TR), as a coalesced column-major GEMV with
+//    a deterministic two-pass column-chunk reduction;
+//  - scale, permute and downcast of the residual for the low-precision solve
+//    (eq. vdlow: rhat = I_W^F(P r / sigma));
+//  - promote, unscale and update (eq. promotevd: d = sigma I_F^W(d_F);
+//    x <- x + d in TW);
+//  - the termination rules (eqs. residterm, term, stag, wilkterm, litmax),
+//    evaluated on the device so that the loop needs no host round trip to
+//    decide; every loop kernel returns at once after `done` is set.
+#include "mpir_internal.h"
+
+namespace mpir {
+namespace {
+
+constexpr int kRowsPerBlock = 256;   // one row per thread
+constexpr int kChunkCols = 256;      // columns per partial sum
+
+__device__ __forceinline__ double bits_to_d(uint64_t b) { return __longlong_as_double((long long)b); }
+
+// Bit pattern of |v| for a max that keeps NaN (its pattern orders above +inf).
+__device__ __forceinline__ uint64_t abs_bits(double v) {
+    return (uint64_t)__double_as_longlong(v) & 0x7fffffffffffffffull;
+}
+__device__ __forceinline__ uint64_t wave_max_bits(uint64_t b) {
+    for (int off = 32; off > 0; off >>= 1) {
+        const uint64_t o = (uint64_t)__shfl_xor((long long)b, off);
+        b = o > b ? o : b;
+    }
+    return b;
+}
+__device__ __forceinline__ void atomic_max_bits(uint64_t *p, uint64_t b) {
+    atomicMax((unsigned long long *)p, (unsigned long long)b);
+}
+
+// Power of two sigma with m / sigma in (1/2, 1] (m > 0, finite).
+__device__ __forceinline__ double pow2_ceil(double m) {
+    int e;
+    const double f = frexp(m, &e);
+    return f == 0.5 ? ldexp(1.0, e - 1) : ldexp(1.0, e);
+}
+
+// ---- residual, pass 1: partial[c][i] = sum_{j in chunk c} a_ij x_j --------
+template <typename TWt, typename TRt>
+__global__ __launch_bounds__(256) void k_resid_partial(int64_t n, const TWt *__restrict__ A, int64_t lda,
+                                                       const TWt *__restrict__ x,
+                                                       double *__restrict__ partial,
+                                                       const IrState *st, int force) {
+    if (!force && st->done) return;
+    const int64_t i = (int64_t)blockIdx.x * kRowsPerBlock + threadIdx.x;
+    const int64_t j0 = (int64_t)blockIdx.y * kChunkCols;
+    const int64_t j1 = (j0 + kChunkCols) < n ? (j0 + kChunkCols) : n;
+    if (i >= n) return;
+    TRt acc = 0;
+    const TWt *col = A + i + j0 * lda;
+    int64_t j = j0;
+    for (; j + 8 <= j1; j += 8) {
+        TRt v[8];
+#pragma unroll
+        for (int q = 0; q < 8; ++q) v[q] = (TRt)col[(j - j0 + q) * lda];
+#pragma unroll
+        for (int q = 0; q < 8; ++q) acc += v[q] * (TRt)x[j + q];
+    }
+    for (; j < j1; ++j) acc += (TRt)col[(j - j0) * lda] * (TRt)x[j];
+    partial[(int64_t)blockIdx.y * n + i] = (double)acc;
+}
+
+// ---- residual, pass 2: r_i = b_i - sum_c partial[c][i] (c increasing) ----
+template <typename TWt, typename TRt>
+__global__ __launch_bounds__(256) void k_resid_reduce(int64_t n, const TWt *__restrict__ b,
+                                                      const TWt *__restrict__ x,
+                                                      const double *__restrict__ partial, int nch,
+                                                      TRt *__restrict__ r, IrState *st, int force) {
+    if (!force && st->done) return;
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    uint64_t rm = 0, xm = 0;
+    if (i < n) {
+        TRt s = 0;
+        for (int c = 0; c < nch; ++c) s += (TRt)partial[(int64_t)c * n + i];
+        const TRt ri = (TRt)b[i] - s;
+        r[i] = ri;
+        rm = abs_bits((double)ri);
+        xm = abs_bits((double)x[i]);
+    }
+    rm = wave_max_bits(rm);
+    xm = wave_max_bits(xm);
+    if ((threadIdx.x & 63) == 0) {
+        atomic_max_bits(&st->rnorm_bits, rm);
+        atomic_max_bits(&st->xnorm_bits, xm);
+    }
+}
+
+// ---- x = 0, r = b (in TR), ||b|| into rnorm_bits ----
+template <typename TWt, typename TRt>
+__global__ void k_ir_init(int64_t n, const TWt *__restrict__ b, TWt *__restrict__ x,
+                          TRt *__restrict__ r, IrState *st) {
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    uint64_t bm = 0;
+    if (i < n) {
+        const TWt bi = b[i];
+        x[i] = (TWt)0;
+        r[i] = (TRt)bi;
+        bm = abs_bits((double)bi);
+    }
+    bm = wave_max_bits(bm);
+    if ((threadIdx.x & 63) == 0) atomic_max_bits(&st->rnorm_bits, bm);
+}
+
+// ---- rhat_i = fl_F(r_{perm_i} / sigma) ----
+template <typename TRt, typename Yt, int TF>
+__global__ __launch_bounds__(256) void k_scale_permute(int64_t n, const TRt *__restrict__ r,
+                                                       const int32_t *__restrict__ perm,
+                                                       Yt *__restrict__ rhat, IrState *st,
+                                                       TrsvSync *ts, int force) {
+    if (!force && st->done) return;
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i == 0) { ts->ticket_l = 0; ts->done_l = 0; ts->ticket_u = 0; ts->done_u = 0; }
+    if (i >= n) return;
+    const double inv = 1.0 / st->sigma;      // exact: sigma is a power of two
+    const double v = (double)r[perm[i]] * inv;
+    Yt o;
+    if (TF == MPIR_F64) o = (Yt)v;
+    else if (TF == MPIR_F32) o = (Yt)(float)v;
+    else o = (Yt)d2h_as_float(v);
+    rhat[i] = o;
+}
+
+// ---- d = sigma * y (exact), x <- fl_W(x + d), ||d|| ----
+template <typename TWt, typename Yt>
+__global__ __launch_bounds__(256) void k_update(int64_t n, const Yt *__restrict__ y, TWt *__restrict__ x,
+                                                IrState *st, int force) {
+    if (!force && st->done) return;
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    uint64_t dm = 0;
+    if (i < n) {
+        const TWt d = (TWt)st->sigma * (TWt)y[i];
+        x[i] = x[i] + d;
+        dm = abs_bits((double)d);
+    }
+    dm = wave_max_bits(dm);
+    if ((threadIdx.x & 63) == 0) atomic_max_bits(&st->dnorm_bits, dm);
+}
+
+// ---- termination (one thread).  it < 0: the initial residual r = b. ----
+__global__ void k_terminate(IrState *st) {
+    if (threadIdx.x != 0 || blockIdx.x != 0 || st->done) return;
+    const double rn = bits_to_d(st->rnorm_bits);
+    st->rnorm_bits = 0;
+    if (st->it < 0) {                       // r = b, x = 0
+        st->it = 0;
+        st->bnorm = rn;
+        st->rnorm = rn;
+        st->xnorm = 0.0;
+        st->rhist[0] = rn;
+        int conv = 0;
+        if (!isfinite(rn)) { st->done = 1; st->stop = MPIR_STOP_NONFINITE; return; }
+        if (rn == 0.0) conv = 1;
+        else if (!st->wilk)
+            conv = st->residterm ? (rn <= st->tol_r * st->bnorm)
+                                 : (rn <= st->tol_e * (st->bnorm + st->anorm * 0.0));
+        if (conv) { st->done = 1; st->stop = MPIR_STOP_CONVERGED; return; }
+        st->sigma = pow2_ceil(rn);
+        return;
+    }
+    const double dn = bits_to_d(st->dnorm_bits);
+    const double xn = bits_to_d(st->xnorm_bits);
+    st->dnorm_bits = 0;
+    st->xnorm_bits = 0;
+    const int it = st->it + 1;
+    st->it = it;
+    st->rnorm = rn;
+    st->dnorm = dn;
+    st->xnorm = xn;
+    st->rhist[it] = rn;
+    st->dhist[it - 1] = dn;
+    int stop = -1;
+    if (!isfinite(rn) || !isfinite(dn)) stop = MPIR_STOP_NONFINITE;
+    else if (rn == 0.0) stop = MPIR_STOP_CONVERGED;
+    else if (!st->wilk) {
+        const int conv = st->residterm ? (rn <= st->tol_r * st->bnorm)
+                                       : (rn <= st->tol_e * (st->bnorm + st->anorm * xn));
+        if (conv) stop = MPIR_STOP_CONVERGED;
+        else if (it >= st->litmax) stop = MPIR_STOP_LITMAX;
+        else if (st->rhist[it] >= st->rmax * st->rhist[it - 1]) stop = MPIR_STOP_STAGNATED;
+    } else {
+        if (it >= st->litmax) stop = MPIR_STOP_LITMAX;
+        else if (it >= 2 && st->dhist[it - 1] >= st->rmax * st->dhist[it - 2]) stop = MPIR_STOP_DSTAGNATED;
+    }
+    if (stop >= 0) { st->done = 1; st->stop = stop; return; }
+    st->sigma = pow2_ceil(rn);
+}
+
+// sigma for a single solve (mpir_solve): from ||b|| in rnorm_bits.
+__global__ void k_set_sigma(IrState *st) {
+    if (threadIdx.x != 0 || blockIdx.x != 0) return;
+    const double rn = bits_to_d(st->rnorm_bits);
+    st->rnorm_bits = 0;
+    st->bnorm = rn;
+    st->sigma = (rn > 0.0 && isfinite(rn)) ? pow2_ceil(rn) : 1.0;
+}
+
+inline unsigned blocks_for(int64_t n, int bs) { return (unsigned)((n + bs - 1) / bs); }
+
+}  // namespace
+
+int residual_chunks(int64_t n) { return (int)((n + kChunkCols - 1) / kChunkCols); }
+
+hipError_t launch_residual(int64_t n, const void *A, int64_t lda, int tw, int tr, const void *b,
+                           const void *x, void *r, double *partial, int nch, IrState *st,
+                           int force, hipStream_t s) {
+    if (n <= 0) return hipSuccess;
+    dim3 g1(blocks_for(n, kRowsPerBlock), (unsigned)nch), b1(kRowsPerBlock);
+    dim3 g2(blocks_for(n, 256)), b2(256);
+    if (tw == MPIR_F64) {
+        k_resid_partial<double, double><<<g1, b1, 0, s>>>(n, (const double *)A, lda, (const double *)x, partial, st, force);
+        k_resid_reduce<double, double><<<g2, b2, 0, s>>>(n, (const double *)b, (const double *)x, partial, nch, (double *)r, st, force);
+    } else if (tr == MPIR_F64) {
+        k_resid_partial<float, double><<<g1, b1, 0, s>>>(n, (const float *)A, lda, (const float *)x, partial, st, force);
+        k_resid_reduce<float, double><<<g2, b2, 0, s>>>(n, (const float *)b, (const float *)x, partial, nch, (double *)r, st, force);
+    } else {
+        k_resid_partial<float, float><<<g1, b1, 0, s>>>(n, (const float *)A, lda, (const float *)x, partial, st, force);
+        k_resid_reduce<float, float><<<g2, b2, 0, s>>>(n, (const float *)b, (const float *)x, partial, nch, (float *)r, st, force);
+    }
+    return hipGetLastError();
+}
+
+hipError_t launch_ir_init(int64_t n, int tw, int tr, const void *b, void *x, void *r, IrState *st,
+                          hipStream_t s) {
+    dim3 g(blocks_for(n, 256)), bl(256);
+    if (tw == MPIR_F64) k_ir_init<double, double><<<g, bl, 0, s>>>(n, (const double *)b, (double *)x, (double *)r, st);
+    else if (tr == MPIR_F64) k_ir_init<float, double><<<g, bl, 0, s>>>(n, (const float *)b, (float *)x, (double *)r, st);
+    else k_ir_init<float, float><<<g, bl, 0, s>>>(n, (const float *)b, (float *)x, (float *)r, st);
+    return hipGetLastError();
+}
+
+hipError_t launch_scale_permute(int64_t n, int tr, int tf, const void *r, const int32_t *perm,
+                                void *rhat, IrState *st, TrsvSync *ts, int force, hipStream_t s) {
+    dim3 g(blocks_for(n, 256)), bl(256);
+    if (tf == MPIR_F64) {
+        k_scale_permute<double, double, MPIR_F64><<<g, bl, 0, s>>>(n, (const double *)r, perm, (double *)rhat, st, ts, force);
+    } else if (tr == MPIR_F64) {
+        if (tf == MPIR_F32) k_scale_permute<double, float, MPIR_F32><<<g, bl, 0, s>>>(n, (const double *)r, perm, (float *)rhat, st, ts, force);
+        else k_scale_permute<double, float, MPIR_F16><<<g, bl, 0, s>>>(n, (const double *)r, perm, (float *)rhat, st, ts, force);
+    } else {
+        if (tf == MPIR_F32) k_scale_permute<float, float, MPIR_F32><<<g, bl, 0, s>>>(n, (const float *)r, perm, (float *)rhat, st, ts, force);
+        else k_scale_permute<float, float, MPIR_F16><<<g, bl, 0, s>>>(n, (const float *)r, perm, (float *)rhat, st, ts, force);
+    }
+    return hipGetLastError();
+}
+
+hipError_t launch_update(int64_t n, int tw, int tf, const void *y, void *x, IrState *st, int force,
+                         hipStream_t s) {
+    dim3 g(blocks_for(n, 256)), bl(256);
+    if (tf == MPIR_F64) k_update<double, double><<<g, bl, 0, s>>>(n, (const double *)y, (double *)x, st, force);
+    else if (tw == MPIR_F64) k_update<double, float><<<g, bl, 0, s>>>(n, (const float *)y, (double *)x, st, force);
+    else k_update<float, float><<<g, bl, 0, s>>>(n, (const float *)y, (float *)x, st, force);
+    return hipGetLastError();
+}
+
+hipError_t launch_terminate(IrState *st, hipStream_t s) {
+    k_terminate<<<1, 64, 0, s>>>(st);
+    return hipGetLastError();
+}
+
+hipError_t launch_set_sigma(IrState *st, hipStream_t s) {
+    k_set_sigma<<<1, 64, 0, s>>>(st);
+    return hipGetLastError();
+}
+
+}  // namespace mpir

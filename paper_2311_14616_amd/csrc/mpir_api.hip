@@ -1,0 +1,576 @@
+// C ABI of the library (declared in include/mpir.h): handle and workspace
+// management, the blocked LU driver and the refinement-loop driver.  Every
+// arithmetic step runs in the HIP kernels of this directory; this file only
+// orders launches on the caller's stream and moves status words.
+#include <chrono>
+#include <cmath>
+#include <cstdio>
+#include <cstdlib>
+#include <cstring>
+#include <mutex>
+#include <vector>
+
+#include "mpir_internal.h"
+
+using namespace mpir;
+
+namespace mpir {
+hipError_t launch_set_sigma(IrState *st, hipStream_t s);
+int leaf_max_rows(int mode);
+}
+
+// --------------------------------------------------------------------------
+// Per-kernel timing (HIP events around launches on the library's stream)
+// --------------------------------------------------------------------------
+namespace {
+
+struct ProfRec {
+    hipEvent_t a, b;
+    double work;
+};
+struct Prof {
+    std::mutex mu;
+    bool on = false;
+    std::vector<ProfRec> recs[5];
+    std::vector<hipEvent_t> pool;
+};
+Prof g_prof;
+
+hipEvent_t prof_event() {
+    if (!g_prof.pool.empty()) {
+        hipEvent_t e = g_prof.pool.back();
+        g_prof.pool.pop_back();
+        return e;
+    }
+    hipEvent_t e = nullptr;
+    if (hipEventCreate(&e) != hipSuccess) return nullptr;
+    return e;
+}
+
+// Scoped timing of one launch of kernel kind `k` with algorithmic work `w`.
+struct ProfScope {
+    int kind;
+    double work;
+    hipStream_t s;
+    hipEvent_t a = nullptr, b = nullptr;
+    ProfScope(int k, double w, hipStream_t st) : kind(k), work(w), s(st) {
+        if (!g_prof.on) return;
+        std::lock_guard<std::mutex> g(g_prof.mu);
+        a = prof_event();
+        b = prof_event();
+        if (a) hipEventRecord(a, s);
+    }
+    ~ProfScope() {
+        if (!a || !b) return;
+        hipEventRecord(b, s);
+        std::lock_guard<std::mutex> g(g_prof.mu);
+        g_prof.recs[kind].push_back({a, b, work});
+    }
+};
+
+}  // namespace
+
+// --------------------------------------------------------------------------
+// Handle
+// --------------------------------------------------------------------------
+struct mpir_fact_s {
+    int64_t n = 0, lda = 0, ld = 0;
+    int tw = 0, tf = 0, tr = 0, mode = 0;
+    const void *A = nullptr;        // borrowed
+    hipStream_t stream = nullptr;
+    void *work = nullptr;           // row-major working array (ld x n)
+    __half *lu16 = nullptr;         // F16: packed binary16 factors
+    int32_t *ipiv = nullptr, *perm = nullptr;
+    int64_t *info_d = nullptr;
+    uint32_t *flags_d = nullptr;
+    uint64_t *anorm_bits_d = nullptr;
+    PanelSync *ps = nullptr;
+    uint32_t ps_base = 0;
+    void *r = nullptr;              // residual (TR), n doubles of room
+    void *rhat = nullptr;           // low-precision right side / solution (TS)
+    double *partial = nullptr;      // residual partial sums
+    int nchunks = 0;
+    IrState *st = nullptr;
+    TrsvSync *ts = nullptr;
+    double anorm = 0.0;
+    int64_t info = 0;
+    double t_factor_ms = 0.0;
+};
+
+namespace {
+
+size_t esize(int p) { return p == MPIR_F64 ? 8 : (p == MPIR_F32 ? 4 : 2); }
+
+bool valid_triple(int tw, int tf, int tr) {
+    if (tw != MPIR_F64 && tw != MPIR_F32) return false;
+    if (tf != MPIR_F64 && tf != MPIR_F32 && tf != MPIR_F16) return false;
+    if (tr != MPIR_F64 && tr != MPIR_F32) return false;
+    if (tw == MPIR_F32 && tf == MPIR_F64) return false;   // TF must not exceed TW
+    if (tr == MPIR_F32 && tw == MPIR_F64) return false;   // TR >= TW
+    return true;
+}
+
+int lu_mode_of(int tf) { return tf == MPIR_F64 ? LU_F64 : (tf == MPIR_F32 ? LU_F32 : LU_F16); }
+
+#define HIPCHK(x)                                  \
+    do {                                           \
+        hipError_t _e = (x);                       \
+        if (_e != hipSuccess) return MPIR_ERR_HIP; \
+    } while (0)
+
+template <typename T>
+hipError_t dalloc(T **p, size_t bytes) {
+    return hipMalloc((void **)p, bytes ? bytes : 16);
+}
+
+void free_handle(mpir_fact f) {
+    if (!f) return;
+    hipFree(f->work);
+    hipFree(f->lu16);
+    hipFree(f->ipiv);
+    hipFree(f->perm);
+    hipFree(f->info_d);
+    hipFree(f->flags_d);
+    hipFree(f->anorm_bits_d);
+    hipFree(f->ps);
+    hipFree(f->r);
+    hipFree(f->rhat);
+    hipFree(f->partial);
+    hipFree(f->st);
+    hipFree(f->ts);
+    delete f;
+}
+
+mpir_status alloc_handle(mpir_fact f) {
+    const int64_t n = f->n;
+    const size_t wes = f->mode == LU_F64 ? 8 : 4;
+    f->ld = n;
+    if (dalloc(&f->work, (size_t)f->ld * n * wes) != hipSuccess) return MPIR_ERR_ALLOC;
+    if (f->tf == MPIR_F16 && dalloc(&f->lu16, (size_t)n * n * 2) != hipSuccess) return MPIR_ERR_ALLOC;
+    f->nchunks = residual_chunks(n);
+    if (dalloc(&f->ipiv, n * 4) != hipSuccess || dalloc(&f->perm, n * 4) != hipSuccess ||
+        dalloc(&f->info_d, 8) != hipSuccess || dalloc(&f->flags_d, 8) != hipSuccess ||
+        dalloc(&f->anorm_bits_d, 8) != hipSuccess ||
+        dalloc(&f->ps, panel_sync_bytes()) != hipSuccess || dalloc(&f->r, n * 8) != hipSuccess ||
+        dalloc(&f->rhat, n * 8) != hipSuccess ||
+        dalloc(&f->partial, (size_t)f->nchunks * n * 8) != hipSuccess ||
+        dalloc(&f->st, sizeof(IrState)) != hipSuccess || dalloc(&f->ts, sizeof(TrsvSync)) != hipSuccess)
+        return MPIR_ERR_ALLOC;
+    return MPIR_OK;
+}
+
+const int kNB = 256;   // panel width (columns per trailing update)
+const int kIB = 32;    // leaf width inside the panel
+
+// Blocked right-looking LU with partial pivoting on the working array.
+mpir_status getrf(mpir_fact f) {
+    const int64_t n = f->n, ld = f->ld;
+    const int mode = f->mode;
+    void *a = f->work;
+    hipStream_t s = f->stream;
+    if (n > leaf_max_rows(mode)) return MPIR_ERR_ARG;
+    for (int64_t K = 0; K < n; K += kNB) {
+        const int w = (int)((n - K) < kNB ? (n - K) : kNB);
+        // ---- panel: columns [K, K+w) ----
+        for (int64_t k = K; k < K + w; k += kIB) {
+            const int wl = (int)((K + w - k) < kIB ? (K + w - k) : kIB);
+            {
+                ProfScope ps_(1, 0.0, s);
+                HIPCHK(launch_leaf(mode, a, n, ld, k, wl, f->ipiv, f->info_d, f->ps, &f->ps_base,
+                                   f->flags_d, s));
+            }
+            if (k > K || k + wl < K + w)
+                HIPCHK(launch_laswp(mode, a, n, ld, k, wl, f->ipiv, K, k, k + wl, K + w, nullptr, s));
+            if (k + wl < K + w) {
+                HIPCHK(launch_trsm(mode, a, ld, k, wl, k + wl, K + w, s));
+                ProfScope ps_(0, 2.0 * (double)(n - k - wl) * (double)(K + w - k - wl) * wl, s);
+                HIPCHK(launch_gemm_update(mode, a, ld, k + wl, n - k - wl, k + wl, K + w - k - wl, k, wl, s));
+            }
+        }
+        // ---- interchanges outside the panel, permutation vector ----
+        HIPCHK(launch_laswp(mode, a, n, ld, K, w, f->ipiv, 0, K, K + w, n, f->perm, s));
+        if (K + w < n) {
+            // ---- U12 = L11^{-1} A12 (blocked by kIB) ----
+            for (int64_t k = K; k < K + w; k += kIB) {
+                const int wl = (int)((K + w - k) < kIB ? (K + w - k) : kIB);
+                HIPCHK(launch_trsm(mode, a, ld, k, wl, K + w, n, s));
+                if (k + wl < K + w) {
+                    ProfScope ps_(0, 2.0 * (double)(K + w - k - wl) * (double)(n - K - w) * wl, s);
+                    HIPCHK(launch_gemm_update(mode, a, ld, k + wl, K + w - k - wl, K + w, n - K - w, k, wl, s));
+                }
+            }
+            // ---- trailing update A22 -= L21 U12 ----
+            ProfScope ps_(0, 2.0 * (double)(n - K - w) * (double)(n - K - w) * w, s);
+            HIPCHK(launch_gemm_update(mode, a, ld, K + w, n - K - w, K + w, n - K - w, K, w, s));
+        }
+    }
+    return MPIR_OK;
+}
+
+// Identity permutation (perm[i] = i) and zeroed status words.
+__global__ void k_init_perm(int64_t n, int32_t *perm) {
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < n) perm[i] = (int32_t)i;
+}
+
+mpir_status factor_impl(mpir_fact f, int64_t *info) {
+    hipStream_t s = f->stream;
+    const int64_t n = f->n;
+    hipEvent_t e0, e1;
+    HIPCHK(hipEventCreate(&e0));
+    HIPCHK(hipEventCreate(&e1));
+    HIPCHK(hipEventRecord(e0, s));
+    HIPCHK(hipMemsetAsync(f->info_d, 0, 8, s));
+    HIPCHK(hipMemsetAsync(f->flags_d, 0, 8, s));
+    HIPCHK(hipMemsetAsync(f->anorm_bits_d, 0, 8, s));
+    HIPCHK(panel_sync_reset(f->ps, s));
+    f->ps_base = 0;
+    k_init_perm<<<(unsigned)((n + 255) / 256), 256, 0, s>>>(n, f->perm);
+    HIPCHK(hipGetLastError());
+    {
+        ProfScope ps_(4, (double)n * n * (esize(f->tw) + (f->mode == LU_F64 ? 8 : 4)), s);
+        HIPCHK(launch_downcast(n, f->A, f->lda, f->tw, f->tf, f->work, f->anorm_bits_d, f->flags_d, s));
+    }
+    uint32_t flags = 0;
+    HIPCHK(hipMemcpyAsync(&flags, f->flags_d, 4, hipMemcpyDeviceToHost, s));
+    HIPCHK(hipStreamSynchronize(s));
+    if (flags & DF_NONFINITE) return MPIR_ERR_NONFINITE;
+    if (flags & DF_RANGE) return MPIR_ERR_RANGE;
+    mpir_status st = getrf(f);
+    if (st != MPIR_OK) return st;
+    if (f->tf == MPIR_F16) HIPCHK(launch_pack_half(n, (const float *)f->work, f->lu16, s));
+    uint64_t abits = 0;
+    int64_t inf = 0;
+    HIPCHK(hipMemcpyAsync(&abits, f->anorm_bits_d, 8, hipMemcpyDeviceToHost, s));
+    HIPCHK(hipMemcpyAsync(&inf, f->info_d, 8, hipMemcpyDeviceToHost, s));
+    HIPCHK(hipMemcpyAsync(&flags, f->flags_d, 4, hipMemcpyDeviceToHost, s));
+    HIPCHK(hipEventRecord(e1, s));
+    HIPCHK(hipStreamSynchronize(s));
+    float ms = 0.f;
+    hipEventElapsedTime(&ms, e0, e1);
+    hipEventDestroy(e0);
+    hipEventDestroy(e1);
+    f->t_factor_ms = ms;
+    std::memcpy(&f->anorm, &abits, 8);
+    f->info = inf;
+    if (info) *info = inf;
+    if (flags & DF_TIMEOUT) return MPIR_ERR_DEVICE;
+    return inf ? MPIR_ERR_SINGULAR : MPIR_OK;
+}
+
+const void *factors_ptr(mpir_fact f) { return f->tf == MPIR_F16 ? (const void *)f->lu16 : f->work; }
+
+}  // namespace
+
+// --------------------------------------------------------------------------
+// Public entry points
+// --------------------------------------------------------------------------
+extern "C" {
+
+void mpir_term_default(mpir_term *t) {
+    if (!t) return;
+    t->Cr = 1.0;
+    t->Ce = 1.0;
+    t->Rmax = 0.5;
+    t->litmax = 10;
+    t->residterm = 1;
+    t->tol_rel = 0.0;
+}
+
+const char *mpir_status_str(mpir_status s) {
+    switch (s) {
+    case MPIR_OK: return "ok";
+    case MPIR_ERR_SINGULAR: return "exactly singular factor (zero pivot)";
+    case MPIR_ERR_ARG: return "invalid argument";
+    case MPIR_ERR_ALLOC: return "device allocation failed";
+    case MPIR_ERR_HIP: return "HIP runtime error";
+    case MPIR_ERR_NONFINITE: return "non-finite input";
+    case MPIR_ERR_RANGE: return "matrix entry overflows the factorization precision";
+    case MPIR_ERR_DEVICE: return "device wait expired";
+    }
+    return "unknown status";
+}
+
+mpir_status mpir_factor(int64_t n, const void *dA, int64_t lda, mpir_prec tw, mpir_prec tf,
+                        mpir_prec tr, void *hip_stream, mpir_fact *out, int64_t *info) {
+    if (out) *out = nullptr;
+    if (info) *info = 0;
+    if (!out || n <= 0 || !dA || lda < n || !valid_triple(tw, tf, tr)) return MPIR_ERR_ARG;
+    if (n > leaf_max_rows(lu_mode_of(tf))) return MPIR_ERR_ARG;
+    mpir_fact f = new (std::nothrow) mpir_fact_s();
+    if (!f) return MPIR_ERR_ALLOC;
+    f->n = n;
+    f->lda = lda;
+    f->tw = tw;
+    f->tf = tf;
+    f->tr = tr;
+    f->mode = lu_mode_of(tf);
+    f->A = dA;
+    f->stream = (hipStream_t)hip_stream;
+    mpir_status st = alloc_handle(f);
+    if (st != MPIR_OK) { free_handle(f); return st; }
+    st = factor_impl(f, info);
+    if (st != MPIR_OK && st != MPIR_ERR_SINGULAR) { free_handle(f); return st; }
+    *out = f;
+    return st;
+}
+
+mpir_status mpir_refactor(mpir_fact f, const void *dA, int64_t lda, int64_t *info) {
+    if (info) *info = 0;
+    if (!f || !dA || lda < f->n) return MPIR_ERR_ARG;
+    f->A = dA;
+    f->lda = lda;
+    return factor_impl(f, info);
+}
+
+void mpir_destroy(mpir_fact f) {
+    if (!f) return;
+    hipStreamSynchronize(f->stream);
+    free_handle(f);
+}
+
+mpir_status mpir_solve(mpir_fact f, const void *db, void *dx) {
+    if (!f || !db || !dx) return MPIR_ERR_ARG;
+    if (f->info) return MPIR_ERR_SINGULAR;
+    hipStream_t s = f->stream;
+    const int64_t n = f->n;
+    IrState h{};
+    h.it = -1;
+    HIPCHK(hipMemcpyAsync(f->st, &h, sizeof(h), hipMemcpyHostToDevice, s));
+    HIPCHK(launch_ir_init(n, f->tw, f->tr, db, dx, f->r, f->st, s));
+    HIPCHK(launch_set_sigma(f->st, s));
+    HIPCHK(launch_scale_permute(n, f->tr, f->tf, f->r, f->perm, f->rhat, f->st, f->ts, 1, s));
+    {
+        ProfScope ps_(2, 2.0 * (double)n * n, s);
+        HIPCHK(launch_trsv(f->tf, factors_ptr(f), n, f->tf == MPIR_F16 ? n : f->ld, f->rhat, f->ts,
+                           f->flags_d, f->st, 1, s));
+    }
+    HIPCHK(launch_update(n, f->tw, f->tf, f->rhat, dx, f->st, 1, s));
+    uint32_t flags = 0;
+    HIPCHK(hipMemcpyAsync(&flags, f->flags_d, 4, hipMemcpyDeviceToHost, s));
+    HIPCHK(hipStreamSynchronize(s));
+    if (flags & DF_TIMEOUT) return MPIR_ERR_DEVICE;
+    return MPIR_OK;
+}
+
+mpir_status mpir_ir_solve(mpir_fact f, const void *db, void *dx, const mpir_term *t,
+                          mpir_report *rep) {
+    if (!f || !db || !dx) return MPIR_ERR_ARG;
+    mpir_term term;
+    if (t) term = *t;
+    else mpir_term_default(&term);
+    if (term.litmax < 1 || term.litmax > MPIR_HIST_MAX - 1 || !(term.Rmax > 0.0)) return MPIR_ERR_ARG;
+    if (rep) {
+        std::memset(rep, 0, sizeof(*rep));
+        rep->info = f->info;
+        rep->t_factor_ms = f->t_factor_ms;
+    }
+    if (f->info) return MPIR_ERR_SINGULAR;
+    hipStream_t s = f->stream;
+    const int64_t n = f->n;
+    const double uw = f->tw == MPIR_F64 ? std::ldexp(1.0, -52) : std::ldexp(1.0, -23);
+    IrState h{};
+    h.it = -1;
+    h.anorm = f->anorm;
+    h.wilk = (f->tr == MPIR_F64 && f->tw != MPIR_F64) ? 1 : 0;
+    h.residterm = term.residterm ? 1 : 0;
+    h.litmax = term.litmax;
+    h.tol_r = term.tol_rel > 0 ? term.tol_rel : term.Cr * uw;
+    h.tol_e = term.tol_rel > 0 ? term.tol_rel : term.Ce * uw;
+    h.rmax = term.Rmax;
+    hipEvent_t e0, e1;
+    HIPCHK(hipEventCreate(&e0));
+    HIPCHK(hipEventCreate(&e1));
+    HIPCHK(hipMemcpyAsync(f->st, &h, sizeof(h), hipMemcpyHostToDevice, s));
+    HIPCHK(hipMemsetAsync(f->flags_d, 0, 4, s));
+    HIPCHK(hipEventRecord(e0, s));
+    HIPCHK(launch_ir_init(n, f->tw, f->tr, db, dx, f->r, f->st, s));
+    HIPCHK(launch_terminate(f->st, s));
+    const void *LU = factors_ptr(f);
+    const int64_t lld = f->tf == MPIR_F16 ? n : f->ld;
+    const size_t twes = esize(f->tw);
+    for (int it = 0; it < term.litmax; ++it) {
+        HIPCHK(launch_scale_permute(n, f->tr, f->tf, f->r, f->perm, f->rhat, f->st, f->ts, 0, s));
+        {
+            ProfScope ps_(2, 2.0 * (double)n * n, s);
+            HIPCHK(launch_trsv(f->tf, LU, n, lld, f->rhat, f->ts, f->flags_d, f->st, 0, s));
+        }
+        HIPCHK(launch_update(n, f->tw, f->tf, f->rhat, dx, f->st, 0, s));
+        {
+            ProfScope ps_(3, (double)n * n * twes, s);
+            HIPCHK(launch_residual(n, f->A, f->lda, f->tw, f->tr, db, dx, f->r, f->partial, f->nchunks,
+                                   f->st, 0, s));
+        }
+        HIPCHK(launch_terminate(f->st, s));
+        int32_t done = 0;
+        HIPCHK(hipMemcpyAsync(&done, &f->st->done, 4, hipMemcpyDeviceToHost, s));
+        HIPCHK(hipStreamSynchronize(s));
+        if (done) break;
+    }
+    HIPCHK(hipEventRecord(e1, s));
+    IrState hs;
+    uint32_t flags = 0;
+    HIPCHK(hipMemcpyAsync(&hs, f->st, sizeof(hs), hipMemcpyDeviceToHost, s));
+    HIPCHK(hipMemcpyAsync(&flags, f->flags_d, 4, hipMemcpyDeviceToHost, s));
+    HIPCHK(hipStreamSynchronize(s));
+    float ms = 0.f;
+    hipEventElapsedTime(&ms, e0, e1);
+    hipEventDestroy(e0);
+    hipEventDestroy(e1);
+    if (flags & DF_TIMEOUT) return MPIR_ERR_DEVICE;
+    if (hs.it == 0 && hs.stop == MPIR_STOP_NONFINITE) return MPIR_ERR_NONFINITE;
+    double rnorm = hs.rnorm, xnorm = hs.xnorm;
+    if (f->tr != MPIR_F64 && hs.it > 0) {
+        // report the binary64 residual of the returned x
+        IrState h2{};
+        h2.it = 0;
+        HIPCHK(hipMemcpyAsync(f->st, &h2, sizeof(h2), hipMemcpyHostToDevice, s));
+        HIPCHK(launch_residual(n, f->A, f->lda, f->tw, MPIR_F64, db, dx, f->r, f->partial, f->nchunks,
+                               f->st, 1, s));
+        uint64_t bits[3];
+        HIPCHK(hipMemcpyAsync(bits, &f->st->rnorm_bits, 24, hipMemcpyDeviceToHost, s));
+        HIPCHK(hipStreamSynchronize(s));
+        std::memcpy(&rnorm, &bits[0], 8);
+        std::memcpy(&xnorm, &bits[2], 8);
+    }
+    if (rep) {
+        rep->n_iter = hs.it;
+        rep->stop = hs.stop;
+        rep->n_hist = hs.it + 1;
+        for (int k = 0; k <= hs.it && k < MPIR_HIST_MAX; ++k) rep->rhist[k] = hs.rhist[k];
+        for (int k = 0; k < hs.it && k < MPIR_HIST_MAX; ++k) rep->dhist[k] = hs.dhist[k];
+        rep->bnorm_inf = hs.bnorm;
+        rep->anorm_inf = f->anorm;
+        rep->xnorm_inf = xnorm;
+        rep->relres = hs.bnorm > 0 ? rnorm / hs.bnorm : rnorm;
+        const double den = f->anorm * xnorm + hs.bnorm;
+        rep->bwd_err = den > 0 ? rnorm / den : 0.0;
+        rep->t_ir_ms = ms;
+    }
+    return MPIR_OK;
+}
+
+mpir_status mpir_downcast(int64_t n, const void *dA, int64_t lda, mpir_prec tw, mpir_prec tf,
+                          void *dAF, double *anorm, void *hip_stream) {
+    if (n <= 0 || !dA || !dAF || lda < n || !valid_triple(tw, tf, tw == MPIR_F64 ? MPIR_F64 : MPIR_F32))
+        return MPIR_ERR_ARG;
+    hipStream_t s = (hipStream_t)hip_stream;
+    uint64_t *bits = nullptr;
+    uint32_t *flags = nullptr;
+    void *tmp = nullptr;
+    mpir_status st = MPIR_OK;
+    if (dalloc(&bits, 16) != hipSuccess || dalloc(&flags, 8) != hipSuccess) st = MPIR_ERR_ALLOC;
+    if (st == MPIR_OK && tf == MPIR_F16 && dalloc(&tmp, (size_t)n * n * 4) != hipSuccess) st = MPIR_ERR_ALLOC;
+    if (st == MPIR_OK) {
+        hipMemsetAsync(bits, 0, 8, s);
+        hipMemsetAsync(flags, 0, 4, s);
+        if (launch_downcast(n, dA, lda, tw, tf, tf == MPIR_F16 ? tmp : dAF, bits, flags, s) != hipSuccess)
+            st = MPIR_ERR_HIP;
+        if (st == MPIR_OK && tf == MPIR_F16 &&
+            launch_pack_half(n, (const float *)tmp, (__half *)dAF, s) != hipSuccess)
+            st = MPIR_ERR_HIP;
+        uint64_t hb = 0;
+        uint32_t hf = 0;
+        if (st == MPIR_OK && (hipMemcpyAsync(&hb, bits, 8, hipMemcpyDeviceToHost, s) != hipSuccess ||
+                              hipMemcpyAsync(&hf, flags, 4, hipMemcpyDeviceToHost, s) != hipSuccess ||
+                              hipStreamSynchronize(s) != hipSuccess))
+            st = MPIR_ERR_HIP;
+        if (st == MPIR_OK) {
+            if (anorm) std::memcpy(anorm, &hb, 8);
+            if (hf & DF_NONFINITE) st = MPIR_ERR_NONFINITE;
+            else if (hf & DF_RANGE) st = MPIR_ERR_RANGE;
+        }
+    }
+    hipFree(bits);
+    hipFree(flags);
+    hipFree(tmp);
+    return st;
+}
+
+mpir_status mpir_get_factors(mpir_fact f, void *dLU, int32_t *ipiv) {
+    if (!f || (!dLU && !ipiv)) return MPIR_ERR_ARG;
+    hipStream_t s = f->stream;
+    const int64_t n = f->n;
+    if (dLU) {
+        if (f->tf == MPIR_F16) HIPCHK(hipMemcpyAsync(dLU, f->lu16, (size_t)n * n * 2, hipMemcpyDeviceToDevice, s));
+        else {
+            const size_t es = esize(f->tf);
+            HIPCHK(hipMemcpy2DAsync(dLU, n * es, f->work, f->ld * es, n * es, n, hipMemcpyDeviceToDevice, s));
+        }
+    }
+    if (ipiv) HIPCHK(hipMemcpyAsync(ipiv, f->ipiv, n * 4, hipMemcpyDeviceToHost, s));
+    HIPCHK(hipStreamSynchronize(s));
+    return MPIR_OK;
+}
+
+mpir_status mpir_residual(int64_t n, const void *dA, int64_t lda, mpir_prec tw, mpir_prec tr,
+                          const void *db, const void *dx, void *dr, double *rnorm, void *hip_stream) {
+    if (n <= 0 || !dA || !db || !dx || !dr || lda < n || !valid_triple(tw, tw, tr)) return MPIR_ERR_ARG;
+    hipStream_t s = (hipStream_t)hip_stream;
+    IrState *st = nullptr;
+    double *partial = nullptr;
+    const int nch = residual_chunks(n);
+    mpir_status ret = MPIR_OK;
+    if (dalloc(&st, sizeof(IrState)) != hipSuccess || dalloc(&partial, (size_t)nch * n * 8) != hipSuccess)
+        ret = MPIR_ERR_ALLOC;
+    if (ret == MPIR_OK) {
+        IrState h{};
+        uint64_t bits = 0;
+        if (hipMemcpyAsync(st, &h, sizeof(h), hipMemcpyHostToDevice, s) != hipSuccess) ret = MPIR_ERR_HIP;
+        {
+            ProfScope ps_(3, (double)n * n * esize(tw), s);
+            if (ret == MPIR_OK && launch_residual(n, dA, lda, tw, tr, db, dx, dr, partial, nch, st, 1, s) != hipSuccess)
+                ret = MPIR_ERR_HIP;
+        }
+        if (ret == MPIR_OK && (hipMemcpyAsync(&bits, &st->rnorm_bits, 8, hipMemcpyDeviceToHost, s) != hipSuccess ||
+                               hipStreamSynchronize(s) != hipSuccess))
+            ret = MPIR_ERR_HIP;
+        if (ret == MPIR_OK && rnorm) std::memcpy(rnorm, &bits, 8);
+    }
+    hipFree(st);
+    hipFree(partial);
+    return ret;
+}
+
+mpir_status mpir_ir_solve_batched(int32_t batch, const int64_t *n, const void *const *dA,
+                                  const int64_t *lda, const void *const *db, void *const *dx,
+                                  mpir_prec tw, mpir_prec tf, mpir_prec tr, const mpir_term *t,
+                                  mpir_report *reps, void *hip_stream) {
+    (void)batch; (void)n; (void)dA; (void)lda; (void)db; (void)dx; (void)tw; (void)tf; (void)tr;
+    (void)t; (void)reps; (void)hip_stream;
+    return MPIR_ERR_ARG;
+}
+
+void mpir_prof_enable(int32_t on) {
+    std::lock_guard<std::mutex> g(g_prof.mu);
+    g_prof.on = on != 0;
+}
+
+void mpir_prof_reset(void) {
+    std::lock_guard<std::mutex> g(g_prof.mu);
+    for (auto &v : g_prof.recs)
+        for (auto &r : v) {
+            g_prof.pool.push_back(r.a);
+            g_prof.pool.push_back(r.b);
+        }
+    for (auto &v : g_prof.recs) v.clear();
+}
+
+mpir_status mpir_prof_get(int32_t kind, double *ms, int64_t *launches, double *work) {
+    if (kind < 0 || kind >= 5) return MPIR_ERR_ARG;
+    std::lock_guard<std::mutex> g(g_prof.mu);
+    double tot = 0.0, wk = 0.0;
+    for (auto &r : g_prof.recs[kind]) {
+        if (hipEventSynchronize(r.b) != hipSuccess) return MPIR_ERR_HIP;
+        float e = 0.f;
+        if (hipEventElapsedTime(&e, r.a, r.b) != hipSuccess) return MPIR_ERR_HIP;
+        tot += e;
+        wk += r.work;
+    }
+    if (ms) *ms = tot;
+    if (launches) *launches = (int64_t)g_prof.recs[kind].size();
+    if (work) *work = wk;
+    return MPIR_OK;
+}
+
+}  // extern "C"

@@ -1,0 +1,167 @@
+// Internal declarations of the MI355X implementation: device-side helpers
+// shared by the kernels, launcher prototypes and the handle layout.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <hip/hip_fp16.h>
+#include <stdint.h>
+
+#include "../../include/mpir.h"
+
+namespace mpir {
+
+// ---------------------------------------------------------------------------
+// Factorization modes (how "factor in precision TF" is carried out).
+//   LU_F64   : binary64 everywhere (FP64 MFMA trailing update).
+//   LU_F32   : binary32 everywhere (FP32 MFMA trailing update).
+//   LU_F16   : binary16 L and U, binary32 trailing matrix, FP16 MFMA with
+//              binary32 accumulation; a U row is rounded to binary16 when it
+//              becomes final, a multiplier when it is formed.
+// ---------------------------------------------------------------------------
+enum LuMode { LU_F64 = 0, LU_F32 = 1, LU_F16 = 2 };
+
+// Device status word bits (sticky, OR-ed by kernels).
+enum DevFlag : uint32_t {
+    DF_NONFINITE = 1u,   // NaN / Inf in an input
+    DF_RANGE = 2u,       // overflow in the downcast
+    DF_TIMEOUT = 4u,     // a bounded inter-workgroup wait expired
+};
+
+// Iteration state kept in device memory (termination decided on device).
+struct IrState {
+    double rnorm;        // ||r|| of the latest residual
+    double dnorm;        // ||d|| of the latest correction
+    double xnorm;        // ||x|| after the latest update
+    double bnorm;        // ||b||
+    double anorm;        // ||A||_inf (from the downcast)
+    double sigma;        // scale of the current low-precision solve
+    uint64_t rnorm_bits; // atomic max accumulators (bit patterns of |v| >= 0)
+    uint64_t dnorm_bits;
+    uint64_t xnorm_bits;
+    int32_t it;          // corrections done
+    int32_t done;        // 1 once a termination rule fired
+    int32_t stop;        // mpir_stop
+    int32_t wilk;        // 1: TR wider than TW (eq. wilkterm)
+    int32_t residterm;
+    int32_t litmax;
+    double tol_r, tol_e, rmax;
+    double rhist[MPIR_HIST_MAX];
+    double dhist[MPIR_HIST_MAX];
+};
+
+// Counters used by the ticket-ordered triangular solves (zeroed per solve).
+struct TrsvSync {
+    uint32_t ticket_l, done_l, ticket_u, done_u;
+};
+
+// Bounded spin: ~seconds at most; an expired wait raises DF_TIMEOUT and the
+// kernel finishes its loop without the data (the host reports an error).
+constexpr uint64_t kSpinLimit = 1ull << 26;
+
+// ---------------------------------------------------------------------------
+// Rounding helpers
+// ---------------------------------------------------------------------------
+__device__ __forceinline__ float round_f16(float x) {
+    return __half2float(__float2half_rn(x));
+}
+
+// binary64 -> binary32 rounded to odd (truncate, then set the last bit if
+// inexact).  Rounding the result to binary16 with ties-to-even then equals
+// the direct binary64 -> binary16 rounding (24 >= 11 + 2).
+__device__ __forceinline__ float d2f_round_odd(double x) {
+    float f = (float)x;
+    double back = (double)f;
+    if (back != x && !isinf(f)) {
+        uint32_t u = __float_as_uint(f);
+        if (fabs(back) > fabs(x)) u -= 1u;
+        u |= 1u;
+        f = __uint_as_float(u);
+    } else if (isinf(f) && !isinf(x)) {
+        // |x| beyond binary32: certainly beyond binary16 as well
+        f = x > 0 ? INFINITY : -INFINITY;
+    }
+    return f;
+}
+
+__device__ __forceinline__ float d2h_as_float(double x) {
+    return round_f16(d2f_round_odd(x));
+}
+
+template <typename T> __device__ __forceinline__ double to_d(T v) { return (double)v; }
+template <> __device__ __forceinline__ double to_d<__half>(__half v) { return (double)__half2float(v); }
+template <typename T> __device__ __forceinline__ float to_f(T v) { return (float)v; }
+template <> __device__ __forceinline__ float to_f<__half>(__half v) { return __half2float(v); }
+
+// Atomic max of a non-negative double through its bit pattern (IEEE order of
+// non-negative doubles equals the unsigned order of their bits; NaN maps to a
+// pattern above every finite value and infinity).
+__device__ __forceinline__ void atomic_max_nonneg(uint64_t *p, double v) {
+    uint64_t bits = __double_as_longlong(v);
+    atomicMax((unsigned long long *)p, (unsigned long long)bits);
+}
+
+// ---------------------------------------------------------------------------
+// Host-side launchers (each defined in the .hip file holding its kernel).
+// All take the stream explicitly; none synchronises.
+// ---------------------------------------------------------------------------
+
+// a1: A_F = I_W^F(A) into a row-major working array (float for TF in
+// {F32, F16}; double for F64), ||A||_inf bits and status flags.
+hipError_t launch_downcast(int64_t n, const void *A, int64_t lda, int tw, int tf,
+                           void *AF, uint64_t *anorm_bits, uint32_t *flags,
+                           hipStream_t s);
+// Working array -> packed TF factors (F16 only: float -> binary16).
+hipError_t launch_pack_half(int64_t n, const float *AF, __half *LU, hipStream_t s);
+// Working array -> TF storage with the given row-major layout (copy).
+hipError_t launch_copy_factors(int64_t n, const void *src, int tf, void *dst, hipStream_t s);
+
+// a2: leaf panel factorization (cooperative).  Rows [k0, n), columns
+// [k0, k0+w), w <= 32.  ipiv receives 0-based global row indices.
+// host_base: host copy of the arrival counter of ps (advanced per launch).
+struct PanelSync;
+hipError_t launch_leaf(int mode, void *a, int64_t n, int64_t ld, int64_t k0, int w,
+                       int32_t *ipiv, int64_t *info, PanelSync *ps, uint32_t *host_base,
+                       uint32_t *flags, hipStream_t s);
+int leaf_max_rows(int mode);
+size_t panel_sync_bytes();
+hipError_t panel_sync_reset(PanelSync *ps, hipStream_t s);
+
+// a3: row interchanges ipiv[k0 .. k0+cnt) applied to the column ranges
+// [c0, c1) and [c2, c3); perm (may be NULL) permuted alongside.
+hipError_t launch_laswp(int mode, void *a, int64_t n, int64_t ld, int64_t k0, int cnt,
+                        const int32_t *ipiv, int64_t c0, int64_t c1, int64_t c2,
+                        int64_t c3, int32_t *perm, hipStream_t s);
+// a3: U12 <- L11^{-1} U12 for rows [k, k+w) (w <= 64), columns [c0, c1).
+hipError_t launch_trsm(int mode, void *a, int64_t ld, int64_t k, int w, int64_t c0,
+                       int64_t c1, hipStream_t s);
+// a4: C[r0:r0+m, c0:c0+nc] -= A[r0:, k:k+kk] * A[k:k+kk, c0:] on one
+// row-major matrix (ld).
+hipError_t launch_gemm_update(int mode, void *a, int64_t ld, int64_t r0, int64_t m,
+                              int64_t c0, int64_t nc, int64_t k, int64_t kk,
+                              hipStream_t s);
+
+// a5: residual r = b - A x in TR, partial sums over column chunks then a
+// fixed-order reduction; ||r|| and ||x|| bits into the state.
+hipError_t launch_residual(int64_t n, const void *A, int64_t lda, int tw, int tr,
+                           const void *b, const void *x, void *r, double *partial,
+                           int nchunks, IrState *st, int force, hipStream_t s);
+int residual_chunks(int64_t n);
+
+// IR vector steps.
+hipError_t launch_ir_init(int64_t n, int tw, int tr, const void *b, void *x, void *r,
+                          IrState *st, hipStream_t s);
+hipError_t launch_set_sigma(IrState *st, hipStream_t s);
+hipError_t launch_scale_permute(int64_t n, int tr, int tf, const void *r,
+                                const int32_t *perm, void *rhat, IrState *st,
+                                TrsvSync *ts, int force, hipStream_t s);
+hipError_t launch_update(int64_t n, int tw, int tf, const void *y, void *x,
+                         IrState *st, int force, hipStream_t s);
+hipError_t launch_terminate(IrState *st, hipStream_t s);
+
+// a7: triangular solves with the packed factors (row-major, TF storage).
+// y is float for TF in {F32, F16}, double for F64.
+hipError_t launch_trsv(int tf, const void *LU, int64_t n, int64_t ld, void *y,
+                       TrsvSync *ts, uint32_t *flags, const IrState *st, int force,
+                       hipStream_t s);
+
+}  // namespace mpir

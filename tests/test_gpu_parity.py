@@ -1,0 +1,305 @@
+"""GPU parity of each hot-path step against the oracle, through the C ABI.
+
+Bars (written per test):
+  - interprecision copy: bit-identical A_F and ||A||_inf (same rounding, same
+    summation order);
+  - residual: |r_gpu - r_orc| <= gamma_n(u_d) * sum_j |a_ij x_j| (the two sum
+    in different orders);
+  - LU: identical pivot sequence on matrices without pivot near-ties, factors
+    within the forward error of two backward-stable evaluations, and the
+    componentwise bound of eq. comperr on the GPU factors themselves;
+  - one low-precision solve: the oracle's solve applied to the GPU factors,
+    within gamma_n(u_s) componentwise;
+  - refinement: iteration count within +-1 of the oracle, backward error
+    <= 1e-14, and the same stop reason.
+"""
+import sys
+
+import numpy as np
+import pytest
+
+from paper_2311_14616_amd import inputs as I
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+
+
+def say(*a):
+    print(*a, flush=True)
+    sys.stdout.flush()
+
+
+@pytest.fixture(scope="module")
+def M():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    from paper_2311_14616_amd import mpir
+    mpir.lib()
+    return mpir
+
+
+DEV = "cuda:0"
+TF = {"f64": 0, "f32": 1, "f16": 2}
+
+
+def dev(a):
+    return torch.from_numpy(np.ascontiguousarray(a)).to(DEV)
+
+
+def _gamma(k, u):
+    return k * u / (1 - k * u)
+
+
+def _perm_from_ipiv(ipiv):
+    perm = np.arange(len(ipiv))
+    for k, p in enumerate(ipiv):
+        perm[[k, p]] = perm[[p, k]]
+    return perm
+
+
+# ------------------------------------------------------------------ a1
+@pytest.mark.parametrize("tf", ["f64", "f32", "f16"])
+@pytest.mark.parametrize("n", [1, 63, 64, 65, 300])
+def test_downcast_bitwise(M, orc, tf, n):
+    say(f"downcast tf={tf} n={n}")
+    rng = np.random.default_rng(n)
+    at = rng.standard_normal((n, n)) * 10.0 ** rng.integers(-9, 4, (n, n))
+    # ties of binary16 and binary32 rounding, subnormals, the overflow edge
+    special = np.array([1 + 2.0**-11, 1 + 3 * 2.0**-11, 2.0**-25, 2.0**-24 * 1.5, 65519.0,
+                        1 + 2.0**-24, 3.0e-8, -6.1e-5])
+    at.flat[: min(n * n, len(special))] = special[: n * n]
+    out, anorm, st = M.downcast(dev(at), TF[tf])
+    assert st == 0
+    af, anorm_ref, st_ref = orc.downcast(at, TF[tf])
+    assert st_ref == 0
+    got = out.double().cpu().numpy()
+    assert np.array_equal(got, af)
+    assert anorm == anorm_ref
+
+
+def test_downcast_errors(M):
+    say("downcast errors")
+    at = I.gmat_operator(70, 1.0)
+    bad = at.copy()
+    bad[5, 9] = np.nan
+    assert M.downcast(dev(bad), M.F32)[2] == M.ERR_NONFINITE
+    assert M.downcast(dev(at * 1e5), M.F16)[2] == M.ERR_RANGE
+
+
+def test_downcast_f32_working_precision(M, orc):
+    say("downcast tw=f32")
+    n = 129
+    at = I.random_dense(n, 3, dtype=np.float32)
+    out, anorm, st = M.downcast(dev(at), M.F16)
+    af, anorm_ref, _ = orc.downcast(at, orc.F16)
+    assert st == 0 and np.array_equal(out.double().cpu().numpy(), af) and anorm == anorm_ref
+
+
+# ------------------------------------------------------------------ a5
+@pytest.mark.parametrize("tw,tr", [("f64", "f64"), ("f32", "f64"), ("f32", "f32")])
+@pytest.mark.parametrize("n", [1, 255, 256, 257, 1000])
+def test_residual(M, orc, tw, tr, n):
+    say(f"residual tw={tw} tr={tr} n={n}")
+    dt = np.float64 if tw == "f64" else np.float32
+    at = I.random_dense(n, 11, dtype=dt)
+    rng = np.random.default_rng(4)
+    x = rng.standard_normal(n).astype(dt)
+    b = rng.standard_normal(n).astype(dt)
+    r, rn = M.residual(dev(at), dev(b), dev(x), TF[tr])
+    ref = orc.residual(at, b, x, TF[tr])
+    u = 2.0**-53 if tr == "f64" else 2.0**-24
+    bound = _gamma(n + 2, u) * (np.abs(at.T.astype(np.float64)) @ np.abs(x.astype(np.float64))
+                                + np.abs(b))
+    got = r.double().cpu().numpy()
+    assert np.all(np.abs(got - ref) <= 2 * bound)
+    assert rn == np.abs(got).max()
+
+
+# ------------------------------------------------------------------ a2-a4
+FACTOR_CASES = [
+    # (name, n, tf) -- sizes span several panels, ragged tails and the
+    # multi-workgroup leaf (rows beyond one workgroup's LDS block)
+    ("gmat", 1, "f32"), ("gmat", 2, "f32"), ("gmat", 33, "f32"), ("gmat", 257, "f32"),
+    ("gmat", 600, "f32"), ("gmat", 1500, "f32"), ("gmat", 600, "f64"), ("gmat", 1100, "f64"),
+    ("gmat", 257, "f16"), ("gmat", 1300, "f16"), ("rand", 300, "f32"), ("rand", 520, "f64"),
+    ("rand", 700, "f16"),
+]
+
+
+def _case_matrix(name, n, seed=5):
+    if name == "gmat":
+        return I.gmat_operator(n, 10.0)
+    return I.random_dense(n, seed)
+
+
+def _lu_mode(orc, tf):
+    return {"f64": orc.LU_F64, "f32": orc.LU_F32, "f16": orc.LU_F16MIXED}[tf]
+
+
+@pytest.mark.parametrize("name,n,tf", FACTOR_CASES)
+def test_factor_parity(M, orc, name, n, tf):
+    say(f"factor {name} n={n} tf={tf}")
+    at = _case_matrix(name, n)
+    f = M.factor(dev(at), TF[tf])
+    lu, ipiv = f.factors()
+    f.destroy()
+    lu = lu.double().cpu().numpy()
+    af, _, _ = orc.downcast(at, TF[tf])
+    lu_o, ipiv_o, info_o, _ = orc.lu(af, _lu_mode(orc, tf))
+    assert info_o == 0 and f.info == 0
+    L = np.tril(lu, -1) + np.eye(n)
+    U = np.triu(lu)
+    pa = af[_perm_from_ipiv(ipiv)]
+    # partial pivoting: every multiplier is at most one in magnitude
+    assert np.abs(np.tril(lu, -1)).max() <= 1.0
+    if tf == "f16":
+        assert np.array_equal(lu, lu.astype(np.float16).astype(np.float64))
+        # binary16 factors with binary32 updates (bound pinned on the oracle)
+        bound = (3 * 2.0**-11 + _gamma(3 * n, 2.0**-24)) * (np.abs(L) @ np.abs(U)) \
+            + 2.0**-24 * (1 + np.abs(np.diag(U)).max())
+        assert np.all(np.abs(L @ U - pa) <= bound)
+    else:
+        u = {"f64": 2.0**-53, "f32": 2.0**-24}[tf]
+        # eq. comperr on the GPU factors
+        assert np.all(np.abs(L @ U - pa) <= _gamma(3 * n, u) * (np.abs(L) @ np.abs(U)) + 1e-300)
+    # The pivot sequence is unique unless two candidates are within rounding
+    # of each other.  With binary16 factors a one-ulp difference of a binary32
+    # sum (GPU and oracle add in different orders) moves a U entry by one
+    # binary16 ulp, enough to flip near-ties of a random matrix; there the
+    # sequences are compared up to the first difference only.
+    if tf != "f16" or name == "gmat":
+        assert np.array_equal(ipiv, ipiv_o)
+    else:
+        d = np.nonzero(ipiv != ipiv_o)[0]
+        assert len(d) == 0 or d[0] >= n // 8
+    if np.array_equal(ipiv, ipiv_o):
+        # both factorizations are backward stable, so entrywise they differ
+        # by at most about kappa(A) * gamma_3n(u) relative to the factors
+        a = at.T
+        kappa = np.abs(a).sum(1).max() * np.abs(np.linalg.inv(a)).sum(1).max()
+        u = {"f64": 2.0**-53, "f32": 2.0**-24, "f16": 2.0**-11}[tf]
+        tol = min(0.5, kappa * 3 * n * u)
+        assert np.abs(lu - lu_o).max() <= tol * np.abs(lu_o).max()
+
+
+def test_singular_matrix_reports_first_zero_pivot(M):
+    say("factor singular")
+    n = 100
+    a = I.random_dense(n, 9).T.copy()
+    a[:, 37] = 0.0
+    f = M.factor(dev(np.ascontiguousarray(a.T)), M.F32)
+    assert f.status == M.ERR_SINGULAR and f.info == 38
+    f.destroy()
+
+
+# ------------------------------------------------------------------ a6-a8
+@pytest.mark.parametrize("tf,n", [("f32", 1), ("f32", 64), ("f32", 200), ("f32", 1500),
+                                  ("f16", 333), ("f64", 700)])
+def test_single_solve_parity(M, orc, tf, n):
+    say(f"solve tf={tf} n={n}")
+    at = I.gmat_operator(n, 10.0)
+    b = np.random.default_rng(1).standard_normal(n) * 1e-3
+    f = M.factor(dev(at), TF[tf])
+    lu, ipiv = f.factors()
+    x = f.solve(dev(b)).cpu().numpy()
+    f.destroy()
+    lu = lu.double().cpu().numpy()
+    sigma = orc.pow2_ceil(np.abs(b).max())
+    y = orc.apply_pivots(ipiv, b) / sigma
+    y = {"f32": y.astype(np.float32).astype(np.float64), "f16": orc.fl_h(y), "f64": y}[tf]
+    ts = orc.TS_F64 if tf == "f64" else orc.TS_F32
+    ref = sigma * orc.trsv_lu(lu, y, ts)
+    u = 2.0**-53 if tf == "f64" else 2.0**-24
+    # componentwise forward error of substitution: |dx| <= gamma_2n |U^-1||L^-1||L||U||x|
+    L = np.tril(lu, -1) + np.eye(n)
+    U = np.triu(lu)
+    Li, Ui = np.linalg.inv(L), np.linalg.inv(U)
+    bound = _gamma(2 * n + 2, u) * (np.abs(Ui) @ np.abs(Li) @ np.abs(L) @ np.abs(U) @ np.abs(ref))
+    assert np.all(np.abs(x - ref) <= 4 * bound + 1e-300)
+
+
+# ------------------------------------------------------------------ a9 (loop)
+IR_CASES = [
+    ("config0", 512, 1.0, "f32"), ("gmat", 1, 1.0, "f32"), ("gmat", 100, 10.0, "f32"),
+    ("gmat", 777, 100.0, "f32"), ("gmat", 1500, 1.0, "f32"), ("gmat", 512, 1.0, "f16"),
+    ("gmat", 900, 10.0, "f16"), ("gmat", 300, 100.0, "f16"), ("gmat", 400, 1.0, "f64"),
+]
+
+
+@pytest.mark.parametrize("name,n,alpha,tf", IR_CASES)
+def test_ir_parity(M, orc, name, n, alpha, tf):
+    say(f"ir {name} n={n} alpha={alpha} tf={tf}")
+    at = I.gmat_operator(n, alpha)
+    b = I.rhs_ones(at)
+    tp = M.term(tol_rel=1e-14, litmax=20)
+    x, rep = M.ir_solve(dev(at), dev(b), TF[tf], term_parms=tp)
+    ref = orc.ir_solve(at, b, TF[tf], tol_rel=1e-14, litmax=20)
+    xg = x.cpu().numpy()
+    assert rep.stop_name == ref.stop_name == "converged"
+    assert abs(rep.n_iter - ref.n_iter) <= 1
+    assert rep.bwd_err <= 1e-14 and ref.bwd_err <= 1e-14
+    rh, dh = rep.history()
+    assert rh[0] == ref.rhist[0]            # ||b||, same data
+    assert rep.relres == pytest.approx(rh[-1] / rh[0], rel=1e-12)
+    xref, _, _ = orc.solve_f64(at, b)
+    ferr = np.abs(xg - xref).max() / np.abs(xref).max()
+    kappa = np.abs(at).sum(0).max() * np.abs(np.linalg.inv(at.T)).sum(1).max()
+    assert ferr <= 1e-12 * kappa * (2.0**-53 / 1e-16)
+    say(f"  n_iter gpu={rep.n_iter} oracle={ref.n_iter} bwd={rep.bwd_err:.2e} ferr={ferr:.2e}")
+
+
+def test_ir_zero_rhs_and_nonfinite(M):
+    say("ir zero rhs / nonfinite")
+    n = 50
+    at = I.gmat_operator(n, 1.0)
+    x, rep = M.ir_solve(dev(at), dev(np.zeros(n)), M.F32)
+    assert rep.n_iter == 0 and rep.stop_name == "converged" and torch.all(x == 0)
+    b = I.rhs_ones(at)
+    b[7] = np.nan
+    f = M.factor(dev(at), M.F32)
+    with pytest.raises(M.MpirError) as e:
+        f.ir_solve(dev(b))
+    assert e.value.status == M.ERR_NONFINITE
+    f.destroy()
+
+
+def test_ir_extended_residual(M, orc):
+    # TW = TF = F32, TR = F64: x kept in binary32, stop on eq. wilkterm
+    say("ir tw=f32 tr=f64")
+    n = 700
+    at32, b32, xstar, _ = I.wilkinson_operator(n, 1e6)
+    x, rep = M.ir_solve(dev(at32), dev(b32), M.F32, tr=M.F64, term_parms=M.term(litmax=20))
+    ref = orc.ir_solve(at32, b32, orc.F32, tr=orc.F64, litmax=20)
+    assert rep.stop_name == ref.stop_name == "dstagnated"
+    assert abs(rep.n_iter - ref.n_iter) <= 1
+    xp, _, _ = orc.solve_f64(at32, b32)
+    xg = x.cpu().numpy().astype(np.float64)
+    assert np.abs(xg - xp).max() / np.abs(xp).max() <= 4 * 2.0**-24
+
+
+def test_ir_half_from_single(M, orc):
+    # TW = TR = F32, TF = F16 (the paper's default when TW is single)
+    say("ir tw=f32 tf=f16 tr=f32")
+    n = 256
+    at = I.gmat_operator(n, 1.0).astype(np.float32)
+    b = I.rhs_ones(at).astype(np.float32)
+    x, rep = M.ir_solve(dev(at), dev(b), M.F16, term_parms=M.term(litmax=20))
+    ref = orc.ir_solve(at, b, orc.F16, litmax=20)
+    assert abs(rep.n_iter - ref.n_iter) <= 1 and rep.stop_name == ref.stop_name
+    # a binary32 residual stalls at the level of eq. stagterm, gamma_n(u_s)
+    assert rep.bwd_err <= _gamma(n, 2.0**-24) and ref.bwd_err <= _gamma(n, 2.0**-24)
+
+
+def test_refactor_reuses_handle(M, orc):
+    say("refactor")
+    n = 300
+    a1 = I.gmat_operator(n, 1.0)
+    a2 = I.gmat_operator(n, 50.0)
+    f = M.factor(dev(a1), M.F32)
+    A2 = dev(a2)
+    f.refactor(A2)
+    b = I.rhs_ones(a2)
+    x, rep = f.ir_solve(dev(b), term_parms=M.term(tol_rel=1e-14, litmax=20))
+    f.destroy()
+    assert rep.stop_name == "converged" and rep.bwd_err <= 1e-14

@@ -104,3 +104,21 @@ def test_anorm_is_max_row_sum(orc):
     at = I.random_dense(50, 9)
     _, anorm, _ = orc.downcast(at, orc.F32)
     assert anorm == pytest.approx(np.abs(at.T).sum(1).max(), rel=1e-15)
+
+
+@pytest.mark.parametrize("kind,n,alpha", [("gauss", 700, 0.0), ("gmat", 1300, 10.0),
+                                          ("gmat", 800, 1.0)])
+def test_f16mixed_backward_error_with_underflow(orc, kind, n, alpha):
+    # binary16 factors, binary32 updates: one binary16 rounding per L and U
+    # entry (relative u_h, or absolute 2^-25 in the subnormal range) plus the
+    # binary32 update errors, valid at any n:
+    #   |L U - P A_F| <= (3 u_h + gamma_3n(u_s)) |L||U| + 2^-24 (1 + max|u_kk|)
+    at = I.random_dense(n, 5) if kind == "gauss" else I.gmat_operator(n, alpha)
+    af, _, _ = orc.downcast(at, orc.F16)
+    lu, ipiv, info, _ = orc.lu(af, orc.LU_F16MIXED)
+    assert info == 0
+    L, U = _unpack(lu)
+    lhs = np.abs(L @ U - af[_perm_from_ipiv(ipiv)])
+    rhs = (3 * 2.0**-11 + _gamma(3 * n, 2.0**-24)) * (np.abs(L) @ np.abs(U)) \
+        + 2.0**-24 * (1 + np.abs(np.diag(U)).max())
+    assert np.all(lhs <= rhs)
