@@ -1,0 +1,167 @@
+"""Benchmark: mixed-precision IR time-to-solve vs an FP64 LU solve, one GPU.
+
+Workload (default): A = I - alpha*G (the paper's integral-equation operator,
+interior grid), alpha = 1, N = 32768, b = A*ones, TW = FP64, TF = FP32,
+TR = FP64; stop when ||r||/||b|| <= 1e-14 (litmax 20).  A step is one full
+pass of the hot path: mpir_factor (downcast + blocked LU on the matrix cores)
+followed by mpir_ir_solve (triangular solves, update, FP64 residual,
+termination) with A and b already resident in HBM.  The comparator is an FP64
+LU factorization + solve (mpir_factor with TF = FP64, then mpir_solve) on the
+same GPU, timed the same way.  Prints one JSON line.
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+METRIC = "IR vs FP64-LU time-to-solve at 1e-14 backward err; batched solves/s"
+PEAK = {"f32": 157.3, "f16": 2516.6, "f64": 78.6}     # dense matrix TFLOP/s (MI355X)
+HBM_PEAK = 8000.0                                     # GB/s
+
+
+def log(*a):
+    print(*a, file=sys.stderr, flush=True)
+
+
+def cpu_baseline(n_sample: int, n_full: int):
+    """Time the oracle (plain C, OpenMP) on a bounded sample of the workload
+    and scale it to the full size (LU ~ N^3 dominates)."""
+    import numpy as np
+    from oracle import oracle as O
+    from paper_2311_14616_amd import inputs as I
+    at = I.gmat_operator(n_sample, 1.0)
+    b = I.rhs_ones(at)
+    t0 = time.perf_counter()
+    r = O.ir_solve(at, b, O.F32, tol_rel=1e-14, litmax=20)
+    dt = time.perf_counter() - t0
+    scale = (n_full / n_sample) ** 3
+    return {"value": dt * 1e3 * scale, "unit": "ms", "cores": O.num_threads(), "kind": "oracle",
+            "sample": f"full IR solve (emulated FP32 LU + FP64 residual loop) at N={n_sample}, "
+                      f"{dt:.2f} s measured, scaled by (N/{n_sample})^3 = {scale:.0f} to N={n_full}",
+            "sample_n_iter": int(r.n_iter), "sample_s": dt}
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=3)
+    ap.add_argument("--warmup", type=int, default=1)
+    ap.add_argument("--n", type=int, default=32768)
+    ap.add_argument("--alpha", type=float, default=1.0)
+    ap.add_argument("--tf", choices=["f32", "f16"], default="f32")
+    ap.add_argument("--fp64-runs", type=int, default=1)
+    ap.add_argument("--cpu-sample", type=int, default=3072)
+    ap.add_argument("--no-cpu", action="store_true")
+    ap.add_argument("--no-fp64", action="store_true")
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print(json.dumps({"error": "this build runs on one GPU; multi-GPU sharding is "
+                                   "described in DESIGN.md but not built"}))
+        sys.exit(2)
+
+    import torch
+    import paper_2311_14616_amd.mpir as M
+    from paper_2311_14616_amd import inputs as I
+
+    dev = torch.device("cuda:0")
+    n = args.n
+    tf = {"f32": M.F32, "f16": M.F16}[args.tf]
+    log(f"[bench] generating A (N={n}) on the device")
+    At = I.gmat_operator_torch(n, args.alpha, dev)
+    b = I.rhs_ones_torch(At)
+    x = torch.empty_like(b)
+    torch.cuda.synchronize()
+    stream = torch.cuda.current_stream()
+    tp = M.term(tol_rel=1e-14, litmax=20)
+
+    def step():
+        f = M.Factorization(At, tf, M.F64, stream)
+        _, rep = f.ir_solve(b, x, tp)
+        f.destroy()
+        return rep
+
+    for w in range(args.warmup):
+        log(f"[bench] warmup {w}")
+        step()
+    torch.cuda.synchronize()
+    M.prof_reset()
+    M.prof_enable(True)
+    log(f"[bench] timing {args.steps} steps")
+    t0 = time.perf_counter()
+    reps = [step() for _ in range(args.steps)]
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    M.prof_enable(False)
+    ms_step = (t1 - t0) * 1e3 / args.steps
+    rep = reps[-1]
+    g_ms, g_cnt, g_flops = M.prof_get(M.PROF_GEMM)
+    p_ms, p_cnt, _ = M.prof_get(M.PROF_PANEL)
+    t_ms, t_cnt, _ = M.prof_get(M.PROF_TRSV)
+    v_ms, v_cnt, v_bytes = M.prof_get(M.PROF_GEMV)
+    d_ms, d_cnt, d_bytes = M.prof_get(M.PROF_DOWNCAST)
+    gemm_tflops = g_flops / (g_ms * 1e-3) / 1e12 if g_ms > 0 else 0.0
+    gemv_gbs = v_bytes / (v_ms * 1e-3) / 1e9 if v_ms > 0 else 0.0
+    trsv_bytes_per = (4 if args.tf == "f32" else 2) * n * n
+    trsv_gbs = trsv_bytes_per * t_cnt / (t_ms * 1e-3) / 1e9 if t_ms > 0 else 0.0
+    log(f"[bench] IR step {ms_step:.2f} ms  n_iter={rep.n_iter} stop={rep.stop_name} "
+        f"bwd={rep.bwd_err:.2e}  gemm {gemm_tflops:.1f} TF/s  panel {p_ms / args.steps:.1f} ms/step")
+
+    out = {
+        "metric": METRIC, "value": round(ms_step, 3), "unit": "ms", "n_gpus": 1,
+        "steps": args.steps, "warmup": args.warmup, "ms_per_step": round(ms_step, 3),
+        "higher_is_better": False, "scaling": "weak", "vs_baseline": None,
+        "dtype": f"{args.tf}+f64", "data": "synthetic",
+        "config": {"workload": f"IR solve of A = I - {args.alpha:g}*Gmat(N), b = A*ones, "
+                               f"N={n}, TW=FP64, TF={args.tf.upper()}, TR=FP64, "
+                               f"tol ||r||/||b|| <= 1e-14, litmax 20",
+                   "n": n, "alpha": args.alpha, "tw": "f64", "tf": args.tf, "tr": "f64"},
+        "ir": {"n_iter": rep.n_iter, "stop": rep.stop_name, "bwd_err": rep.bwd_err,
+               "relres": rep.relres, "t_factor_ms": rep.t_factor_ms, "t_ir_ms": rep.t_ir_ms},
+        "roofline": {"bound": "mfma", "achieved": round(gemm_tflops, 2), "peak": PEAK[args.tf],
+                     "unit": "TFLOP/s", "frac": round(gemm_tflops / PEAK[args.tf], 4),
+                     "traffic": None, "kernel": f"trailing-update GEMM ({args.tf} MFMA)",
+                     "launches": g_cnt, "avg_launch_ms": g_ms / max(g_cnt, 1)},
+        "kernels": {
+            "gemm_ms_per_step": g_ms / args.steps, "panel_ms_per_step": p_ms / args.steps,
+            "trsv_ms_per_step": t_ms / args.steps, "gemv_ms_per_step": v_ms / args.steps,
+            "downcast_ms_per_step": d_ms / args.steps,
+            "gemv_GBps": round(gemv_gbs, 1), "gemv_hbm_frac": round(gemv_gbs / HBM_PEAK, 4),
+            "trsv_GBps": round(trsv_gbs, 1),
+        },
+    }
+    if not args.no_fp64:
+        log("[bench] FP64 LU comparator")
+        xs = torch.empty_like(b)
+
+        def fp64_step():
+            f = M.Factorization(At, M.F64, M.F64, stream)
+            f.solve(b, xs)
+            f.destroy()
+
+        fp64_step()            # warm-up
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(args.fp64_runs):
+            fp64_step()
+        torch.cuda.synchronize()
+        fp64_ms = (time.perf_counter() - t0) * 1e3 / args.fp64_runs
+        r64, rn64 = M.residual(At, b, xs, M.F64)
+        bn = float(b.abs().max())
+        out["fp64_lu_ms"] = round(fp64_ms, 3)
+        out["speedup_vs_fp64_lu"] = round(fp64_ms / ms_step, 3)
+        out["fp64_lu_relres"] = rn64 / bn
+        log(f"[bench] FP64 LU solve {fp64_ms:.2f} ms  relres={rn64 / bn:.2e}")
+    if not args.no_cpu:
+        log(f"[bench] CPU oracle sample N={args.cpu_sample}")
+        out["cpu_baseline"] = cpu_baseline(args.cpu_sample, n)
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()
