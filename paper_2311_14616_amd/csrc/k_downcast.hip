@@ -18,7 +18,7 @@ constexpr int TC = 64;   // columns per tile
 
 template <typename TWt, typename Wt, int TF>
 __global__ __launch_bounds__(256) void k_downcast(int64_t n, const TWt *__restrict__ A,
-                                                  int64_t lda, Wt *__restrict__ AF,
+                                                  int64_t lda, Wt *__restrict__ AF, int64_t ldf,
                                                   uint64_t *anorm_bits, uint32_t *flags) {
     __shared__ double tile[TC][TR + 1];
     const int t = threadIdx.x;
@@ -64,7 +64,7 @@ __global__ __launch_bounds__(256) void k_downcast(int64_t n, const TWt *__restri
                     else w = (Wt)d2h_as_float(v);
                     if (!isfinite(v)) fl |= DF_NONFINITE;
                     else if (isinf((double)w)) fl |= DF_RANGE;
-                    AF[i * n + j] = w;
+                    AF[i * ldf + j] = w;
                 }
             }
         }
@@ -77,37 +77,42 @@ __global__ __launch_bounds__(256) void k_downcast(int64_t n, const TWt *__restri
     if (fl) atomicOr(flags, fl);
 }
 
-__global__ void k_pack_half(int64_t total, const float *__restrict__ src, __half *__restrict__ dst) {
+__global__ void k_pack_half(int64_t n, const float *__restrict__ src, int64_t lds,
+                            __half *__restrict__ dst) {
+    const int64_t total = n * n;
     int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     const int64_t stride = (int64_t)gridDim.x * blockDim.x;
-    for (; i < total; i += stride) dst[i] = __float2half_rn(src[i]);
+    for (; i < total; i += stride) {
+        const int64_t r = i / n, c = i - r * n;
+        dst[i] = __float2half_rn(src[r * lds + c]);
+    }
 }
 
 }  // namespace
 
 hipError_t launch_downcast(int64_t n, const void *A, int64_t lda, int tw, int tf, void *AF,
-                           uint64_t *anorm_bits, uint32_t *flags, hipStream_t s) {
+                           int64_t ldf, uint64_t *anorm_bits, uint32_t *flags, hipStream_t s) {
     if (n <= 0) return hipSuccess;
     dim3 grid((unsigned)((n + TR - 1) / TR)), block(256);
     if (tw == MPIR_F64) {
         const double *a = (const double *)A;
-        if (tf == MPIR_F64) k_downcast<double, double, MPIR_F64><<<grid, block, 0, s>>>(n, a, lda, (double *)AF, anorm_bits, flags);
-        else if (tf == MPIR_F32) k_downcast<double, float, MPIR_F32><<<grid, block, 0, s>>>(n, a, lda, (float *)AF, anorm_bits, flags);
-        else k_downcast<double, float, MPIR_F16><<<grid, block, 0, s>>>(n, a, lda, (float *)AF, anorm_bits, flags);
+        if (tf == MPIR_F64) k_downcast<double, double, MPIR_F64><<<grid, block, 0, s>>>(n, a, lda, (double *)AF, ldf, anorm_bits, flags);
+        else if (tf == MPIR_F32) k_downcast<double, float, MPIR_F32><<<grid, block, 0, s>>>(n, a, lda, (float *)AF, ldf, anorm_bits, flags);
+        else k_downcast<double, float, MPIR_F16><<<grid, block, 0, s>>>(n, a, lda, (float *)AF, ldf, anorm_bits, flags);
     } else {
         const float *a = (const float *)A;
-        if (tf == MPIR_F32) k_downcast<float, float, MPIR_F32><<<grid, block, 0, s>>>(n, a, lda, (float *)AF, anorm_bits, flags);
-        else k_downcast<float, float, MPIR_F16><<<grid, block, 0, s>>>(n, a, lda, (float *)AF, anorm_bits, flags);
+        if (tf == MPIR_F32) k_downcast<float, float, MPIR_F32><<<grid, block, 0, s>>>(n, a, lda, (float *)AF, ldf, anorm_bits, flags);
+        else k_downcast<float, float, MPIR_F16><<<grid, block, 0, s>>>(n, a, lda, (float *)AF, ldf, anorm_bits, flags);
     }
     return hipGetLastError();
 }
 
-hipError_t launch_pack_half(int64_t n, const float *AF, __half *LU, hipStream_t s) {
+hipError_t launch_pack_half(int64_t n, const float *AF, int64_t ldf, __half *LU, hipStream_t s) {
     const int64_t total = n * n;
     if (total <= 0) return hipSuccess;
     int64_t blocks = (total + 255) / 256;
     if (blocks > 65536) blocks = 65536;
-    k_pack_half<<<(unsigned)blocks, 256, 0, s>>>(total, AF, LU);
+    k_pack_half<<<(unsigned)blocks, 256, 0, s>>>(n, AF, ldf, LU);
     return hipGetLastError();
 }
 

@@ -10,12 +10,17 @@
 //              accumulators; A22 stays binary32.
 //   TF = F64 : binary64, v_mfma_f64_16x16x4_f64 (the FP64 comparator).
 //
-// Tiling: 128 x 128 C tile per workgroup of four wave64s (2 x 2), each wave
-// owning 64 x 64 of C in accumulator registers; operand tiles are staged in
-// LDS with the next K-chunk prefetched into registers while the current one
-// is multiplied.  The launch maps consecutive workgroup ids to tiles of one
-// tile-row so that a tile-row's L21 block is shared in L2 by the workgroups
-// that the dispatcher places on the same XCD.
+// Tiling: a workgroup of four wave64s computes a BM x BN tile of C (binary32:
+// 256 x 128, each wave 128 x 64 = 4 x 2 blocks of 32 x 32; binary64:
+// 128 x 128, each wave 64 x 64 = 4 x 4 blocks of 16 x 16), accumulators in
+// registers.  K is walked in chunks staged through two LDS buffers: while the
+// matrix cores work on chunk i, the global loads of chunk i+1 are in flight
+// (16-byte vector loads when every offset is 4-element aligned), so the load
+// latency hides behind the MFMA work of a chunk.  Workgroup ids are remapped
+// so that each XCD (which has its own L2) receives a contiguous band of
+// tiles sharing L21 rows and U12 columns.
+#include <type_traits>
+
 #include "mpir_internal.h"
 
 namespace mpir {
@@ -24,176 +29,171 @@ namespace {
 typedef float floatx16 __attribute__((ext_vector_type(16)));
 typedef float floatx4 __attribute__((ext_vector_type(4)));
 typedef _Float16 half8 __attribute__((ext_vector_type(8)));
+typedef _Float16 half4 __attribute__((ext_vector_type(4)));
 typedef double doublex4 __attribute__((ext_vector_type(4)));
 
-constexpr int BM = 128, BN = 128;
-
-// XCD-aware tile order: hardware dispatches workgroup ids round-robin over
-// the 8 XCDs; remap so that XCD x receives a contiguous range of tiles
-// (neighbouring tiles share operand rows/columns in that XCD's L2).
+// XCD-aware tile order: the dispatcher hands workgroup ids round-robin to
+// the 8 XCDs; remap so that XCD x owns the contiguous tile range
+// [x*per, (x+1)*per) (tiles ordered row-major over the tile grid).
 __device__ __forceinline__ int xcd_remap(int bid, int nblk) {
     constexpr int NX = 8;
     if (nblk < NX * 4) return bid;
-    const int per = nblk / NX;               // tiles per XCD (full part)
+    const int per = nblk / NX;
     const int full = per * NX;
     if (bid >= full) return bid;
-    const int x = bid % NX, q = bid / NX;
-    return x * per + q;
+    return (bid % NX) * per + bid / NX;
 }
 
-// ---------------------------------------------------------------- binary32
-template <int BK>
-__global__ __launch_bounds__(256) void k_gemm_f32(float *__restrict__ a, int64_t ld, int64_t r0,
-                                                  int64_t m, int64_t c0, int64_t nc, int64_t k,
-                                                  int64_t kk, int tiles_n, int nblk) {
-    __shared__ float As[BK][BM + 4];   // k-major: lanes read consecutive rows
-    __shared__ float Bs[BK][BN + 4];
+template <bool VEC, int NV>
+__device__ __forceinline__ void load_row_f32(float (&dst)[NV], const float *src, bool rowok,
+                                             int64_t k0, int64_t klim) {
+    // NV consecutive floats from src[k0 ...], zero beyond klim or if !rowok
+    if (VEC && rowok && k0 + NV <= klim) {
+#pragma unroll
+        for (int q = 0; q < NV; q += 4) {
+            const floatx4 v = *reinterpret_cast<const floatx4 *>(src + k0 + q);
+            dst[q] = v[0]; dst[q + 1] = v[1]; dst[q + 2] = v[2]; dst[q + 3] = v[3];
+        }
+    } else {
+#pragma unroll
+        for (int q = 0; q < NV; ++q) dst[q] = (rowok && k0 + q < klim) ? src[k0 + q] : 0.0f;
+    }
+}
+
+// ------------------------------------------------- binary32 and binary16
+// Workgroup tile BM x BN, K-chunk BK, NBUF LDS buffers, four waves in a 2 x 2
+// grid, each wave (BM/2) x (BN/2) of C in 32 x 32 MFMA blocks.
+// Global -> register split: A: TPR = 256/BM threads per row, each BK/TPR
+// consecutive k; B: TPK = 256/BK threads per k-row, each BN/TPK consecutive
+// columns.  Binary32 tiles are stored k-major in LDS (lanes read consecutive
+// rows or columns of one k); binary16 tiles row-major for A and transposed
+// for B (8 consecutive k per lane, one 16-byte LDS read per operand).
+template <bool HALF, bool VEC, int BM, int BN, int BK, int NBUF>
+__global__ __launch_bounds__(256) void k_gemm_32(float *__restrict__ a, int64_t ld, int64_t r0,
+                                                 int64_t m, int64_t c0, int64_t nc, int64_t k,
+                                                 int64_t kk, int tiles_n, int nblk) {
+    constexpr int TPR = 256 / BM, AK = BK / TPR;      // A: threads per row, k's per thread
+    constexpr int TPK = 256 / BK, BCOL = BN / TPK;    // B: threads per k-row, cols per thread
+    constexpr int MI = BM / 64, NJ = BN / 64;         // 32x32 blocks per wave
+    static_assert(TPR * BM == 256 && TPK * BK == 256 && AK % 4 == 0 && BCOL % 4 == 0, "split");
+    static_assert(!HALF || BK % 16 == 0, "half k-step");
+    using T = typename std::conditional<HALF, _Float16, float>::type;
+    constexpr int AP = HALF ? BK + 8 : BM + 4;     // pitch of the fast dim
+    constexpr int BP = HALF ? BK + 8 : BN + 4;
+    constexpr int AS = HALF ? BM * AP : BK * AP;
+    constexpr int BS = HALF ? BN * BP : BK * BP;
+    __shared__ __align__(16) T As[NBUF][AS];
+    __shared__ __align__(16) T Bs[NBUF][BS];
+
     const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
     const int bid = xcd_remap(blockIdx.x, nblk);
     const int64_t tm = (int64_t)(bid / tiles_n) * BM, tn = (int64_t)(bid % tiles_n) * BN;
-    const int wm = (wv >> 1) * 64, wn = (wv & 1) * 64;
+    const int wm = (wv >> 1) * (BM / 2), wn = (wv & 1) * (BN / 2);
 
-    // global->register staging: A: row tid/2, 8 k's; B: k tid/16, 8 cols
-    constexpr int AK = BK / 2;           // k's per thread for A (BK = 16 -> 8)
-    const int arow = tid >> 1, ak0 = (tid & 1) * AK;
-    constexpr int BCOLS = (BN * BK) / 256;   // cols per thread for B (8)
-    const int bk = tid / (BN / BCOLS), bc0 = (tid % (BN / BCOLS)) * BCOLS;
-    float ra[AK], rb[BCOLS];
+    const int arow = tid / TPR, ak0 = (tid % TPR) * AK;
+    const bool arow_ok = tm + arow < m;
+    const float *ap = a + (r0 + tm + arow) * ld + k + ak0;
+    const int bk = tid / TPK, bc0 = (tid % TPK) * BCOL;
+    const float *bp = a + k * ld + c0 + tn + bc0;
+    const int64_t bcol_lim = nc - (tn + bc0);     // valid columns from bc0
+
+    float ra[AK], rb[BCOL];
     auto load = [&](int64_t kc) {
-        const int64_t gi = r0 + tm + arow;
-        const bool rok = (tm + arow) < m;
-#pragma unroll
-        for (int q = 0; q < AK; ++q) {
-            const int64_t kq = kc + ak0 + q;
-            ra[q] = (rok && kq < kk) ? a[gi * ld + k + kq] : 0.0f;
-        }
+        load_row_f32<VEC, AK>(ra, ap, arow_ok, kc, kk - ak0);
         const int64_t kr = kc + bk;
+        const bool kok = kr < kk;
+        if (VEC && kok && bcol_lim >= BCOL) {
 #pragma unroll
-        for (int q = 0; q < BCOLS; ++q) {
-            const int64_t cj = tn + bc0 + q;
-            rb[q] = (kr < kk && cj < nc) ? a[(k + kr) * ld + c0 + cj] : 0.0f;
+            for (int q = 0; q < BCOL; q += 4) {
+                const floatx4 v = *reinterpret_cast<const floatx4 *>(bp + kr * ld + q);
+                rb[q] = v[0]; rb[q + 1] = v[1]; rb[q + 2] = v[2]; rb[q + 3] = v[3];
+            }
+        } else {
+#pragma unroll
+            for (int q = 0; q < BCOL; ++q) rb[q] = (kok && q < bcol_lim) ? bp[kr * ld + q] : 0.0f;
         }
     };
-    auto store = [&]() {
+    auto store = [&](int buf) {
+        if constexpr (HALF) {
 #pragma unroll
-        for (int q = 0; q < AK; ++q) As[ak0 + q][arow] = ra[q];
+            for (int q = 0; q < AK; q += 4) {
+                half4 h;
+                h[0] = (_Float16)ra[q]; h[1] = (_Float16)ra[q + 1];
+                h[2] = (_Float16)ra[q + 2]; h[3] = (_Float16)ra[q + 3];
+                *reinterpret_cast<half4 *>(&As[buf][arow * AP + ak0 + q]) = h;
+            }
 #pragma unroll
-        for (int q = 0; q < BCOLS; ++q) Bs[bk][bc0 + q] = rb[q];
+            for (int q = 0; q < BCOL; ++q) Bs[buf][(bc0 + q) * BP + bk] = (_Float16)rb[q];
+        } else {
+#pragma unroll
+            for (int q = 0; q < AK; ++q) As[buf][(ak0 + q) * AP + arow] = ra[q];
+#pragma unroll
+            for (int q = 0; q < BCOL; q += 4) {
+                floatx4 v;
+                v[0] = rb[q]; v[1] = rb[q + 1]; v[2] = rb[q + 2]; v[3] = rb[q + 3];
+                *reinterpret_cast<floatx4 *>(&Bs[buf][bk * BP + bc0 + q]) = v;
+            }
+        }
     };
 
-    floatx16 acc[2][2];
+    floatx16 acc[MI][NJ];
 #pragma unroll
-    for (int i = 0; i < 2; ++i)
+    for (int i = 0; i < MI; ++i)
 #pragma unroll
-        for (int j = 0; j < 2; ++j) acc[i][j] = floatx16{0};
+        for (int j = 0; j < NJ; ++j) acc[i][j] = floatx16{0};
 
     load(0);
+    store(0);
+    __syncthreads();
+    int buf = 0;
     for (int64_t kc = 0; kc < kk; kc += BK) {
-        store();
-        __syncthreads();
-        if (kc + BK < kk) load(kc + BK);
+        const bool more = kc + BK < kk;
+        if (more) load(kc + BK);
+        if constexpr (HALF) {
 #pragma unroll
-        for (int s = 0; s < BK; s += 2) {
-            const int kr = s + (lane >> 5);
-            float af[2], bf[2];
+            for (int s = 0; s < BK; s += 16) {
+                const int kb = s + 8 * (lane >> 5);
+                half8 af[MI], bf[NJ];
 #pragma unroll
-            for (int i = 0; i < 2; ++i) af[i] = As[kr][wm + i * 32 + (lane & 31)];
+                for (int i = 0; i < MI; ++i)
+                    af[i] = *reinterpret_cast<const half8 *>(&As[buf][(wm + i * 32 + (lane & 31)) * AP + kb]);
 #pragma unroll
-            for (int j = 0; j < 2; ++j) bf[j] = Bs[kr][wn + j * 32 + (lane & 31)];
+                for (int j = 0; j < NJ; ++j)
+                    bf[j] = *reinterpret_cast<const half8 *>(&Bs[buf][(wn + j * 32 + (lane & 31)) * BP + kb]);
 #pragma unroll
-            for (int i = 0; i < 2; ++i)
+                for (int i = 0; i < MI; ++i)
 #pragma unroll
-                for (int j = 0; j < 2; ++j)
-                    acc[i][j] = __builtin_amdgcn_mfma_f32_32x32x2f32(af[i], bf[j], acc[i][j], 0, 0, 0);
+                    for (int j = 0; j < NJ; ++j)
+                        acc[i][j] = __builtin_amdgcn_mfma_f32_32x32x16_f16(af[i], bf[j], acc[i][j], 0, 0, 0);
+            }
+        } else {
+#pragma unroll
+            for (int s = 0; s < BK; s += 2) {
+                const int kr = s + (lane >> 5);
+                float af[MI], bf[NJ];
+#pragma unroll
+                for (int i = 0; i < MI; ++i) af[i] = As[buf][kr * AP + wm + i * 32 + (lane & 31)];
+#pragma unroll
+                for (int j = 0; j < NJ; ++j) bf[j] = Bs[buf][kr * BP + wn + j * 32 + (lane & 31)];
+#pragma unroll
+                for (int i = 0; i < MI; ++i)
+#pragma unroll
+                    for (int j = 0; j < NJ; ++j)
+                        acc[i][j] = __builtin_amdgcn_mfma_f32_32x32x2f32(af[i], bf[j], acc[i][j], 0, 0, 0);
+            }
+        }
+        if (more) {
+            if constexpr (NBUF == 1) __syncthreads();
+            store(NBUF == 1 ? 0 : buf ^ 1);
         }
         __syncthreads();
+        if constexpr (NBUF == 2) buf ^= 1;
     }
     // epilogue: lane l, register v -> row 8*(v/4) + 4*(l/32) + v%4, col l%32
 #pragma unroll
-    for (int i = 0; i < 2; ++i)
+    for (int i = 0; i < MI; ++i)
 #pragma unroll
-        for (int j = 0; j < 2; ++j)
-#pragma unroll
-            for (int v = 0; v < 16; ++v) {
-                const int64_t row = tm + wm + i * 32 + 8 * (v >> 2) + 4 * (lane >> 5) + (v & 3);
-                const int64_t col = tn + wn + j * 32 + (lane & 31);
-                if (row < m && col < nc) {
-                    float *p = a + (r0 + row) * ld + c0 + col;
-                    *p = *p - acc[i][j][v];
-                }
-            }
-}
-
-// ------------------------------------------- binary16 operands, binary32 acc
-constexpr int BK16 = 32;
-__global__ __launch_bounds__(256) void k_gemm_f16(float *__restrict__ a, int64_t ld, int64_t r0,
-                                                  int64_t m, int64_t c0, int64_t nc, int64_t k,
-                                                  int64_t kk, int tiles_n, int nblk) {
-    constexpr int KP = BK16 + 8;            // row pitch in halves (16-byte aligned)
-    __shared__ __align__(16) _Float16 As[BM][KP];   // row-major: 8 consecutive k per lane
-    __shared__ __align__(16) _Float16 Bs[BN][KP];   // transposed: [col][k]
-    const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
-    const int bid = xcd_remap(blockIdx.x, nblk);
-    const int64_t tm = (int64_t)(bid / tiles_n) * BM, tn = (int64_t)(bid % tiles_n) * BN;
-    const int wm = (wv >> 1) * 64, wn = (wv & 1) * 64;
-
-    // A: 128 x 32 -> thread: row tid/2, 16 k's.  B: 32 x 128 -> thread: k tid/8, 16 cols
-    const int arow = tid >> 1, ak0 = (tid & 1) * 16;
-    const int bk = tid >> 3, bc0 = (tid & 7) * 16;
-    float ra[16], rb[16];
-    auto load = [&](int64_t kc) {
-        const int64_t gi = r0 + tm + arow;
-        const bool rok = (tm + arow) < m;
-#pragma unroll
-        for (int q = 0; q < 16; ++q) {
-            const int64_t kq = kc + ak0 + q;
-            ra[q] = (rok && kq < kk) ? a[gi * ld + k + kq] : 0.0f;
-        }
-        const int64_t kr = kc + bk;
-#pragma unroll
-        for (int q = 0; q < 16; ++q) {
-            const int64_t cj = tn + bc0 + q;
-            rb[q] = (kr < kk && cj < nc) ? a[(k + kr) * ld + c0 + cj] : 0.0f;
-        }
-    };
-    auto store = [&]() {
-#pragma unroll
-        for (int q = 0; q < 16; ++q) As[arow][ak0 + q] = (_Float16)ra[q];
-#pragma unroll
-        for (int q = 0; q < 16; ++q) Bs[bc0 + q][bk] = (_Float16)rb[q];
-    };
-
-    floatx16 acc[2][2];
-#pragma unroll
-    for (int i = 0; i < 2; ++i)
-#pragma unroll
-        for (int j = 0; j < 2; ++j) acc[i][j] = floatx16{0};
-
-    load(0);
-    for (int64_t kc = 0; kc < kk; kc += BK16) {
-        store();
-        __syncthreads();
-        if (kc + BK16 < kk) load(kc + BK16);
-#pragma unroll
-        for (int s = 0; s < BK16; s += 16) {
-            const int kb = s + 8 * (lane >> 5);
-            half8 af[2], bf[2];
-#pragma unroll
-            for (int i = 0; i < 2; ++i) af[i] = *reinterpret_cast<const half8 *>(&As[wm + i * 32 + (lane & 31)][kb]);
-#pragma unroll
-            for (int j = 0; j < 2; ++j) bf[j] = *reinterpret_cast<const half8 *>(&Bs[wn + j * 32 + (lane & 31)][kb]);
-#pragma unroll
-            for (int i = 0; i < 2; ++i)
-#pragma unroll
-                for (int j = 0; j < 2; ++j)
-                    acc[i][j] = __builtin_amdgcn_mfma_f32_32x32x16_f16(af[i], bf[j], acc[i][j], 0, 0, 0);
-        }
-        __syncthreads();
-    }
-#pragma unroll
-    for (int i = 0; i < 2; ++i)
-#pragma unroll
-        for (int j = 0; j < 2; ++j)
+        for (int j = 0; j < NJ; ++j)
 #pragma unroll
             for (int v = 0; v < 16; ++v) {
                 const int64_t row = tm + wm + i * 32 + 8 * (v >> 2) + 4 * (lane >> 5) + (v & 3);
@@ -206,73 +206,98 @@ __global__ __launch_bounds__(256) void k_gemm_f16(float *__restrict__ a, int64_t
 }
 
 // ---------------------------------------------------------------- binary64
-constexpr int BK64 = 8;
+// Workgroup tile BM x BN, K-chunk BK, two LDS buffers, four waves in a 2 x 2
+// grid, each wave (BM/2) x (BN/2) of C in 16 x 16 MFMA blocks.  A: TPR =
+// 256/BM threads per row, each BK/TPR consecutive k; B: TPK = 256/BK threads
+// per k-row, each BN/TPK consecutive columns.
+template <bool VEC, int BM, int BN, int BK>
 __global__ __launch_bounds__(256) void k_gemm_f64(double *__restrict__ a, int64_t ld, int64_t r0,
                                                   int64_t m, int64_t c0, int64_t nc, int64_t k,
                                                   int64_t kk, int tiles_n, int nblk) {
-    __shared__ double As[BK64][BM + 2];
-    __shared__ double Bs[BK64][BN + 2];
+    constexpr int TPR = 256 / BM, AK = BK / TPR;
+    constexpr int TPK = 256 / BK, BCOL = BN / TPK;
+    constexpr int MI = BM / 32, NJ = BN / 32;
+    static_assert(TPR * BM == 256 && TPK * BK == 256 && AK % 2 == 0 && BCOL % 2 == 0, "split");
+    __shared__ __align__(16) double As[2][BK][BM + 2];
+    __shared__ __align__(16) double Bs[2][BK][BN + 2];
     const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
     const int bid = xcd_remap(blockIdx.x, nblk);
     const int64_t tm = (int64_t)(bid / tiles_n) * BM, tn = (int64_t)(bid % tiles_n) * BN;
-    const int wm = (wv >> 1) * 64, wn = (wv & 1) * 64;
-    // A: 128 x 8 -> thread: row tid/2, 4 k's.  B: 8 x 128 -> thread: k tid/32, 4 cols
-    const int arow = tid >> 1, ak0 = (tid & 1) * 4;
-    const int bk = tid >> 5, bc0 = (tid & 31) * 4;
-    double ra[4], rb[4];
+    const int wm = (wv >> 1) * (BM / 2), wn = (wv & 1) * (BN / 2);
+    const int arow = tid / TPR, ak0 = (tid % TPR) * AK;
+    const int bk = tid / TPK, bc0 = (tid % TPK) * BCOL;
+    const bool aok = tm + arow < m;
+    const double *ap = a + (r0 + tm + arow) * ld + k + ak0;
+    const double *bp = a + k * ld + c0 + tn + bc0;
+    const int64_t bcol_lim = nc - (tn + bc0);
+    double ra[AK], rb[BCOL];
     auto load = [&](int64_t kc) {
-        const int64_t gi = r0 + tm + arow;
-        const bool rok = (tm + arow) < m;
+        if (VEC && aok && kc + ak0 + AK <= kk) {
 #pragma unroll
-        for (int q = 0; q < 4; ++q) {
-            const int64_t kq = kc + ak0 + q;
-            ra[q] = (rok && kq < kk) ? a[gi * ld + k + kq] : 0.0;
+            for (int q = 0; q < AK; q += 2) {
+                const double2 v = *reinterpret_cast<const double2 *>(ap + kc + q);
+                ra[q] = v.x; ra[q + 1] = v.y;
+            }
+        } else {
+#pragma unroll
+            for (int q = 0; q < AK; ++q) ra[q] = (aok && kc + ak0 + q < kk) ? ap[kc + q] : 0.0;
         }
         const int64_t kr = kc + bk;
+        const bool kok = kr < kk;
+        if (VEC && kok && bcol_lim >= BCOL) {
 #pragma unroll
-        for (int q = 0; q < 4; ++q) {
-            const int64_t cj = tn + bc0 + q;
-            rb[q] = (kr < kk && cj < nc) ? a[(k + kr) * ld + c0 + cj] : 0.0;
+            for (int q = 0; q < BCOL; q += 2) {
+                const double2 v = *reinterpret_cast<const double2 *>(bp + kr * ld + q);
+                rb[q] = v.x; rb[q + 1] = v.y;
+            }
+        } else {
+#pragma unroll
+            for (int q = 0; q < BCOL; ++q) rb[q] = (kok && q < bcol_lim) ? bp[kr * ld + q] : 0.0;
         }
     };
-    auto store = [&]() {
+    auto store = [&](int buf) {
 #pragma unroll
-        for (int q = 0; q < 4; ++q) As[ak0 + q][arow] = ra[q];
+        for (int q = 0; q < AK; ++q) As[buf][ak0 + q][arow] = ra[q];
 #pragma unroll
-        for (int q = 0; q < 4; ++q) Bs[bk][bc0 + q] = rb[q];
+        for (int q = 0; q < BCOL; q += 2)
+            *reinterpret_cast<double2 *>(&Bs[buf][bk][bc0 + q]) = make_double2(rb[q], rb[q + 1]);
     };
-    doublex4 acc[4][4];
+    doublex4 acc[MI][NJ];
 #pragma unroll
-    for (int i = 0; i < 4; ++i)
+    for (int i = 0; i < MI; ++i)
 #pragma unroll
-        for (int j = 0; j < 4; ++j) acc[i][j] = doublex4{0};
+        for (int j = 0; j < NJ; ++j) acc[i][j] = doublex4{0};
     load(0);
-    for (int64_t kc = 0; kc < kk; kc += BK64) {
-        store();
-        __syncthreads();
-        if (kc + BK64 < kk) load(kc + BK64);
+    store(0);
+    __syncthreads();
+    int buf = 0;
+    for (int64_t kc = 0; kc < kk; kc += BK) {
+        const bool more = kc + BK < kk;
+        if (more) load(kc + BK);
 #pragma unroll
-        for (int s = 0; s < BK64; s += 4) {
+        for (int s = 0; s < BK; s += 4) {
             const int kr = s + (lane >> 4);
-            double af[4], bf[4];
+            double af[MI], bf[NJ];
 #pragma unroll
-            for (int i = 0; i < 4; ++i) af[i] = As[kr][wm + i * 16 + (lane & 15)];
+            for (int i = 0; i < MI; ++i) af[i] = As[buf][kr][wm + i * 16 + (lane & 15)];
 #pragma unroll
-            for (int j = 0; j < 4; ++j) bf[j] = Bs[kr][wn + j * 16 + (lane & 15)];
+            for (int j = 0; j < NJ; ++j) bf[j] = Bs[buf][kr][wn + j * 16 + (lane & 15)];
 #pragma unroll
-            for (int i = 0; i < 4; ++i)
+            for (int i = 0; i < MI; ++i)
 #pragma unroll
-                for (int j = 0; j < 4; ++j)
+                for (int j = 0; j < NJ; ++j)
                     acc[i][j] = __builtin_amdgcn_mfma_f64_16x16x4f64(af[i], bf[j], acc[i][j], 0, 0, 0);
         }
+        if (more) store(buf ^ 1);
         __syncthreads();
+        buf ^= 1;
     }
     // v_mfma_f64_16x16x4f64 output: lane l, register v -> row (l/16) + 4*v,
     // col l%16 (rows interleaved, unlike the binary32 16x16 layout)
 #pragma unroll
-    for (int i = 0; i < 4; ++i)
+    for (int i = 0; i < MI; ++i)
 #pragma unroll
-        for (int j = 0; j < 4; ++j)
+        for (int j = 0; j < NJ; ++j)
 #pragma unroll
             for (int v = 0; v < 4; ++v) {
                 const int64_t row = tm + wm + i * 16 + (lane >> 4) + 4 * v;
@@ -284,21 +309,43 @@ __global__ __launch_bounds__(256) void k_gemm_f64(double *__restrict__ a, int64_
             }
 }
 
+// Tile configuration of the binary32 / binary16 kernels (chosen by timing
+// the trailing update on MI355X).
+template <bool HALF> struct Cfg32;
+template <> struct Cfg32<false> { static constexpr int BM = 64, BN = 64, BK = 16, NBUF = 2; };
+template <> struct Cfg32<true> { static constexpr int BM = 128, BN = 64, BK = 32, NBUF = 2; };
+struct Cfg64 { static constexpr int BM = 64, BN = 64, BK = 16; };
+
+template <bool HALF>
+void go32(bool vec, float *a, int64_t ld, int64_t r0, int64_t m, int64_t c0, int64_t nc, int64_t k,
+          int64_t kk, hipStream_t s) {
+    using C = Cfg32<HALF>;
+    const int64_t tiles_m = (m + C::BM - 1) / C::BM, tiles_n = (nc + C::BN - 1) / C::BN;
+    const int64_t nblk = tiles_m * tiles_n;
+    if (vec) k_gemm_32<HALF, true, C::BM, C::BN, C::BK, C::NBUF><<<(unsigned)nblk, 256, 0, s>>>(a, ld, r0, m, c0, nc, k, kk, (int)tiles_n, (int)nblk);
+    else k_gemm_32<HALF, false, C::BM, C::BN, C::BK, C::NBUF><<<(unsigned)nblk, 256, 0, s>>>(a, ld, r0, m, c0, nc, k, kk, (int)tiles_n, (int)nblk);
+}
+
 }  // namespace
 
 hipError_t launch_gemm_update(int mode, void *a, int64_t ld, int64_t r0, int64_t m, int64_t c0,
                               int64_t nc, int64_t k, int64_t kk, hipStream_t s) {
     if (m <= 0 || nc <= 0 || kk <= 0) return hipSuccess;
-    const int64_t tiles_m = (m + BM - 1) / BM, tiles_n = (nc + BN - 1) / BN;
-    const int64_t nblk = tiles_m * tiles_n;
-    if (nblk > 0x7fffffff) return hipErrorInvalidValue;
-    dim3 grid((unsigned)nblk), block(256);
-    if (mode == LU_F64)
-        k_gemm_f64<<<grid, block, 0, s>>>((double *)a, ld, r0, m, c0, nc, k, kk, (int)tiles_n, (int)nblk);
-    else if (mode == LU_F32)
-        k_gemm_f32<16><<<grid, block, 0, s>>>((float *)a, ld, r0, m, c0, nc, k, kk, (int)tiles_n, (int)nblk);
-    else
-        k_gemm_f16<<<grid, block, 0, s>>>((float *)a, ld, r0, m, c0, nc, k, kk, (int)tiles_n, (int)nblk);
+    if ((m / 64 + 1) * (nc / 64 + 1) > 0x7fffffffll) return hipErrorInvalidValue;
+    // 16-byte vector loads need every row start and offset 16-byte aligned
+    const uintptr_t base = (uintptr_t)a;
+    if (mode == LU_F64) {
+        const bool vec = (ld % 2 == 0) && (k % 2 == 0) && (c0 % 2 == 0) && (base % 16 == 0);
+        using C = Cfg64;
+        const int64_t tiles_m = (m + C::BM - 1) / C::BM, tiles_n = (nc + C::BN - 1) / C::BN;
+        const int64_t nblk = tiles_m * tiles_n;
+        if (vec) k_gemm_f64<true, C::BM, C::BN, C::BK><<<(unsigned)nblk, 256, 0, s>>>((double *)a, ld, r0, m, c0, nc, k, kk, (int)tiles_n, (int)nblk);
+        else k_gemm_f64<false, C::BM, C::BN, C::BK><<<(unsigned)nblk, 256, 0, s>>>((double *)a, ld, r0, m, c0, nc, k, kk, (int)tiles_n, (int)nblk);
+        return hipGetLastError();
+    }
+    const bool vec = (ld % 4 == 0) && (k % 4 == 0) && (c0 % 4 == 0) && (base % 16 == 0);
+    if (mode == LU_F32) go32<false>(vec, (float *)a, ld, r0, m, c0, nc, k, kk, s);
+    else go32<true>(vec, (float *)a, ld, r0, m, c0, nc, k, kk, s);
     return hipGetLastError();
 }
 

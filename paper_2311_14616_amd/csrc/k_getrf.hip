@@ -14,93 +14,117 @@
 namespace mpir {
 
 constexpr int kLeafMaxW = 32;     // columns per leaf
-constexpr int kLeafMaxG = 256;    // workgroups per leaf (one per CU)
+constexpr int kLeafT = 1024;      // threads per leaf workgroup = rows it owns
+constexpr int kLeafMaxG = 64;     // workgroups per leaf (one wave reads all slots)
 
-// Per-column exchange area of the cooperative leaf: every workgroup posts
-// its local pivot candidate (|value|, row, and the candidate row), the owner
-// of the diagonal row posts that row; double-buffered by column parity.
+// Exchange area of the cooperative leaf.  Every value travels in 64-bit
+// words (32-bit payload | 32-bit epoch), so a reader that sees the current
+// epoch in a word also sees its payload: no separate barrier, no fences.
+// Per column parity and workgroup: a header (|value| in 1-2 words, row
+// index) and the candidate row (1-2 words per column); plus the old
+// diagonal row posted by its owner.
+constexpr int kHeadWords = 4;
+constexpr int kRowWords = 2 * kLeafMaxW;
 struct LeafSlot {
-    double val;
-    int32_t idx;
-    int32_t pad;
-    double row[kLeafMaxW];
+    uint64_t head[kHeadWords];
+    uint64_t row[kRowWords];
 };
 struct PanelSync {
-    uint32_t counter;             // monotonic arrival counter (grid barrier)
-    uint32_t pad0[31];
-    uint32_t base;                // host-maintained copy (unused on device)
-    uint32_t pad1[31];
     LeafSlot slot[2][kLeafMaxG];
-    double diag[2][kLeafMaxW];
+    uint64_t diag[2][kRowWords];
 };
 
 size_t panel_sync_bytes() { return sizeof(PanelSync); }
 
 hipError_t panel_sync_reset(PanelSync *ps, hipStream_t s) {
-    return hipMemsetAsync(ps, 0, 256, s);
+    return hipMemsetAsync(ps, 0, sizeof(PanelSync), s);
 }
 
 namespace {
 
-template <typename T>
-__device__ __forceinline__ T ld_agent(const T *p) {
+__device__ __forceinline__ void put_word(uint64_t *p, uint32_t payload, uint32_t epoch) {
+    __hip_atomic_store(p, ((uint64_t)epoch << 32) | payload, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+__device__ __forceinline__ uint64_t get_word(const uint64_t *p) {
     return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
 }
-template <typename T>
-__device__ __forceinline__ void st_agent(T *p, T v) {
-    __hip_atomic_store(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-}
+__device__ __forceinline__ bool word_ok(uint64_t w, uint32_t epoch) { return (uint32_t)(w >> 32) == epoch; }
+
+// Values of type W split into 32-bit payloads (1 for float, 2 for double).
+template <typename W> struct Words;
+template <> struct Words<float> {
+    static constexpr int K = 1;
+    __device__ static uint32_t part(float v, int) { return __float_as_uint(v); }
+    __device__ static float join(const uint32_t *p) { return __uint_as_float(p[0]); }
+};
+template <> struct Words<double> {
+    static constexpr int K = 2;
+    __device__ static uint32_t part(double v, int q) {
+        const uint64_t b = (uint64_t)__double_as_longlong(v);
+        return q == 0 ? (uint32_t)b : (uint32_t)(b >> 32);
+    }
+    __device__ static double join(const uint32_t *p) {
+        return __longlong_as_double((long long)(((uint64_t)p[1] << 32) | p[0]));
+    }
+};
 
 __device__ __forceinline__ bool better(double v, int i, double bv, int bi) {
     return v > bv || (v == bv && i < bi);
 }
 
 // Leaf factorization of rows [k0, n) x columns [k0, k0+w) of the working
-// array.  Workgroup g owns relative rows [g*R, g*R+R) in LDS.  For every
-// column: local argmax (first maximum), exchange through PanelSync with one
-// grid barrier, swap, scale, rank-1 update of the remaining leaf columns.
+// array.  Workgroup g owns relative rows [g*1024, g*1024+1024), one row per
+// thread, the w leaf entries of the row in registers.  For every column:
+// local argmax (first maximum), candidate posted as epoch-tagged words,
+// winner chosen identically by every workgroup, swap, scale, rank-1 update.
 // F16: the pivot row is rounded to binary16 when it becomes the pivot row,
 // each multiplier to binary16 when formed (products of binary16 numbers are
 // exact in binary32).
-template <typename W, bool F16, int RMAX>
-__global__ __launch_bounds__(256) void k_leaf(W *__restrict__ a, int64_t n, int64_t ld,
-                                              int64_t k0, int w, int R, int G,
-                                              int32_t *__restrict__ ipiv, int64_t *info,
-                                              PanelSync *ps, uint32_t base, uint32_t *flags) {
-    constexpr int LDW = kLeafMaxW + 1;
-    __shared__ W blk[RMAX * LDW];
-    __shared__ double red_v[4];
-    __shared__ int red_i[4];
-    __shared__ double prow[kLeafMaxW];
-    __shared__ double orow[kLeafMaxW];
-    __shared__ int s_p, s_win, s_bad;
+template <typename W, bool F16>
+__global__ __launch_bounds__(kLeafT) void k_leaf(W *__restrict__ a, int64_t n, int64_t ld,
+                                                 int64_t k0, int w, int G,
+                                                 int32_t *__restrict__ ipiv, int64_t *info,
+                                                 PanelSync *ps, uint32_t base, uint32_t *flags) {
+    using Wd = Words<W>;
+    constexpr int K = Wd::K;
+    __shared__ double red_v[kLeafT / 64];
+    __shared__ int red_i[kLeafT / 64];
+    __shared__ W crow[kLeafMaxW];      // this workgroup's candidate row
+    __shared__ W jrow[kLeafMaxW];      // row j (if owned here)
+    __shared__ W prow[kLeafMaxW];      // pivot row
+    __shared__ W orow[kLeafMaxW];      // old row j
+    __shared__ double s_bv;
+    __shared__ int s_bi, s_p, s_bad;
 
     const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
     const int64_t m = n - k0;
-    const int64_t r0 = (int64_t)blockIdx.x * R;
-    const int rows = (int)((m - r0) < R ? (m - r0) : R);
-    // an earlier launch already timed out: the arrival counter is behind,
-    // so every workgroup returns at once (the host reports the error)
+    const int64_t r0 = (int64_t)blockIdx.x * kLeafT;
+    const int rows = (int)((m - r0) < kLeafT ? (m - r0) : kLeafT);
+    // an earlier launch already timed out: every workgroup returns at once
     if (__hip_atomic_load(flags, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) & DF_TIMEOUT) return;
     if (tid == 0) s_bad = 0;
-
-    for (int e = tid; e < rows * w; e += 256) {
-        const int r = e / w, c = e - r * w;
-        blk[r * LDW + c] = a[(k0 + r0 + r) * ld + k0 + c];
-    }
+    if (tid < kLeafMaxW) { prow[tid] = (W)0; orow[tid] = (W)0; crow[tid] = (W)0; jrow[tid] = (W)0; }
     __syncthreads();
+    const bool mine = tid < rows;
+    const int64_t rr = r0 + tid;               // relative row of this thread
+    W v[kLeafMaxW];
+#pragma unroll
+    for (int c = 0; c < kLeafMaxW; ++c) v[c] = (W)0;
+    if (mine) {
+        const W *src = a + (k0 + rr) * ld + k0;
+#pragma unroll
+        for (int c = 0; c < kLeafMaxW; ++c)
+            if (c < w) v[c] = src[c];
+    }
 
-    for (int j = 0; j < w; ++j) {
+#pragma unroll
+    for (int j = 0; j < kLeafMaxW; ++j) {
+        if (j >= w) break;
+        const uint32_t epoch = base + (uint32_t)j + 1u;
         const int par = j & 1;
         // ---- local argmax of |a_rj| over owned rows r >= j ----
-        double bv = -1.0;
-        int bi = INT_MAX;
-        for (int r = tid; r < rows; r += 256) {
-            const int64_t rr = r0 + r;
-            if (rr < j) continue;
-            const double v = fabs((double)blk[r * LDW + j]);
-            if (v > bv) { bv = v; bi = (int)rr; }
-        }
+        double bv = (mine && rr >= j) ? fabs((double)v[j]) : -1.0;
+        int bi = (mine && rr >= j) ? (int)rr : INT_MAX;
         for (int off = 32; off > 0; off >>= 1) {
             const double ov = __shfl_xor(bv, off);
             const int oi = __shfl_xor(bi, off);
@@ -108,110 +132,144 @@ __global__ __launch_bounds__(256) void k_leaf(W *__restrict__ a, int64_t n, int6
         }
         if (lane == 0) { red_v[wv] = bv; red_i[wv] = bi; }
         __syncthreads();
-        if (tid == 0) {
-            for (int q = 1; q < 4; ++q)
-                if (better(red_v[q], red_i[q], red_v[0], red_i[0])) { red_v[0] = red_v[q]; red_i[0] = red_i[q]; }
+        if (wv == 0) {
+            bv = lane < kLeafT / 64 ? red_v[lane] : -1.0;
+            bi = lane < kLeafT / 64 ? red_i[lane] : INT_MAX;
+            for (int off = 8; off > 0; off >>= 1) {
+                const double ov = __shfl_xor(bv, off);
+                const int oi = __shfl_xor(bi, off);
+                if (better(ov, oi, bv, bi)) { bv = ov; bi = oi; }
+            }
+            if (lane == 0) { s_bv = bv; s_bi = bi; }
         }
         __syncthreads();
-        const double lbv = red_v[0];
-        const int lbi = red_i[0];
+        if (mine && rr == s_bi) {
+#pragma unroll
+            for (int c = 0; c < kLeafMaxW; ++c) crow[c] = v[c];
+        }
+        if (mine && rr == j) {
+#pragma unroll
+            for (int c = 0; c < kLeafMaxW; ++c) jrow[c] = v[c];
+        }
+        __syncthreads();
 
         if (G == 1) {
-            if (tid < w) {
-                prow[tid] = (double)blk[(lbi - r0) * LDW + tid];
-                orow[tid] = (double)blk[(j - r0) * LDW + tid];
-            }
-            if (tid == 0) s_p = lbi;
-            __syncthreads();
-        } else {
-            // ---- post candidate, diagonal row; grid barrier; pick winner ----
+            if (tid < kLeafMaxW) { prow[tid] = crow[tid]; orow[tid] = jrow[tid]; }
+            if (tid == 0) s_p = s_bi;
+        } else if (wv == 0) {
+            // ---- post this workgroup's candidate and (if owned) row j ----
             LeafSlot *my = &ps->slot[par][blockIdx.x];
-            if (tid < w) {
-                const bool has = lbi != INT_MAX;
-                st_agent(&my->row[tid], has ? (double)blk[(lbi - r0) * LDW + tid] : 0.0);
-                if (j >= r0 && j < r0 + rows) st_agent(&ps->diag[par][tid], (double)blk[(j - r0) * LDW + tid]);
+            const bool own_j = j >= r0 && j < r0 + rows;
+            if (lane < w) {
+#pragma unroll
+                for (int q = 0; q < K; ++q) {
+                    put_word(&my->row[lane * K + q], Wd::part(crow[lane], q), epoch);
+                    if (own_j) put_word(&ps->diag[par][lane * K + q], Wd::part(jrow[lane], q), epoch);
+                }
             }
-            if (tid == 0) {
-                st_agent(&my->val, lbv);
-                st_agent(&my->idx, (int32_t)lbi);
+            if (lane == 32) {
+                const uint64_t b = (uint64_t)__double_as_longlong(s_bv);
+                put_word(&my->head[0], (uint32_t)b, epoch);
+                put_word(&my->head[1], (uint32_t)(b >> 32), epoch);
+                put_word(&my->head[2], (uint32_t)s_bi, epoch);
             }
-            __syncthreads();
-            if (tid == 0) {
-                __hip_atomic_fetch_add(&ps->counter, 1u, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
-                const uint32_t target = base + (uint32_t)(j + 1) * (uint32_t)G;
+            // ---- read every workgroup's header (lane g <-> workgroup g) ----
+            double gv = -1.0;
+            int gi = INT_MAX, gw = 0;
+            {
+                uint64_t h0 = 0, h1 = 0, h2 = 0;
+                bool ok = lane >= G;
                 uint64_t spins = 0;
-                while (__hip_atomic_load(&ps->counter, __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_AGENT) < target) {
-                    if (++spins > kSpinLimit) { s_bad = 1; break; }
+                for (;;) {
+                    if (!ok) {
+                        const LeafSlot *sl = &ps->slot[par][lane];
+                        h0 = get_word(&sl->head[0]);
+                        h1 = get_word(&sl->head[1]);
+                        h2 = get_word(&sl->head[2]);
+                        ok = word_ok(h0, epoch) && word_ok(h1, epoch) && word_ok(h2, epoch);
+                    }
+                    if (__all(ok)) break;
+                    if (++spins > kSpinLimit) { if (lane == 0) s_bad = 1; break; }
                     __builtin_amdgcn_s_sleep(1);
                 }
-            }
-            __syncthreads();
-            if (wv == 0) {
-                double gv = -1.0;
-                int gi = INT_MAX, gw = 0;
-                for (int g = lane; g < G; g += 64) {
-                    const double v = ld_agent(&ps->slot[par][g].val);
-                    const int i = ld_agent(&ps->slot[par][g].idx);
-                    if (better(v, i, gv, gi)) { gv = v; gi = i; gw = g; }
+                if (lane < G && ok) {
+                    gv = __longlong_as_double((long long)((h1 << 32) | (uint32_t)h0));
+                    gi = (int)(uint32_t)h2;
+                    gw = lane;
                 }
-                for (int off = 32; off > 0; off >>= 1) {
-                    const double ov = __shfl_xor(gv, off);
-                    const int oi = __shfl_xor(gi, off);
-                    const int og = __shfl_xor(gw, off);
-                    if (better(ov, oi, gv, gi)) { gv = ov; gi = oi; gw = og; }
+            }
+            for (int off = 32; off > 0; off >>= 1) {
+                const double ov = __shfl_xor(gv, off);
+                const int oi = __shfl_xor(gi, off);
+                const int og = __shfl_xor(gw, off);
+                if (better(ov, oi, gv, gi)) { gv = ov; gi = oi; gw = og; }
+            }
+            // ---- winner's row and the old row j ----
+            {
+                uint32_t pw[K], ow[K];
+                bool ok = lane >= w;
+                uint64_t spins = 0;
+                for (;;) {
+                    if (!ok) {
+                        ok = true;
+#pragma unroll
+                        for (int q = 0; q < K; ++q) {
+                            const uint64_t x = get_word(&ps->slot[par][gw].row[lane * K + q]);
+                            const uint64_t y = get_word(&ps->diag[par][lane * K + q]);
+                            ok = ok && word_ok(x, epoch) && word_ok(y, epoch);
+                            pw[q] = (uint32_t)x;
+                            ow[q] = (uint32_t)y;
+                        }
+                    }
+                    if (__all(ok)) break;
+                    if (++spins > kSpinLimit) { if (lane == 0) s_bad = 1; break; }
+                    __builtin_amdgcn_s_sleep(1);
                 }
-                if (lane == 0) { s_p = gi; s_win = gw; }
+                if (lane < w) { prow[lane] = Wd::join(pw); orow[lane] = Wd::join(ow); }
             }
-            __syncthreads();
-            if (tid < w) {
-                prow[tid] = ld_agent(&ps->slot[par][s_win].row[tid]);
-                orow[tid] = ld_agent(&ps->diag[par][tid]);
-            }
-            __syncthreads();
+            if (lane == 0) s_p = gi;
         }
-
+        __syncthreads();
         const int p = s_p;
-        if (s_bad || p == INT_MAX) {   // expired wait: leave the loop, report
+        if (s_bad || p == INT_MAX) {
             if (tid == 0) atomicOr(flags, (uint32_t)DF_TIMEOUT);
             break;
         }
-        if (tid < w) {
-            double v = prow[tid];
-            if (F16 && tid >= j) v = (double)round_f16((float)v);
-            prow[tid] = v;
-        }
+        if (F16 && tid < kLeafMaxW && tid >= j) prow[tid] = (W)round_f16((float)prow[tid]);
         __syncthreads();
-        // ---- swap rows j and p inside the leaf ----
-        if (p != j) {
-            if (p >= r0 && p < r0 + rows && tid < w) blk[(p - r0) * LDW + tid] = (W)orow[tid];
+        // ---- swap rows j and p, record the pivot ----
+        if (mine && p != j && rr == p) {
+#pragma unroll
+            for (int c = 0; c < kLeafMaxW; ++c) v[c] = orow[c];
         }
-        if (j >= r0 && j < r0 + rows && tid < w) blk[(j - r0) * LDW + tid] = (W)prow[tid];
+        if (mine && rr == j) {
+#pragma unroll
+            for (int c = 0; c < kLeafMaxW; ++c) v[c] = prow[c];
+        }
         if (blockIdx.x == 0 && tid == 0) {
             ipiv[k0 + j] = (int32_t)(k0 + p);
-            if (prow[j] == 0.0 && *info == 0) *info = k0 + j + 1;
+            if (prow[j] == (W)0 && *info == 0) *info = k0 + j + 1;
         }
-        __syncthreads();
-        // ---- scale and rank-1 update of the owned rows below the pivot ----
-        const W piv = (W)prow[j];
-        if (piv != (W)0) {
-            for (int r = tid; r < rows; r += 256) {
-                const int64_t rr = r0 + r;
-                if (rr <= j) continue;
-                W l = blk[r * LDW + j] / piv;
-                if (F16) l = (W)round_f16((float)l);
-                blk[r * LDW + j] = l;
-                for (int c = j + 1; c < w; ++c) {
-                    const W prod = l * (W)prow[c];
-                    blk[r * LDW + c] = blk[r * LDW + c] - prod;
-                }
+        // ---- scale and rank-1 update of the rows below the pivot ----
+        const W piv = prow[j];
+        if (mine && rr > j && piv != (W)0) {
+            W l = v[j] / piv;
+            if (F16) l = (W)round_f16((float)l);
+            v[j] = l;
+#pragma unroll
+            for (int c = j + 1; c < kLeafMaxW; ++c) {
+                const W prod = l * prow[c];
+                v[c] = v[c] - prod;
             }
         }
-        __syncthreads();
+        // prow/orow/crow are rewritten only after the next column's first
+        // __syncthreads, which every thread reaches after this point.
     }
-
-    for (int e = tid; e < rows * w; e += 256) {
-        const int r = e / w, c = e - r * w;
-        a[(k0 + r0 + r) * ld + k0 + c] = blk[r * LDW + c];
+    if (mine) {
+        W *dst = a + (k0 + rr) * ld + k0;
+#pragma unroll
+        for (int c = 0; c < kLeafMaxW; ++c)
+            if (c < w) dst[c] = v[c];
     }
 }
 
@@ -339,37 +397,32 @@ int num_cus() {
     return g_num_cus;
 }
 
-constexpr int kLeafRowsF = 1024;   // rows per workgroup held in LDS (binary32)
-constexpr int kLeafRowsD = 512;    // (binary64)
-
-template <typename W, bool F16, int RMAX>
+template <typename W, bool F16>
 hipError_t leaf_go(W *a, int64_t n, int64_t ld, int64_t k0, int w, int32_t *ipiv, int64_t *info,
                    PanelSync *ps, uint32_t *host_base, uint32_t *flags, hipStream_t s) {
     const int64_t m = n - k0;
-    int64_t G64 = (m + RMAX - 1) / RMAX;
-    const int gmax = num_cus() < kLeafMaxG ? num_cus() : kLeafMaxG;
-    if (G64 > gmax) return hipErrorInvalidValue;
-    // fewer rows per workgroup than RMAX when that keeps G unchanged
+    const int64_t G64 = (m + kLeafT - 1) / kLeafT;
+    if (G64 > kLeafMaxG) return hipErrorInvalidValue;
     const int G = (int)G64;
-    const int R = (int)((m + G - 1) / G);
     uint32_t base = *host_base;
     if (G == 1) {
-        k_leaf<W, F16, RMAX><<<1, 256, 0, s>>>(a, n, ld, k0, w, R, G, ipiv, info, ps, base, flags);
+        k_leaf<W, F16><<<1, kLeafT, 0, s>>>(a, n, ld, k0, w, G, ipiv, info, ps, base, flags);
         return hipGetLastError();
     }
-    void *args[] = {&a, (void *)&n, (void *)&ld, (void *)&k0, (void *)&w, (void *)&R, (void *)&G,
+    void *args[] = {&a, (void *)&n, (void *)&ld, (void *)&k0, (void *)&w, (void *)&G,
                     &ipiv, &info, &ps, &base, &flags};
-    hipError_t e = hipLaunchCooperativeKernel((const void *)k_leaf<W, F16, RMAX>, dim3(G), dim3(256),
+    hipError_t e = hipLaunchCooperativeKernel((const void *)k_leaf<W, F16>, dim3(G), dim3(kLeafT),
                                               args, 0, s);
-    if (e == hipSuccess) *host_base = base + (uint32_t)G * (uint32_t)w;
+    if (e == hipSuccess) *host_base = base + (uint32_t)w;
     return e;
 }
 
 }  // namespace
 
 int leaf_max_rows(int mode) {
+    (void)mode;
     const int gmax = num_cus() < kLeafMaxG ? num_cus() : kLeafMaxG;
-    return gmax * (mode == LU_F64 ? kLeafRowsD : kLeafRowsF);
+    return gmax * kLeafT;
 }
 
 hipError_t launch_leaf(int mode, void *a, int64_t n, int64_t ld, int64_t k0, int w, int32_t *ipiv,
@@ -377,10 +430,10 @@ hipError_t launch_leaf(int mode, void *a, int64_t n, int64_t ld, int64_t k0, int
                        hipStream_t s) {
     if (w <= 0 || w > kLeafMaxW || k0 >= n) return hipErrorInvalidValue;
     if (mode == LU_F64)
-        return leaf_go<double, false, kLeafRowsD>((double *)a, n, ld, k0, w, ipiv, info, ps, host_base, flags, s);
+        return leaf_go<double, false>((double *)a, n, ld, k0, w, ipiv, info, ps, host_base, flags, s);
     if (mode == LU_F32)
-        return leaf_go<float, false, kLeafRowsF>((float *)a, n, ld, k0, w, ipiv, info, ps, host_base, flags, s);
-    return leaf_go<float, true, kLeafRowsF>((float *)a, n, ld, k0, w, ipiv, info, ps, host_base, flags, s);
+        return leaf_go<float, false>((float *)a, n, ld, k0, w, ipiv, info, ps, host_base, flags, s);
+    return leaf_go<float, true>((float *)a, n, ld, k0, w, ipiv, info, ps, host_base, flags, s);
 }
 
 hipError_t launch_laswp(int mode, void *a, int64_t n, int64_t ld, int64_t k0, int cnt,

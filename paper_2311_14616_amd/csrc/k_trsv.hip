@@ -47,33 +47,59 @@ __global__ __launch_bounds__(256) void k_trsv(const Ft *__restrict__ LU, int64_t
     const int rows = (int)((n - i0) < BS ? (n - i0) : BS);
 
     // ---- off-diagonal blocks, in the order they become final ----
+    // Poll `done` with relaxed coherent loads; one acquire fence once new
+    // blocks are seen.  All blocks already final are then streamed in groups
+    // of four (16 factor rows x 4 blocks of loads in flight per lane).
     Yt acc[16];
 #pragma unroll
     for (int r = 0; r < 16; ++r) acc[r] = (Yt)0;
-    uint32_t avail = 0;
     bool timed_out = false;
-    for (int q = 0; q < t; ++q) {
-        if (avail <= (uint32_t)q) {
+    int q = 0;
+    while (q < t) {
+        uint32_t avail = 0;
+        {
             uint64_t spins = 0;
             for (;;) {
                 uint32_t d = 0;
-                if (lane == 0) d = __hip_atomic_load(done, __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_AGENT);
-                d = __shfl(d, 0);
-                avail = d;
+                if (lane == 0) d = __hip_atomic_load(done, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+                avail = (uint32_t)__shfl((int)d, 0);
                 if (avail > (uint32_t)q) break;
                 if (++spins > kSpinLimit) { timed_out = true; break; }
                 __builtin_amdgcn_s_sleep(1);
             }
             if (timed_out) break;
+            __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
         }
-        const int cb = LOWER ? q : nblk - 1 - q;
-        const int64_t col = (int64_t)cb * BS + lane;
-        if (col < n) {
-            const Yt yv = ld_agent(&y[col]);
-            const Ft *base = LU + (i0 + wv * 16) * ld + col;
+        const int qend = (int)avail < t ? (int)avail : t;
+        for (; q + 4 <= qend; q += 4) {
+            Yt yv[4];
+            int64_t col[4];
 #pragma unroll
-            for (int r = 0; r < 16; ++r)
-                if (wv * 16 + r < rows) acc[r] += (Yt)to_d(base[(int64_t)r * ld]) * yv;
+            for (int u = 0; u < 4; ++u) {
+                const int cb = LOWER ? q + u : nblk - 1 - (q + u);
+                col[u] = (int64_t)cb * BS + lane;
+                yv[u] = col[u] < n ? ld_agent(&y[col[u]]) : (Yt)0;
+            }
+            const Ft *base = LU + (i0 + wv * 16) * ld;
+#pragma unroll
+            for (int r = 0; r < 16; ++r) {
+                if (wv * 16 + r < rows) {
+#pragma unroll
+                    for (int u = 0; u < 4; ++u)
+                        if (col[u] < n) acc[r] += (Yt)to_d(base[(int64_t)r * ld + col[u]]) * yv[u];
+                }
+            }
+        }
+        for (; q < qend; ++q) {
+            const int cb = LOWER ? q : nblk - 1 - q;
+            const int64_t col = (int64_t)cb * BS + lane;
+            if (col < n) {
+                const Yt yv = ld_agent(&y[col]);
+                const Ft *base = LU + (i0 + wv * 16) * ld + col;
+#pragma unroll
+                for (int r = 0; r < 16; ++r)
+                    if (wv * 16 + r < rows) acc[r] += (Yt)to_d(base[(int64_t)r * ld]) * yv;
+            }
         }
     }
 #pragma unroll

@@ -144,7 +144,11 @@ void free_handle(mpir_fact f) {
 mpir_status alloc_handle(mpir_fact f) {
     const int64_t n = f->n;
     const size_t wes = f->mode == LU_F64 ? 8 : 4;
-    f->ld = n;
+    // Row pitch of the working array: a multiple of 32 elements (aligned
+    // vector loads), never a multiple of 1024 (a power-of-two pitch would map
+    // every row of a column block onto the same HBM channels).
+    f->ld = (n + 31) / 32 * 32;
+    if (f->ld % 1024 == 0) f->ld += 32;
     if (dalloc(&f->work, (size_t)f->ld * n * wes) != hipSuccess) return MPIR_ERR_ALLOC;
     if (f->tf == MPIR_F16 && dalloc(&f->lu16, (size_t)n * n * 2) != hipSuccess) return MPIR_ERR_ALLOC;
     f->nchunks = residual_chunks(n);
@@ -159,8 +163,33 @@ mpir_status alloc_handle(mpir_fact f) {
     return MPIR_OK;
 }
 
-const int kNB = 256;   // panel width (columns per trailing update)
 const int kIB = 32;    // leaf width inside the panel
+
+// Panel width (columns per trailing update): a larger width raises the
+// arithmetic intensity of the trailing update (its C tile is read and written
+// once per panel), a smaller one shortens the panel.  MPIR_NB overrides the
+// per-precision default (a multiple of kIB).
+int panel_width(int mode) {
+    static int env = -1;
+    if (env < 0) {
+        const char *e = std::getenv("MPIR_NB");
+        env = e ? std::atoi(e) : 0;
+        if (env < 0 || env % kIB) env = 0;
+    }
+    if (env > 0) return env;
+    return mode == LU_F16 ? 512 : 512;
+}
+
+// Row interchanges of ipiv[k0 .. k0+cnt), in chunks the kernel accepts.
+hipError_t laswp_chunks(int mode, void *a, int64_t n, int64_t ld, int64_t k0, int cnt, const int32_t *ipiv,
+                        int64_t c0, int64_t c1, int64_t c2, int64_t c3, int32_t *perm, hipStream_t s) {
+    for (int off = 0; off < cnt; off += 256) {
+        const int c = cnt - off < 256 ? cnt - off : 256;
+        hipError_t e = launch_laswp(mode, a, n, ld, k0 + off, c, ipiv, c0, c1, c2, c3, perm, s);
+        if (e != hipSuccess) return e;
+    }
+    return hipSuccess;
+}
 
 // Blocked right-looking LU with partial pivoting on the working array.
 mpir_status getrf(mpir_fact f) {
@@ -168,9 +197,10 @@ mpir_status getrf(mpir_fact f) {
     const int mode = f->mode;
     void *a = f->work;
     hipStream_t s = f->stream;
+    const int nb = panel_width(mode);
     if (n > leaf_max_rows(mode)) return MPIR_ERR_ARG;
-    for (int64_t K = 0; K < n; K += kNB) {
-        const int w = (int)((n - K) < kNB ? (n - K) : kNB);
+    for (int64_t K = 0; K < n; K += nb) {
+        const int w = (int)((n - K) < nb ? (n - K) : nb);
         // ---- panel: columns [K, K+w) ----
         for (int64_t k = K; k < K + w; k += kIB) {
             const int wl = (int)((K + w - k) < kIB ? (K + w - k) : kIB);
@@ -188,7 +218,7 @@ mpir_status getrf(mpir_fact f) {
             }
         }
         // ---- interchanges outside the panel, permutation vector ----
-        HIPCHK(launch_laswp(mode, a, n, ld, K, w, f->ipiv, 0, K, K + w, n, f->perm, s));
+        HIPCHK(laswp_chunks(mode, a, n, ld, K, w, f->ipiv, 0, K, K + w, n, f->perm, s));
         if (K + w < n) {
             // ---- U12 = L11^{-1} A12 (blocked by kIB) ----
             for (int64_t k = K; k < K + w; k += kIB) {
@@ -229,7 +259,7 @@ mpir_status factor_impl(mpir_fact f, int64_t *info) {
     HIPCHK(hipGetLastError());
     {
         ProfScope ps_(4, (double)n * n * (esize(f->tw) + (f->mode == LU_F64 ? 8 : 4)), s);
-        HIPCHK(launch_downcast(n, f->A, f->lda, f->tw, f->tf, f->work, f->anorm_bits_d, f->flags_d, s));
+        HIPCHK(launch_downcast(n, f->A, f->lda, f->tw, f->tf, f->work, f->ld, f->anorm_bits_d, f->flags_d, s));
     }
     uint32_t flags = 0;
     HIPCHK(hipMemcpyAsync(&flags, f->flags_d, 4, hipMemcpyDeviceToHost, s));
@@ -238,7 +268,7 @@ mpir_status factor_impl(mpir_fact f, int64_t *info) {
     if (flags & DF_RANGE) return MPIR_ERR_RANGE;
     mpir_status st = getrf(f);
     if (st != MPIR_OK) return st;
-    if (f->tf == MPIR_F16) HIPCHK(launch_pack_half(n, (const float *)f->work, f->lu16, s));
+    if (f->tf == MPIR_F16) HIPCHK(launch_pack_half(n, (const float *)f->work, f->ld, f->lu16, s));
     uint64_t abits = 0;
     int64_t inf = 0;
     HIPCHK(hipMemcpyAsync(&abits, f->anorm_bits_d, 8, hipMemcpyDeviceToHost, s));
@@ -464,10 +494,10 @@ mpir_status mpir_downcast(int64_t n, const void *dA, int64_t lda, mpir_prec tw, 
     if (st == MPIR_OK) {
         hipMemsetAsync(bits, 0, 8, s);
         hipMemsetAsync(flags, 0, 4, s);
-        if (launch_downcast(n, dA, lda, tw, tf, tf == MPIR_F16 ? tmp : dAF, bits, flags, s) != hipSuccess)
+        if (launch_downcast(n, dA, lda, tw, tf, tf == MPIR_F16 ? tmp : dAF, n, bits, flags, s) != hipSuccess)
             st = MPIR_ERR_HIP;
         if (st == MPIR_OK && tf == MPIR_F16 &&
-            launch_pack_half(n, (const float *)tmp, (__half *)dAF, s) != hipSuccess)
+            launch_pack_half(n, (const float *)tmp, n, (__half *)dAF, s) != hipSuccess)
             st = MPIR_ERR_HIP;
         uint64_t hb = 0;
         uint32_t hf = 0;

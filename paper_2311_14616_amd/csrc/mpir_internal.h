@@ -108,10 +108,10 @@ __device__ __forceinline__ void atomic_max_nonneg(uint64_t *p, double v) {
 // a1: A_F = I_W^F(A) into a row-major working array (float for TF in
 // {F32, F16}; double for F64), ||A||_inf bits and status flags.
 hipError_t launch_downcast(int64_t n, const void *A, int64_t lda, int tw, int tf,
-                           void *AF, uint64_t *anorm_bits, uint32_t *flags,
+                           void *AF, int64_t ldf, uint64_t *anorm_bits, uint32_t *flags,
                            hipStream_t s);
-// Working array -> packed TF factors (F16 only: float -> binary16).
-hipError_t launch_pack_half(int64_t n, const float *AF, __half *LU, hipStream_t s);
+// Working array (row pitch ldf) -> packed n x n TF factors (F16: binary16).
+hipError_t launch_pack_half(int64_t n, const float *AF, int64_t ldf, __half *LU, hipStream_t s);
 // Working array -> TF storage with the given row-major layout (copy).
 hipError_t launch_copy_factors(int64_t n, const void *src, int tf, void *dst, hipStream_t s);
 
