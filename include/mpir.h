@@ -159,11 +159,14 @@ mpir_status mpir_residual(int64_t n, const void *dA, int64_t lda, mpir_prec tw,
                           mpir_prec tr, const void *db, const void *dx, void *dr,
                           double *rnorm, void *hip_stream);
 
-/* Per-kernel timing with HIP events recorded around each launch on the
- * library's stream.  kind: 0 = trailing-update GEMM, 1 = panel factor,
- * 2 = triangular solves, 3 = residual GEMV, 4 = downcast.  mpir_prof_get
- * returns the summed duration, the launch count and the summed algorithmic
- * work (flops for kinds 0-2, bytes for 3-4) since the last reset. */
+/* Per-kernel timing with HIP events recorded around each launch, on the
+ * stream that launch uses.  kind: 0 = trailing-update GEMM (A22 -= L21 U12),
+ * 1 = panel factorization (leaves and in-panel updates), 2 = triangular
+ * solves, 3 = residual GEMV, 4 = downcast, 5 = row interchanges outside the
+ * panel and U12 = L11^{-1} A12.  mpir_prof_get returns the summed duration,
+ * the number of timed intervals and the summed algorithmic work (flops for
+ * kinds 0 and 2, bytes for 3 and 4, 0 otherwise) since the last reset.  With
+ * the look-ahead, intervals of different kinds overlap in time. */
 void mpir_prof_enable(int32_t on);
 void mpir_prof_reset(void);
 mpir_status mpir_prof_get(int32_t kind, double *ms, int64_t *launches, double *work);

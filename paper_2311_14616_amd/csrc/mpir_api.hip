@@ -31,7 +31,7 @@ struct ProfRec {
 struct Prof {
     std::mutex mu;
     bool on = false;
-    std::vector<ProfRec> recs[5];
+    std::vector<ProfRec> recs[6];
     std::vector<hipEvent_t> pool;
 };
 Prof g_prof;
@@ -95,6 +95,8 @@ struct mpir_fact_s {
     double anorm = 0.0;
     int64_t info = 0;
     double t_factor_ms = 0.0;
+    hipStream_t stream2 = nullptr;  // look-ahead: trailing updates
+    hipEvent_t evA[2] = {nullptr, nullptr}, evB[2] = {nullptr, nullptr};
 };
 
 namespace {
@@ -138,6 +140,11 @@ void free_handle(mpir_fact f) {
     hipFree(f->partial);
     hipFree(f->st);
     hipFree(f->ts);
+    for (int i = 0; i < 2; ++i) {
+        if (f->evA[i]) hipEventDestroy(f->evA[i]);
+        if (f->evB[i]) hipEventDestroy(f->evB[i]);
+    }
+    if (f->stream2) hipStreamDestroy(f->stream2);
     delete f;
 }
 
@@ -160,6 +167,12 @@ mpir_status alloc_handle(mpir_fact f) {
         dalloc(&f->partial, (size_t)f->nchunks * n * 8) != hipSuccess ||
         dalloc(&f->st, sizeof(IrState)) != hipSuccess || dalloc(&f->ts, sizeof(TrsvSync)) != hipSuccess)
         return MPIR_ERR_ALLOC;
+    // second stream (default priority) and ordering events for the look-ahead
+    if (hipStreamCreateWithFlags(&f->stream2, hipStreamNonBlocking) != hipSuccess) return MPIR_ERR_HIP;
+    for (int i = 0; i < 2; ++i)
+        if (hipEventCreateWithFlags(&f->evA[i], hipEventDisableTiming) != hipSuccess ||
+            hipEventCreateWithFlags(&f->evB[i], hipEventDisableTiming) != hipSuccess)
+            return MPIR_ERR_HIP;
     return MPIR_OK;
 }
 
@@ -191,49 +204,118 @@ hipError_t laswp_chunks(int mode, void *a, int64_t n, int64_t ld, int64_t k0, in
     return hipSuccess;
 }
 
-// Blocked right-looking LU with partial pivoting on the working array.
-mpir_status getrf(mpir_fact f) {
+// Columns [c0, c1) of rows [K, K+w): U12 <- L11^{-1} U12, blocked by kIB
+// (small triangular solve of each kIB-row block, then the update of the
+// panel rows below it).
+hipError_t upper_solve(mpir_fact f, int64_t K, int w, int64_t c0, int64_t c1, hipStream_t s) {
+    if (c1 <= c0) return hipSuccess;
+    const int mode = f->mode;
+    for (int64_t k = K; k < K + w; k += kIB) {
+        const int wl = (int)((K + w - k) < kIB ? (K + w - k) : kIB);
+        hipError_t e = launch_trsm(mode, f->work, f->ld, k, wl, c0, c1, s);
+        if (e != hipSuccess) return e;
+        if (k + wl < K + w) {
+            e = launch_gemm_update(mode, f->work, f->ld, k + wl, K + w - k - wl, c0, c1 - c0, k, wl, s);
+            if (e != hipSuccess) return e;
+        }
+    }
+    return hipSuccess;
+}
+
+// Panel factorization of columns [K, K+w), rows [K, n): leaves of kIB
+// columns, each followed by its interchanges, triangular solve and update
+// restricted to the other columns of the panel.
+hipError_t factor_panel(mpir_fact f, int64_t K, int w, hipStream_t s) {
     const int64_t n = f->n, ld = f->ld;
     const int mode = f->mode;
     void *a = f->work;
-    hipStream_t s = f->stream;
-    const int nb = panel_width(mode);
-    if (n > leaf_max_rows(mode)) return MPIR_ERR_ARG;
-    for (int64_t K = 0; K < n; K += nb) {
-        const int w = (int)((n - K) < nb ? (n - K) : nb);
-        // ---- panel: columns [K, K+w) ----
-        for (int64_t k = K; k < K + w; k += kIB) {
-            const int wl = (int)((K + w - k) < kIB ? (K + w - k) : kIB);
-            {
-                ProfScope ps_(1, 0.0, s);
-                HIPCHK(launch_leaf(mode, a, n, ld, k, wl, f->ipiv, f->info_d, f->ps, &f->ps_base,
-                                   f->flags_d, s));
-            }
-            if (k > K || k + wl < K + w)
-                HIPCHK(launch_laswp(mode, a, n, ld, k, wl, f->ipiv, K, k, k + wl, K + w, nullptr, s));
-            if (k + wl < K + w) {
-                HIPCHK(launch_trsm(mode, a, ld, k, wl, k + wl, K + w, s));
-                ProfScope ps_(0, 2.0 * (double)(n - k - wl) * (double)(K + w - k - wl) * wl, s);
-                HIPCHK(launch_gemm_update(mode, a, ld, k + wl, n - k - wl, k + wl, K + w - k - wl, k, wl, s));
-            }
+    ProfScope ps_(1, 0.0, s);
+    for (int64_t k = K; k < K + w; k += kIB) {
+        const int wl = (int)((K + w - k) < kIB ? (K + w - k) : kIB);
+        hipError_t e = launch_leaf(mode, a, n, ld, k, wl, f->ipiv, f->info_d, f->ps, &f->ps_base,
+                                   f->flags_d, s);
+        if (e != hipSuccess) return e;
+        if (k > K || k + wl < K + w) {
+            e = launch_laswp(mode, a, n, ld, k, wl, f->ipiv, K, k, k + wl, K + w, nullptr, s);
+            if (e != hipSuccess) return e;
         }
-        // ---- interchanges outside the panel, permutation vector ----
-        HIPCHK(laswp_chunks(mode, a, n, ld, K, w, f->ipiv, 0, K, K + w, n, f->perm, s));
-        if (K + w < n) {
-            // ---- U12 = L11^{-1} A12 (blocked by kIB) ----
-            for (int64_t k = K; k < K + w; k += kIB) {
-                const int wl = (int)((K + w - k) < kIB ? (K + w - k) : kIB);
-                HIPCHK(launch_trsm(mode, a, ld, k, wl, K + w, n, s));
-                if (k + wl < K + w) {
-                    ProfScope ps_(0, 2.0 * (double)(K + w - k - wl) * (double)(n - K - w) * wl, s);
-                    HIPCHK(launch_gemm_update(mode, a, ld, k + wl, K + w - k - wl, K + w, n - K - w, k, wl, s));
-                }
-            }
-            // ---- trailing update A22 -= L21 U12 ----
-            ProfScope ps_(0, 2.0 * (double)(n - K - w) * (double)(n - K - w) * w, s);
-            HIPCHK(launch_gemm_update(mode, a, ld, K + w, n - K - w, K + w, n - K - w, K, w, s));
+        if (k + wl < K + w) {
+            e = launch_trsm(mode, a, ld, k, wl, k + wl, K + w, s);
+            if (e != hipSuccess) return e;
+            e = launch_gemm_update(mode, a, ld, k + wl, n - k - wl, k + wl, K + w - k - wl, k, wl, s);
+            if (e != hipSuccess) return e;
         }
     }
+    return hipSuccess;
+}
+
+// Step of panel [K, K+w) applied to the columns [c0, c1): interchanges,
+// U12, trailing update of rows [K+w, n).
+hipError_t apply_step(mpir_fact f, int64_t K, int w, int64_t c0, int64_t c1, hipStream_t s) {
+    if (c1 <= c0) return hipSuccess;
+    const int64_t n = f->n;
+    hipError_t e;
+    {
+        ProfScope ps_(5, 0.0, s);
+        e = laswp_chunks(f->mode, f->work, n, f->ld, K, w, f->ipiv, c0, c1, c1, c1, nullptr, s);
+        if (e != hipSuccess) return e;
+        e = upper_solve(f, K, w, c0, c1, s);
+        if (e != hipSuccess) return e;
+    }
+    if (K + w < n) {
+        ProfScope ps_(0, 2.0 * (double)(n - K - w) * (double)(c1 - c0) * w, s);
+        e = launch_gemm_update(f->mode, f->work, f->ld, K + w, n - K - w, c0, c1 - c0, K, w, s);
+    }
+    return e;
+}
+
+// Blocked right-looking LU with partial pivoting on the working array, with
+// a look-ahead of one panel: while the trailing update of step p runs on the
+// second stream, the main stream applies step p to panel p+1 only and
+// factors panel p+1 (the latency-bound part), so the panel chain is hidden
+// behind the matrix-core work.  The two streams touch disjoint columns; one
+// event per stream and step parity orders them.
+mpir_status getrf(mpir_fact f) {
+    const int64_t n = f->n;
+    hipStream_t s = f->stream, s2 = f->stream2;
+    const int nb = panel_width(f->mode);
+    if (n > leaf_max_rows(f->mode)) return MPIR_ERR_ARG;
+    hipEvent_t *evA = f->evA, *evB = f->evB;
+    // stream 2 starts after the work already queued on the main stream
+    HIPCHK(hipEventRecord(evA[1], s));
+    HIPCHK(hipStreamWaitEvent(s2, evA[1], 0));
+    HIPCHK(hipEventRecord(evB[1], s2));
+    const int w0 = (int)(n < nb ? n : nb);
+    HIPCHK(factor_panel(f, 0, w0, s));
+    HIPCHK(hipEventRecord(evA[1], s));
+    int p = 0;
+    for (int64_t K = 0; K < n; K += nb, ++p) {
+        const int w = (int)((n - K) < nb ? (n - K) : nb);
+        const int64_t K1 = K + w;
+        const int w1 = (int)((n - K1) < nb ? (n - K1) : nb);
+        const int64_t K2 = K1 + (w1 > 0 ? w1 : 0);
+        const int cur = p & 1, prev = cur ^ 1;
+        // ---- stream 2: everything of step p except panel p+1's columns ----
+        HIPCHK(hipStreamWaitEvent(s2, evA[prev], 0));          // panel p factored
+        {
+            ProfScope ps_(5, 0.0, s2);
+            HIPCHK(laswp_chunks(f->mode, f->work, n, f->ld, K, w, f->ipiv, 0, K, K2, n, f->perm, s2));
+            HIPCHK(upper_solve(f, K, w, K2, n, s2));
+        }
+        if (K2 < n) {
+            ProfScope ps_(0, 2.0 * (double)(n - K1) * (double)(n - K2) * w, s2);
+            HIPCHK(launch_gemm_update(f->mode, f->work, f->ld, K1, n - K1, K2, n - K2, K, w, s2));
+        }
+        HIPCHK(hipEventRecord(evB[cur], s2));
+        // ---- main stream: step p on panel p+1, then factor panel p+1 ----
+        if (w1 > 0) {
+            HIPCHK(hipStreamWaitEvent(s, evB[prev], 0));        // step p-1 done everywhere
+            HIPCHK(apply_step(f, K, w, K1, K2, s));
+            HIPCHK(factor_panel(f, K1, w1, s));
+            HIPCHK(hipEventRecord(evA[cur], s));
+        }
+    }
+    HIPCHK(hipStreamWaitEvent(s, evB[(p - 1) & 1], 0));
     return MPIR_OK;
 }
 
@@ -587,7 +669,7 @@ void mpir_prof_reset(void) {
 }
 
 mpir_status mpir_prof_get(int32_t kind, double *ms, int64_t *launches, double *work) {
-    if (kind < 0 || kind >= 5) return MPIR_ERR_ARG;
+    if (kind < 0 || kind >= 6) return MPIR_ERR_ARG;
     std::lock_guard<std::mutex> g(g_prof.mu);
     double tot = 0.0, wk = 0.0;
     for (auto &r : g_prof.recs[kind]) {
