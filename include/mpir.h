@@ -118,18 +118,36 @@ mpir_status mpir_solve(mpir_fact f, const void *db, void *dx);
 mpir_status mpir_ir_solve(mpir_fact f, const void *db, void *dx,
                           const mpir_term *t, mpir_report *rep);
 
-/* Batched IR for `batch` independent systems of uneven sizes n[k] (host
- * array).  dA[k], db[k], dx[k]: host arrays of device pointers; lda[k] >= n[k].
- * Same precisions for every system; reps: host array of `batch` reports.
- * Every system is factored and refined on the device in one persistent
- * launch; the call returns the first failing status (per-system status in
- * reps[k].info: 0, or the first zero pivot). */
+/* Batched IR for `batch` independent systems of uneven sizes
+ * 1 <= n[k] <= 1024 (host array).  dA[k], db[k], dx[k]: host arrays of
+ * device pointers (A column-major, lda[k] >= n[k]); same precisions for
+ * every system: TW in {F64, F32}, TF in {F32, F16}, TR = F64 (TW = F32 means
+ * TR wider than TW: eq. wilkterm).  Every system is factored and refined on
+ * the device in one persistent launch (workgroups take the systems from a
+ * queue, largest first).  reps: host array of `batch` reports (may be NULL);
+ * reps[k].reserved holds the per-system status (MPIR_OK, MPIR_ERR_SINGULAR
+ * with reps[k].info, MPIR_ERR_NONFINITE, MPIR_ERR_RANGE).  Returns MPIR_OK,
+ * an argument/runtime error, or the first failing per-system status.  The
+ * workspace is allocated and freed by the call. */
 mpir_status mpir_ir_solve_batched(int32_t batch, const int64_t *n,
                                   const void *const *dA, const int64_t *lda,
                                   const void *const *db, void *const *dx,
                                   mpir_prec tw, mpir_prec tf, mpir_prec tr,
                                   const mpir_term *t, mpir_report *reps,
                                   void *hip_stream);
+
+/* The same batch as a reusable plan: mpir_batch_create validates, allocates
+ * the workspace once and, if use_graph != 0, captures the launch sequence in
+ * a hipGraph on hip_stream; mpir_batch_run replays it (or launches it) and
+ * copies the reports to the host array reps (NULL: none); mpir_batch_destroy
+ * releases it.  The device pointers are borrowed until destroy. */
+typedef struct mpir_batch_s *mpir_batch;
+mpir_status mpir_batch_create(int32_t batch, const int64_t *n, const void *const *dA,
+                              const int64_t *lda, const void *const *db, void *const *dx,
+                              mpir_prec tw, mpir_prec tf, mpir_prec tr, const mpir_term *t,
+                              int32_t use_graph, void *hip_stream, mpir_batch *out);
+mpir_status mpir_batch_run(mpir_batch b, mpir_report *reps);
+void mpir_batch_destroy(mpir_batch b);
 
 /* Release a handle (NULL is allowed). */
 void mpir_destroy(mpir_fact f);

@@ -1,0 +1,536 @@
+// Batched iterative refinement: thousands of independent systems of uneven
+// size (n <= 1024) solved in one persistent launch.  Each workgroup takes the
+// next system from an atomic queue (systems ordered largest first, so the
+// long ones start early) and runs the whole method on it: the interprecision
+// copy and ||A||_inf, a blocked right-looking LU with partial pivoting (32
+// column panels factored in LDS, interchanges, U12 solve, trailing update on
+// the matrix cores), then Algorithm IR (low-precision triangular solves,
+// update, FP64 residual, the termination rules) and a per-system report.
+//
+// Storage per system: the caller's A (column-major, TW), b and x (TW); a
+// row-major binary32 working array W (n x n; binary16 numbers for TF = F16)
+// and the row permutation, both in a workspace owned by the library.
+#include "mpir_internal.h"
+
+namespace mpir {
+
+struct BatchSys {
+    int64_t n, lda;
+    const void *A;
+    const void *b;
+    void *x;
+    float *W;
+    int32_t *perm;
+    int64_t pad;
+};
+
+struct BatchTerm {
+    double tol_r, tol_e, rmax;
+    int32_t litmax, residterm, wilk, pad;
+};
+
+namespace {
+
+typedef float floatx16 __attribute__((ext_vector_type(16)));
+typedef _Float16 half8 __attribute__((ext_vector_type(8)));
+
+constexpr int NT = 512;             // threads per workgroup
+constexpr int NW = NT / 64;         // waves
+constexpr int NMAX = 1024;          // largest system
+constexpr int PB = 32;              // panel width
+constexpr int PP = PB + 1;          // LDS pitch of the panel
+constexpr int PANEL_FLOATS = NMAX * PP;
+
+__device__ __forceinline__ double pow2_ceil(double m) {
+    int e;
+    const double f = frexp(m, &e);
+    return f == 0.5 ? ldexp(1.0, e - 1) : ldexp(1.0, e);
+}
+
+__device__ __forceinline__ bool better(double v, int i, double bv, int bi) {
+    return v > bv || (v == bv && i < bi);
+}
+
+// Max of a non-negative double over the workgroup (NaN wins), via bits.
+__device__ __forceinline__ double block_max(double v, uint64_t *red) {
+    uint64_t b = (uint64_t)__double_as_longlong(v) & 0x7fffffffffffffffull;
+    for (int off = 32; off > 0; off >>= 1) {
+        const uint64_t o = (uint64_t)__shfl_xor((long long)b, off);
+        b = o > b ? o : b;
+    }
+    const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+    __syncthreads();
+    if (lane == 0) red[wv] = b;
+    __syncthreads();
+    uint64_t m = red[0];
+    for (int q = 1; q < NW; ++q) m = red[q] > m ? red[q] : m;
+    return __longlong_as_double((long long)m);
+}
+
+template <typename TWt, bool F16>
+__global__ __launch_bounds__(NT) void k_batched(const BatchSys *__restrict__ sys,
+                                                const int32_t *__restrict__ order, int nsys,
+                                                uint32_t *queue, BatchTerm term,
+                                                mpir_report *__restrict__ reps) {
+    __shared__ __align__(16) float panel[PANEL_FLOATS];   // LU: panel / staging tiles
+    // refinement phase (the LU is finished): vectors carved from the panel
+    double *const vr = reinterpret_cast<double *>(panel);  // residual (TR = FP64)
+    double *const vx = vr + NMAX;                          // x as binary64 (exact copy of TW)
+    float *const vy = reinterpret_cast<float *>(vx + NMAX); // low-precision rhs / solution
+    __shared__ float L11[PB][PB + 1];
+    __shared__ int32_t piv[PB];
+    __shared__ int32_t pdst[2 * PB], psrc[2 * PB];
+    __shared__ double red_v[NW];
+    __shared__ int red_i[NW];
+    __shared__ uint64_t redb[NW];
+    __shared__ double tmp64[64];
+    __shared__ double hist_r[MPIR_HIST_MAX], hist_d[MPIR_HIST_MAX];
+    __shared__ int s_sys, s_p, s_extra, s_info, s_flags;
+    (void)tmp64;
+
+    const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
+
+    for (;;) {
+        if (tid == 0) {
+            const uint32_t q = atomicAdd(queue, 1u);
+            s_sys = q < (uint32_t)nsys ? order[q] : -1;
+            s_info = 0;
+            s_flags = 0;
+        }
+        __syncthreads();
+        const int si = s_sys;
+        if (si < 0) break;
+        const BatchSys S = sys[si];
+        const int n = (int)S.n;
+        const int64_t lda = S.lda;
+        const TWt *A = (const TWt *)S.A;
+        const TWt *b = (const TWt *)S.b;
+        TWt *x = (TWt *)S.x;
+        float *W = S.W;
+        int32_t *perm = S.perm;
+
+        // ---------------- interchange-free copy A_F = fl_F(A), ||A||_inf ----
+        // 64 x 64 tiles: coalesced column reads, LDS transpose, coalesced row
+        // writes; row sums by one thread per row in increasing column order.
+        double *tile = reinterpret_cast<double *>(panel);   // [64][65] doubles
+        double amax = 0.0;                                  // max row sum seen by this thread
+        for (int i0 = 0; i0 < n; i0 += 64) {
+            double racc = 0.0;
+            for (int j0 = 0; j0 < n; j0 += 64) {
+                for (int e = tid; e < 64 * 64; e += NT) {
+                    const int r = e & 63, c = e >> 6;
+                    const int i = i0 + r, j = j0 + c;
+                    tile[c * 65 + r] = (i < n && j < n) ? (double)A[i + (int64_t)j * lda] : 0.0;
+                }
+                __syncthreads();
+                if (tid < 64 && i0 + tid < n) {
+                    const int cmax = (n - j0) < 64 ? (n - j0) : 64;
+                    for (int c = 0; c < cmax; ++c) racc = racc + fabs(tile[c * 65 + tid]);
+                }
+                int fl = 0;
+                for (int e = tid; e < 64 * 64; e += NT) {
+                    const int c = e & 63, r = e >> 6;
+                    const int i = i0 + r, j = j0 + c;
+                    if (i < n && j < n) {
+                        const double v = tile[c * 65 + r];
+                        const float f = F16 ? d2h_as_float(v) : (float)v;
+                        if (!isfinite(v)) fl |= DF_NONFINITE;
+                        else if (isinf(f)) fl |= DF_RANGE;
+                        W[(int64_t)i * n + j] = f;
+                    }
+                }
+                if (fl) atomicOr(&s_flags, fl);
+                __syncthreads();
+            }
+            if (tid < 64 && i0 + tid < n) {
+                amax = fmax(amax, racc);
+                if (isnan(racc)) amax = racc;
+            }
+        }
+        for (int i = tid; i < n; i += NT) perm[i] = i;
+        __syncthreads();
+        const double anorm = block_max(amax, redb);
+        if (s_flags) {
+            if (tid == 0) {
+                mpir_report &R = reps[si];
+                R.n_iter = 0;
+                R.stop = 0;
+                R.reserved = (s_flags & DF_NONFINITE) ? MPIR_ERR_NONFINITE : MPIR_ERR_RANGE;
+                R.info = 0;
+            }
+            __syncthreads();
+            continue;
+        }
+
+        // ---------------- blocked LU with partial pivoting ----------------
+        for (int k = 0; k < n; k += PB) {
+            const int w = (n - k) < PB ? (n - k) : PB;
+            const int m = n - k;
+            __syncthreads();
+            for (int e = tid; e < m * w; e += NT) {
+                const int r = e / w, c = e - r * w;
+                panel[r * PP + c] = W[(int64_t)(k + r) * n + k + c];
+            }
+            __syncthreads();
+            for (int j = 0; j < w; ++j) {
+                double bv = -1.0;
+                int bi = 0x7fffffff;
+                for (int r = tid; r < m; r += NT)
+                    if (r >= j) {
+                        const double v = fabs((double)panel[r * PP + j]);
+                        if (v > bv) { bv = v; bi = r; }
+                    }
+                for (int off = 32; off > 0; off >>= 1) {
+                    const double ov = __shfl_xor(bv, off);
+                    const int oi = __shfl_xor(bi, off);
+                    if (better(ov, oi, bv, bi)) { bv = ov; bi = oi; }
+                }
+                if (lane == 0) { red_v[wv] = bv; red_i[wv] = bi; }
+                __syncthreads();
+                if (tid == 0) {
+                    double v0 = red_v[0];
+                    int i0 = red_i[0];
+                    for (int q = 1; q < NW; ++q)
+                        if (better(red_v[q], red_i[q], v0, i0)) { v0 = red_v[q]; i0 = red_i[q]; }
+                    s_p = i0;
+                    piv[j] = i0;
+                }
+                __syncthreads();
+                const int p = s_p;
+                if (tid < w) {
+                    const int c = tid;
+                    const float t = panel[j * PP + c];
+                    float pv = panel[p * PP + c];
+                    if (p != j) panel[p * PP + c] = t;
+                    if (F16 && c >= j) pv = round_f16(pv);
+                    panel[j * PP + c] = pv;
+                }
+                __syncthreads();
+                const float pj = panel[j * PP + j];
+                if (pj == 0.0f) {
+                    if (tid == 0 && s_info == 0) s_info = k + j + 1;
+                } else {
+                    for (int r = j + 1 + tid; r < m; r += NT) {
+                        float l = panel[r * PP + j] / pj;
+                        if (F16) l = round_f16(l);
+                        panel[r * PP + j] = l;
+                        for (int c = j + 1; c < w; ++c) {
+                            const float prod = l * panel[j * PP + c];
+                            panel[r * PP + c] = panel[r * PP + c] - prod;
+                        }
+                    }
+                }
+                __syncthreads();
+            }
+            for (int e = tid; e < m * w; e += NT) {
+                const int r = e / w, c = e - r * w;
+                W[(int64_t)(k + r) * n + k + c] = panel[r * PP + c];
+            }
+            // composed row permutation of this panel (positions >= k)
+            if (tid == 0) s_extra = 0;
+            __syncthreads();
+            if (tid < w) {
+                auto src_of = [&](int i) {
+                    for (int s = w - 1; s >= 0; --s) {
+                        const int ks = s, ps = piv[s];
+                        if (i == ks) i = ps;
+                        else if (i == ps) i = ks;
+                    }
+                    return i;
+                };
+                pdst[tid] = tid;
+                psrc[tid] = src_of(tid);
+                const int pp = piv[tid];
+                if (pp >= w) {
+                    bool first = true;
+                    for (int q = 0; q < tid; ++q) if (piv[q] == pp) { first = false; break; }
+                    if (first) {
+                        const int slot = w + atomicAdd(&s_extra, 1);
+                        pdst[slot] = pp;
+                        psrc[slot] = src_of(pp);
+                    }
+                }
+            }
+            __syncthreads();
+            const int np = w + s_extra;
+            // apply it to the columns outside the panel and to perm (LDS staged)
+            {
+                constexpr int CH = 256;
+                float *stage = panel;                       // [2*PB][CH]
+                int32_t *pst = reinterpret_cast<int32_t *>(panel + 2 * PB * CH);
+                for (int q = tid; q < np; q += NT) pst[q] = perm[k + psrc[q]];
+                for (int c0 = 0; c0 < n; c0 += CH) {
+                    __syncthreads();
+                    for (int e = tid; e < np * CH; e += NT) {
+                        const int q = e / CH, c = c0 + (e - q * CH);
+                        if (c < n && (c < k || c >= k + w))
+                            stage[e] = W[(int64_t)(k + psrc[q]) * n + c];
+                    }
+                    __syncthreads();
+                    for (int e = tid; e < np * CH; e += NT) {
+                        const int q = e / CH, c = c0 + (e - q * CH);
+                        if (c < n && (c < k || c >= k + w))
+                            W[(int64_t)(k + pdst[q]) * n + c] = stage[e];
+                    }
+                }
+                __syncthreads();
+                for (int q = tid; q < np; q += NT) perm[k + pdst[q]] = pst[q];
+            }
+            if (k + w >= n) break;
+            // U12 = L11^{-1} A12 for rows [k, k+w), columns [k+w, n)
+            for (int e = tid; e < w * w; e += NT) {
+                const int r = e / w, c = e - r * w;
+                L11[r][c] = W[(int64_t)(k + r) * n + k + c];
+            }
+            __syncthreads();
+            for (int c = k + w + tid; c < n; c += NT) {
+                float xv[PB];
+#pragma unroll
+                for (int t = 0; t < PB; ++t) xv[t] = t < w ? W[(int64_t)(k + t) * n + c] : 0.0f;
+#pragma unroll
+                for (int t = 0; t < PB; ++t) {
+                    if (F16) xv[t] = round_f16(xv[t]);
+#pragma unroll
+                    for (int s = t + 1; s < PB; ++s) {
+                        const float prod = L11[s][t] * xv[t];
+                        xv[s] = xv[s] - prod;
+                    }
+                }
+#pragma unroll
+                for (int t = 0; t < PB; ++t) if (t < w) W[(int64_t)(k + t) * n + c] = xv[t];
+            }
+            __syncthreads();
+            // trailing update A22 -= L21 U12 (K = w <= 32) in 32 x 32 blocks
+            {
+                const int r0 = k + w, mm = n - r0;
+                const int nbk = (mm + 31) / 32;
+                for (int blk = wv; blk < nbk * nbk; blk += NW) {
+                    const int bi = blk / nbk, bj = blk - bi * nbk;
+                    const int rb = r0 + bi * 32, cb = r0 + bj * 32;
+                    floatx16 acc = floatx16{0};
+                    const int ar = rb + (lane & 31), bc = cb + (lane & 31);
+                    if (F16) {
+#pragma unroll
+                        for (int s = 0; s < PB; s += 16) {
+                            half8 av, bvv;
+#pragma unroll
+                            for (int q = 0; q < 8; ++q) {
+                                const int kq = s + 8 * (lane >> 5) + q;
+                                av[q] = (_Float16)((ar < n && kq < w) ? W[(int64_t)ar * n + k + kq] : 0.0f);
+                                bvv[q] = (_Float16)((bc < n && kq < w) ? W[(int64_t)(k + kq) * n + bc] : 0.0f);
+                            }
+                            acc = __builtin_amdgcn_mfma_f32_32x32x16_f16(av, bvv, acc, 0, 0, 0);
+                        }
+                    } else {
+#pragma unroll
+                        for (int s = 0; s < PB; s += 2) {
+                            const int kq = s + (lane >> 5);
+                            const float av = (ar < n && kq < w) ? W[(int64_t)ar * n + k + kq] : 0.0f;
+                            const float bvv = (bc < n && kq < w) ? W[(int64_t)(k + kq) * n + bc] : 0.0f;
+                            acc = __builtin_amdgcn_mfma_f32_32x32x2f32(av, bvv, acc, 0, 0, 0);
+                        }
+                    }
+#pragma unroll
+                    for (int v = 0; v < 16; ++v) {
+                        const int row = rb + 8 * (v >> 2) + 4 * (lane >> 5) + (v & 3);
+                        const int col = cb + (lane & 31);
+                        if (row < n && col < n) {
+                            float *pc = W + (int64_t)row * n + col;
+                            *pc = *pc - acc[v];
+                        }
+                    }
+                }
+            }
+        }
+        __syncthreads();
+        const int info = s_info;
+
+        // ---------------- Algorithm IR ----------------
+        int it = 0, stop = MPIR_STOP_CONVERGED;
+        double bnorm = 0.0, rnorm = 0.0, xnorm = 0.0;
+        if (info == 0) {
+            {
+                double m = 0.0;
+                for (int i = tid; i < n; i += NT) {
+                    const double bi = (double)b[i];
+                    vr[i] = bi;
+                    vx[i] = 0.0;
+                    x[i] = (TWt)0;
+                    m = fmax(m, fabs(bi));
+                    if (isnan(bi)) m = bi;
+                }
+                bnorm = block_max(m, redb);
+            }
+            rnorm = bnorm;
+            if (tid == 0) hist_r[0] = bnorm;
+            double prev_r = bnorm, prev_d = 0.0;
+            bool done = false;
+            if (!isfinite(bnorm)) { done = true; stop = MPIR_STOP_NONFINITE; }
+            else if (bnorm == 0.0) done = true;
+            else if (!term.wilk) {
+                const bool conv = term.residterm ? (rnorm <= term.tol_r * bnorm)
+                                                 : (rnorm <= term.tol_e * bnorm);
+                done = conv;
+            }
+            while (!done) {
+                const double sigma = pow2_ceil(rnorm);
+                const double inv = 1.0 / sigma;
+                for (int i = tid; i < n; i += NT) {
+                    const double v = vr[perm[i]] * inv;
+                    vy[i] = F16 ? d2h_as_float(v) : (float)v;
+                }
+                __syncthreads();
+                // forward substitution with unit L, 64-row blocks
+                for (int i0 = 0; i0 < n; i0 += 64) {
+                    const int rows = (n - i0) < 64 ? (n - i0) : 64;
+                    // off-diagonal: wave wv handles rows i0 + wv*8 .. +8
+                    for (int rr = 0; rr < 8; ++rr) {
+                        const int i = i0 + wv * 8 + rr;
+                        float acc = 0.0f;
+                        if (wv * 8 + rr < rows)
+                            for (int c = lane; c < i0; c += 64) acc += W[(int64_t)i * n + c] * vy[c];
+                        for (int off = 32; off > 0; off >>= 1) acc += __shfl_xor(acc, off);
+                        if (lane == 0) tmp64[wv * 8 + rr] = acc;
+                    }
+                    __syncthreads();
+                    if (wv == 0) {
+                        float z = 0.0f;
+                        float drow[64];
+                        if (lane < rows) {
+                            z = vy[i0 + lane] - (float)tmp64[lane];
+#pragma unroll
+                            for (int c = 0; c < 64; ++c) drow[c] = c < rows ? W[(int64_t)(i0 + lane) * n + i0 + c] : 0.0f;
+                        } else {
+#pragma unroll
+                            for (int c = 0; c < 64; ++c) drow[c] = 0.0f;
+                        }
+#pragma unroll
+                        for (int jj = 0; jj < 64; ++jj) {
+                            const float yj = __shfl(z, jj);
+                            if (lane > jj) z -= drow[jj] * yj;
+                        }
+                        if (lane < rows) vy[i0 + lane] = z;
+                    }
+                    __syncthreads();
+                }
+                // back substitution with U
+                for (int i0 = ((n - 1) / 64) * 64; i0 >= 0; i0 -= 64) {
+                    const int rows = (n - i0) < 64 ? (n - i0) : 64;
+                    for (int rr = 0; rr < 8; ++rr) {
+                        const int i = i0 + wv * 8 + rr;
+                        float acc = 0.0f;
+                        if (wv * 8 + rr < rows)
+                            for (int c = i0 + 64 + lane; c < n; c += 64) acc += W[(int64_t)i * n + c] * vy[c];
+                        for (int off = 32; off > 0; off >>= 1) acc += __shfl_xor(acc, off);
+                        if (lane == 0) tmp64[wv * 8 + rr] = acc;
+                    }
+                    __syncthreads();
+                    if (wv == 0) {
+                        float z = 0.0f;
+                        float drow[64];
+                        if (lane < rows) {
+                            z = vy[i0 + lane] - (float)tmp64[lane];
+#pragma unroll
+                            for (int c = 0; c < 64; ++c) drow[c] = c < rows ? W[(int64_t)(i0 + lane) * n + i0 + c] : 0.0f;
+                        } else {
+#pragma unroll
+                            for (int c = 0; c < 64; ++c) drow[c] = 1.0f;
+                        }
+#pragma unroll
+                        for (int jj = 63; jj >= 0; --jj) {
+                            if (lane == jj && lane < rows) z = z / drow[jj];
+                            const float yj = __shfl(z, jj);
+                            if (lane < jj) z -= drow[jj] * yj;
+                        }
+                        if (lane < rows) vy[i0 + lane] = z;
+                    }
+                    __syncthreads();
+                }
+                // d = sigma * y, x <- fl_W(x + d)
+                double dm = 0.0;
+                for (int i = tid; i < n; i += NT) {
+                    const TWt d = (TWt)sigma * (TWt)vy[i];
+                    const TWt xn = (TWt)vx[i] + d;
+                    vx[i] = (double)xn;
+                    x[i] = xn;
+                    dm = fmax(dm, fabs((double)d));
+                    if (isnan((double)d)) dm = (double)d;
+                }
+                const double dnorm = block_max(dm, redb);
+                // r = b - A x in binary64 (thread per row, columns in order)
+                double rm = 0.0, xm = 0.0;
+                for (int i = tid; i < n; i += NT) {
+                    double acc = 0.0;
+                    const TWt *col = A + i;
+                    for (int j = 0; j < n; ++j) acc += (double)col[(int64_t)j * lda] * vx[j];
+                    const double ri = (double)b[i] - acc;
+                    vr[i] = ri;
+                    rm = fmax(rm, fabs(ri));
+                    if (isnan(ri)) rm = ri;
+                    xm = fmax(xm, fabs(vx[i]));
+                }
+                rnorm = block_max(rm, redb);
+                xnorm = block_max(xm, redb);
+                ++it;
+                if (tid == 0) { hist_r[it] = rnorm; hist_d[it - 1] = dnorm; }
+                // every thread holds the same norms: the tests need no barrier
+                const double pr = prev_r, pd = prev_d;
+                prev_r = rnorm;
+                prev_d = dnorm;
+                if (!isfinite(rnorm) || !isfinite(dnorm)) { stop = MPIR_STOP_NONFINITE; break; }
+                if (rnorm == 0.0) { stop = MPIR_STOP_CONVERGED; break; }
+                if (!term.wilk) {
+                    const bool conv = term.residterm ? (rnorm <= term.tol_r * bnorm)
+                                                     : (rnorm <= term.tol_e * (bnorm + anorm * xnorm));
+                    if (conv) { stop = MPIR_STOP_CONVERGED; break; }
+                    if (it >= term.litmax) { stop = MPIR_STOP_LITMAX; break; }
+                    if (rnorm >= term.rmax * pr) { stop = MPIR_STOP_STAGNATED; break; }
+                } else {
+                    if (it >= term.litmax) { stop = MPIR_STOP_LITMAX; break; }
+                    if (it >= 2 && dnorm >= term.rmax * pd) { stop = MPIR_STOP_DSTAGNATED; break; }
+                }
+                __syncthreads();
+            }
+        }
+        __syncthreads();
+        // ---------------- report ----------------
+        if (tid == 0) {
+            mpir_report &R = reps[si];
+            R.n_iter = it;
+            R.stop = stop;
+            R.n_hist = it + 1;
+            R.reserved = info ? MPIR_ERR_SINGULAR : MPIR_OK;
+            for (int q = 0; q <= it && q < MPIR_HIST_MAX; ++q) R.rhist[q] = hist_r[q];
+            for (int q = 0; q < it && q < MPIR_HIST_MAX; ++q) R.dhist[q] = hist_d[q];
+            R.anorm_inf = anorm;
+            R.bnorm_inf = bnorm;
+            R.xnorm_inf = xnorm;
+            R.relres = bnorm > 0.0 ? rnorm / bnorm : rnorm;
+            const double den = anorm * xnorm + bnorm;
+            R.bwd_err = den > 0.0 ? rnorm / den : 0.0;
+            R.info = info;
+            R.t_factor_ms = 0.0;
+            R.t_ir_ms = 0.0;
+        }
+        __syncthreads();
+    }
+}
+
+}  // namespace
+
+int batched_max_n() { return NMAX; }
+
+hipError_t launch_batched(int tw, int tf, const BatchSys *sys, const int32_t *order, int nsys,
+                          uint32_t *queue, const BatchTerm &term, mpir_report *reps, int nwg,
+                          hipStream_t s) {
+    if (tw == MPIR_F64) {
+        if (tf == MPIR_F16) k_batched<double, true><<<nwg, NT, 0, s>>>(sys, order, nsys, queue, term, reps);
+        else k_batched<double, false><<<nwg, NT, 0, s>>>(sys, order, nsys, queue, term, reps);
+    } else {
+        if (tf == MPIR_F16) k_batched<float, true><<<nwg, NT, 0, s>>>(sys, order, nsys, queue, term, reps);
+        else k_batched<float, false><<<nwg, NT, 0, s>>>(sys, order, nsys, queue, term, reps);
+    }
+    return hipGetLastError();
+}
+
+}  // namespace mpir

@@ -2,6 +2,7 @@
 // management, the blocked LU driver and the refinement-loop driver.  Every
 // arithmetic step runs in the HIP kernels of this directory; this file only
 // orders launches on the caller's stream and moves status words.
+#include <algorithm>
 #include <chrono>
 #include <cmath>
 #include <cstdio>
@@ -17,6 +18,20 @@ using namespace mpir;
 namespace mpir {
 hipError_t launch_set_sigma(IrState *st, hipStream_t s);
 int leaf_max_rows(int mode);
+// layout shared with k_batched.hip
+struct BatchSys {
+    int64_t n, lda;
+    const void *A;
+    const void *b;
+    void *x;
+    float *W;
+    int32_t *perm;
+    int64_t pad;
+};
+struct BatchTerm {
+    double tol_r, tol_e, rmax;
+    int32_t litmax, residterm, wilk, pad;
+};
 }
 
 // --------------------------------------------------------------------------
@@ -644,13 +659,179 @@ mpir_status mpir_residual(int64_t n, const void *dA, int64_t lda, mpir_prec tw, 
     return ret;
 }
 
+}  // extern "C"
+
+// --------------------------------------------------------------------------
+// Batched refinement (a persistent launch over a queue of systems)
+// --------------------------------------------------------------------------
+struct mpir_batch_s {
+    int32_t batch = 0;
+    int tw = 0, tf = 0, tr = 0;
+    hipStream_t stream = nullptr;
+    BatchSys *sys_d = nullptr;
+    int32_t *order_d = nullptr;
+    uint32_t *queue_d = nullptr;
+    float *work = nullptr;
+    int32_t *perm = nullptr;
+    mpir_report *reps_d = nullptr;
+    BatchTerm term{};
+    int nwg = 0;
+    hipGraph_t graph = nullptr;
+    hipGraphExec_t exec = nullptr;
+};
+
+namespace {
+
+__global__ void k_zero_u32(uint32_t *p) {
+    if (threadIdx.x == 0 && blockIdx.x == 0) *p = 0u;
+}
+
+void free_batch(mpir_batch b) {
+    if (!b) return;
+    if (b->exec) hipGraphExecDestroy(b->exec);
+    if (b->graph) hipGraphDestroy(b->graph);
+    hipFree(b->sys_d);
+    hipFree(b->order_d);
+    hipFree(b->queue_d);
+    hipFree(b->work);
+    hipFree(b->perm);
+    hipFree(b->reps_d);
+    delete b;
+}
+
+// Enqueue one solve of the whole batch: reset the queue with a kernel (no
+// memset node, so the sequence can be captured), then the persistent launch.
+hipError_t enqueue_batch(mpir_batch b, hipStream_t s) {
+    k_zero_u32<<<1, 64, 0, s>>>(b->queue_d);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+    return launch_batched(b->tw, b->tf, b->sys_d, b->order_d, b->batch, b->queue_d, b->term,
+                          b->reps_d, b->nwg, s);
+}
+
+int device_cus() {
+    int dev = 0;
+    hipDeviceProp_t prop;
+    if (hipGetDevice(&dev) != hipSuccess || hipGetDeviceProperties(&prop, dev) != hipSuccess) return 0;
+    return prop.multiProcessorCount;
+}
+
+}  // namespace
+
+extern "C" {
+
+mpir_status mpir_batch_create(int32_t batch, const int64_t *n, const void *const *dA,
+                              const int64_t *lda, const void *const *db, void *const *dx,
+                              mpir_prec tw, mpir_prec tf, mpir_prec tr, const mpir_term *t,
+                              int32_t use_graph, void *hip_stream, mpir_batch *out) {
+    if (out) *out = nullptr;
+    if (!out || batch <= 0 || !n || !dA || !lda || !db || !dx) return MPIR_ERR_ARG;
+    if (!(tw == MPIR_F64 || tw == MPIR_F32) || !(tf == MPIR_F32 || tf == MPIR_F16) || tr != MPIR_F64)
+        return MPIR_ERR_ARG;
+    if (tw == MPIR_F32 && tf == MPIR_F32) {
+        // TF = TW = F32 with TR = F64 (eq. wilkterm) is allowed
+    }
+    mpir_term term;
+    if (t) term = *t;
+    else mpir_term_default(&term);
+    if (term.litmax < 1 || term.litmax > MPIR_HIST_MAX - 1 || !(term.Rmax > 0.0)) return MPIR_ERR_ARG;
+    int64_t total = 0, totn = 0;
+    for (int32_t k = 0; k < batch; ++k) {
+        if (n[k] <= 0 || n[k] > batched_max_n() || lda[k] < n[k] || !dA[k] || !db[k] || !dx[k])
+            return MPIR_ERR_ARG;
+        total += n[k] * n[k];
+        totn += n[k];
+    }
+    mpir_batch b = new (std::nothrow) mpir_batch_s();
+    if (!b) return MPIR_ERR_ALLOC;
+    b->batch = batch;
+    b->tw = tw;
+    b->tf = tf;
+    b->tr = tr;
+    b->stream = (hipStream_t)hip_stream;
+    const double uw = tw == MPIR_F64 ? std::ldexp(1.0, -52) : std::ldexp(1.0, -23);
+    b->term.tol_r = term.tol_rel > 0 ? term.tol_rel : term.Cr * uw;
+    b->term.tol_e = term.tol_rel > 0 ? term.tol_rel : term.Ce * uw;
+    b->term.rmax = term.Rmax;
+    b->term.litmax = term.litmax;
+    b->term.residterm = term.residterm ? 1 : 0;
+    b->term.wilk = tw != MPIR_F64 ? 1 : 0;
+    if (dalloc(&b->sys_d, sizeof(BatchSys) * batch) != hipSuccess ||
+        dalloc(&b->order_d, sizeof(int32_t) * batch) != hipSuccess ||
+        dalloc(&b->queue_d, 16) != hipSuccess || dalloc(&b->work, sizeof(float) * total) != hipSuccess ||
+        dalloc(&b->perm, sizeof(int32_t) * totn) != hipSuccess ||
+        dalloc(&b->reps_d, sizeof(mpir_report) * batch) != hipSuccess) {
+        free_batch(b);
+        return MPIR_ERR_ALLOC;
+    }
+    std::vector<BatchSys> sys(batch);
+    int64_t wo = 0, po = 0;
+    for (int32_t k = 0; k < batch; ++k) {
+        sys[k] = BatchSys{n[k], lda[k], dA[k], db[k], dx[k], b->work + wo, b->perm + po, 0};
+        wo += n[k] * n[k];
+        po += n[k];
+    }
+    // longest first (work ~ n^3): the largest systems start in the first wave
+    std::vector<int32_t> order(batch);
+    for (int32_t k = 0; k < batch; ++k) order[k] = k;
+    std::stable_sort(order.begin(), order.end(), [&](int32_t x, int32_t y) { return n[x] > n[y]; });
+    if (hipMemcpy(b->sys_d, sys.data(), sizeof(BatchSys) * batch, hipMemcpyHostToDevice) != hipSuccess ||
+        hipMemcpy(b->order_d, order.data(), sizeof(int32_t) * batch, hipMemcpyHostToDevice) != hipSuccess) {
+        free_batch(b);
+        return MPIR_ERR_HIP;
+    }
+    const int cus = device_cus();
+    b->nwg = cus > 0 ? (cus < batch ? cus : batch) : 1;
+    if (use_graph) {
+        // capture on a private stream (the caller's may be the legacy default
+        // stream, which cannot be captured); replays go to the caller's stream
+        hipStream_t cs = nullptr;
+        if (hipStreamCreateWithFlags(&cs, hipStreamNonBlocking) != hipSuccess) {
+            free_batch(b);
+            return MPIR_ERR_HIP;
+        }
+        hipError_t e0 = hipStreamBeginCapture(cs, hipStreamCaptureModeThreadLocal);
+        const hipError_t e1 = e0 == hipSuccess ? enqueue_batch(b, cs) : e0;
+        const hipError_t e2 = e0 == hipSuccess ? hipStreamEndCapture(cs, &b->graph) : e0;
+        hipStreamDestroy(cs);
+        if (e1 != hipSuccess || e2 != hipSuccess ||
+            hipGraphInstantiate(&b->exec, b->graph, nullptr, nullptr, 0) != hipSuccess) {
+            free_batch(b);
+            return MPIR_ERR_HIP;
+        }
+    }
+    *out = b;
+    return MPIR_OK;
+}
+
+mpir_status mpir_batch_run(mpir_batch b, mpir_report *reps) {
+    if (!b) return MPIR_ERR_ARG;
+    if (b->exec) HIPCHK(hipGraphLaunch(b->exec, b->stream));
+    else HIPCHK(enqueue_batch(b, b->stream));
+    if (reps) HIPCHK(hipMemcpyAsync(reps, b->reps_d, sizeof(mpir_report) * b->batch, hipMemcpyDeviceToHost, b->stream));
+    HIPCHK(hipStreamSynchronize(b->stream));
+    if (reps)
+        for (int32_t k = 0; k < b->batch; ++k)
+            if (reps[k].reserved != MPIR_OK) return (mpir_status)reps[k].reserved;
+    return MPIR_OK;
+}
+
+void mpir_batch_destroy(mpir_batch b) {
+    if (!b) return;
+    hipStreamSynchronize(b->stream);
+    free_batch(b);
+}
+
 mpir_status mpir_ir_solve_batched(int32_t batch, const int64_t *n, const void *const *dA,
                                   const int64_t *lda, const void *const *db, void *const *dx,
                                   mpir_prec tw, mpir_prec tf, mpir_prec tr, const mpir_term *t,
                                   mpir_report *reps, void *hip_stream) {
-    (void)batch; (void)n; (void)dA; (void)lda; (void)db; (void)dx; (void)tw; (void)tf; (void)tr;
-    (void)t; (void)reps; (void)hip_stream;
-    return MPIR_ERR_ARG;
+    mpir_batch b = nullptr;
+    mpir_status st = mpir_batch_create(batch, n, dA, lda, db, dx, tw, tf, tr, t, 0, hip_stream, &b);
+    if (st != MPIR_OK) return st;
+    st = mpir_batch_run(b, reps);
+    mpir_batch_destroy(b);
+    return st;
 }
 
 void mpir_prof_enable(int32_t on) {

@@ -158,6 +158,14 @@ hipError_t launch_update(int64_t n, int tw, int tf, const void *y, void *x,
                          IrState *st, int force, hipStream_t s);
 hipError_t launch_terminate(IrState *st, hipStream_t s);
 
+// a10: batched refinement of uneven systems in one persistent launch.
+struct BatchSys;
+struct BatchTerm;
+int batched_max_n();
+hipError_t launch_batched(int tw, int tf, const BatchSys *sys, const int32_t *order, int nsys,
+                          uint32_t *queue, const BatchTerm &term, mpir_report *reps, int nwg,
+                          hipStream_t s);
+
 // a7: triangular solves with the packed factors (row-major, TF storage).
 // y is float for TF in {F32, F16}, double for F64.
 hipError_t launch_trsv(int tf, const void *LU, int64_t n, int64_t ld, void *y,

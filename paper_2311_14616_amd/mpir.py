@@ -30,6 +30,7 @@ EXPORTS = [
     "mpir_term_default", "mpir_factor", "mpir_refactor", "mpir_solve", "mpir_ir_solve",
     "mpir_ir_solve_batched", "mpir_destroy", "mpir_status_str", "mpir_downcast",
     "mpir_get_factors", "mpir_residual", "mpir_prof_enable", "mpir_prof_reset", "mpir_prof_get",
+    "mpir_batch_create", "mpir_batch_run", "mpir_batch_destroy",
 ]
 
 
@@ -94,6 +95,12 @@ def lib():
         L.mpir_get_factors.argtypes = [vp, vp, vp]
         L.mpir_residual.restype = C.c_int
         L.mpir_residual.argtypes = [i64, vp, i64, C.c_int, C.c_int, vp, vp, vp, P(d), vp]
+        L.mpir_batch_create.restype = C.c_int
+        L.mpir_batch_create.argtypes = [i32, P(i64), P(vp), P(i64), P(vp), P(vp), C.c_int, C.c_int,
+                                        C.c_int, P(Term), i32, vp, P(vp)]
+        L.mpir_batch_run.restype = C.c_int
+        L.mpir_batch_run.argtypes = [vp, vp]
+        L.mpir_batch_destroy.argtypes = [vp]
         L.mpir_prof_enable.argtypes = [i32]
         L.mpir_prof_get.restype = C.c_int
         L.mpir_prof_get.argtypes = [i32, P(d), P(i64), P(d)]
@@ -256,12 +263,53 @@ def residual(At, b, x, tr: int = F64, stream=None):
     return r, rn.value
 
 
+class Batch:
+    """A batch of independent systems solved in one persistent launch
+    (mpir_batch_*): the workspace is allocated once and, with use_graph, the
+    launch sequence is captured in a hipGraph and replayed by run()."""
+
+    def __init__(self, As, bs, xs, tf: int, tr: int = F64, term_parms: Term | None = None,
+                 use_graph: bool = True, stream=None):
+        k = len(As)
+        self.keep = (As, bs, xs)
+        self.k = k
+        tw = _prec_of_dtype(As[0].dtype)
+        ns = (C.c_int64 * k)(*[a.shape[0] for a in As])
+        ldas = (C.c_int64 * k)(*[a.shape[1] for a in As])
+        pa = (C.c_void_p * k)(*[_dev_ptr(a).value for a in As])
+        pb = (C.c_void_p * k)(*[_dev_ptr(b).value for b in bs])
+        px = (C.c_void_p * k)(*[_dev_ptr(x).value for x in xs])
+        h = C.c_void_p(0)
+        tp = C.byref(term_parms) if term_parms is not None else None
+        _check(lib().mpir_batch_create(k, ns, pa, ldas, pb, px, tw, tf, tr, tp, 1 if use_graph else 0,
+                                       _stream_ptr(stream), C.byref(h)), "mpir_batch_create")
+        self._h = h
+
+    def run(self):
+        reps = (Report * self.k)()
+        st = lib().mpir_batch_run(self._h, reps)
+        if st not in (OK, ERR_SINGULAR, ERR_NONFINITE, ERR_RANGE):
+            raise MpirError(st, "mpir_batch_run")
+        return st, list(reps)
+
+    def destroy(self):
+        if getattr(self, "_h", None):
+            lib().mpir_batch_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.destroy()
+        except Exception:
+            pass
+
+
 def ir_solve_batched(As, bs, xs, tf: int, tr: int | None = None, term_parms: Term | None = None,
                      stream=None):
     """Batched IR over lists of column-major matrices / vectors (same TW)."""
     k = len(As)
     tw = _prec_of_dtype(As[0].dtype)
-    tr = tw if tr is None else tr
+    tr = F64 if tr is None else tr
     ns = (C.c_int64 * k)(*[a.shape[0] for a in As])
     ldas = (C.c_int64 * k)(*[a.shape[1] for a in As])
     pa = (C.c_void_p * k)(*[a.data_ptr() for a in As])
