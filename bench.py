@@ -47,6 +47,40 @@ def cpu_baseline(n_sample: int, n_full: int):
             "sample_n_iter": int(r.n_iter), "sample_s": dt}
 
 
+def batched_bench(M, I, torch, dev, tf_name: str, reps: int = 3):
+    """Solves/s of the uneven batch (4096 systems, N_k in [32, 1024], seed
+    2311) in one persistent launch replayed from a hipGraph, with the
+    per-system forward error against x* = ones (b = A*ones)."""
+    import numpy as np
+    ns, alphas, ds = I.batched_spec()
+    As, bs, xs = [], [], []
+    for n, al, d in zip(ns, alphas, ds):
+        at = I.gmat_operator_torch(int(n), float(al), dev)
+        at[torch.arange(int(n)), torch.arange(int(n))] += torch.from_numpy(d).to(dev)
+        As.append(at)
+        bs.append(at.sum(0))
+        xs.append(torch.empty(int(n), dtype=torch.float64, device=dev))
+    tf = {"f32": M.F32, "f16": M.F16}[tf_name]
+    bt = M.Batch(As, bs, xs, tf, term_parms=M.term(tol_rel=1e-14, litmax=20), use_graph=True)
+    bt.run()                                    # warm-up
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(reps):
+        st, rep = bt.run()
+    torch.cuda.synchronize()
+    ms = (time.perf_counter() - t0) * 1e3 / reps
+    bt.destroy()
+    ferr = np.array([float((x - 1.0).abs().max()) for x in xs])
+    bwd = np.array([r.bwd_err for r in rep])
+    iters = np.array([r.n_iter for r in rep])
+    return {"tf": tf_name, "systems": len(ns), "ms": round(ms, 3),
+            "solves_per_s": round(len(ns) / (ms * 1e-3), 1),
+            "all_converged": bool(all(r.stop == 0 for r in rep)),
+            "n_iter_mean": float(iters.mean()), "n_iter_max": int(iters.max()),
+            "ferr_p50": float(np.percentile(ferr, 50)), "ferr_p99": float(np.percentile(ferr, 99)),
+            "bwd_err_max": float(bwd.max())}
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -56,9 +90,10 @@ def main():
     ap.add_argument("--alpha", type=float, default=1.0)
     ap.add_argument("--tf", choices=["f32", "f16"], default="f32")
     ap.add_argument("--fp64-runs", type=int, default=1)
-    ap.add_argument("--cpu-sample", type=int, default=3072)
+    ap.add_argument("--cpu-sample", type=int, default=5120)
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--no-fp64", action="store_true")
+    ap.add_argument("--no-batched", action="store_true")
     args = ap.parse_args()
     if args.gpus != 1:
         print(json.dumps({"error": "this build runs on one GPU; multi-GPU sharding is "
@@ -157,6 +192,12 @@ def main():
         out["speedup_vs_fp64_lu"] = round(fp64_ms / ms_step, 3)
         out["fp64_lu_relres"] = rn64 / bn
         log(f"[bench] FP64 LU solve {fp64_ms:.2f} ms  relres={rn64 / bn:.2e}")
+    if not args.no_batched:
+        out["batched"] = []
+        for tfn in ("f32", "f16"):
+            log(f"[bench] batched 4096 uneven systems, TF={tfn}")
+            out["batched"].append(batched_bench(M, I, torch, dev, tfn))
+            log(f"[bench]   {out['batched'][-1]}")
     if not args.no_cpu:
         log(f"[bench] CPU oracle sample N={args.cpu_sample}")
         out["cpu_baseline"] = cpu_baseline(args.cpu_sample, n)
