@@ -42,28 +42,59 @@ __device__ __forceinline__ double pow2_ceil(double m) {
 }
 
 // ---- residual, pass 1: partial[c][i] = sum_{j in chunk c} a_ij x_j --------
-template <typename TWt, typename TRt>
+// Thread per RPT consecutive rows (one 8- or 16-byte load per column covers
+// them; a wave reads 64*RPT consecutive entries of a column), 16 columns in
+// flight per thread.
+template <typename TWt, typename TRt, int RPT>
 __global__ __launch_bounds__(256) void k_resid_partial(int64_t n, const TWt *__restrict__ A, int64_t lda,
                                                        const TWt *__restrict__ x,
                                                        double *__restrict__ partial,
                                                        const IrState *st, int force) {
     if (!force && st->done) return;
-    const int64_t i = (int64_t)blockIdx.x * kRowsPerBlock + threadIdx.x;
+    const int64_t i = ((int64_t)blockIdx.x * kRowsPerBlock + threadIdx.x) * RPT;
     const int64_t j0 = (int64_t)blockIdx.y * kChunkCols;
     const int64_t j1 = (j0 + kChunkCols) < n ? (j0 + kChunkCols) : n;
     if (i >= n) return;
-    TRt acc = 0;
+    TRt acc[RPT];
+#pragma unroll
+    for (int r = 0; r < RPT; ++r) acc[r] = 0;
     const TWt *col = A + i + j0 * lda;
+    const bool full = i + RPT <= n;
     int64_t j = j0;
-    for (; j + 8 <= j1; j += 8) {
-        TRt v[8];
+    if (full) {
+        for (; j + 16 <= j1; j += 16) {
+            TWt v[16][RPT];
 #pragma unroll
-        for (int q = 0; q < 8; ++q) v[q] = (TRt)col[(j - j0 + q) * lda];
+            for (int q = 0; q < 16; ++q) {
+                const TWt *p = col + (j - j0 + q) * lda;
+                if constexpr (RPT == 2 && sizeof(TWt) == 8) {
+                    const double2 t = *reinterpret_cast<const double2 *>(p);
+                    v[q][0] = t.x; v[q][1] = t.y;
+                } else if constexpr (RPT == 2 && sizeof(TWt) == 4) {
+                    const float2 t = *reinterpret_cast<const float2 *>(p);
+                    v[q][0] = t.x; v[q][1] = t.y;
+                } else {
 #pragma unroll
-        for (int q = 0; q < 8; ++q) acc += v[q] * (TRt)x[j + q];
+                    for (int r = 0; r < RPT; ++r) v[q][r] = p[r];
+                }
+            }
+#pragma unroll
+            for (int q = 0; q < 16; ++q) {
+                const TRt xq = (TRt)x[j + q];
+#pragma unroll
+                for (int r = 0; r < RPT; ++r) acc[r] += (TRt)v[q][r] * xq;
+            }
+        }
     }
-    for (; j < j1; ++j) acc += (TRt)col[(j - j0) * lda] * (TRt)x[j];
-    partial[(int64_t)blockIdx.y * n + i] = (double)acc;
+    for (; j < j1; ++j) {
+        const TRt xq = (TRt)x[j];
+#pragma unroll
+        for (int r = 0; r < RPT; ++r)
+            if (i + r < n) acc[r] += (TRt)col[(j - j0) * lda + r] * xq;
+    }
+#pragma unroll
+    for (int r = 0; r < RPT; ++r)
+        if (i + r < n) partial[(int64_t)blockIdx.y * n + i + r] = (double)acc[r];
 }
 
 // ---- residual, pass 2: r_i = b_i - sum_c partial[c][i] (c increasing) ----
@@ -210,16 +241,24 @@ hipError_t launch_residual(int64_t n, const void *A, int64_t lda, int tw, int tr
                            const void *x, void *r, double *partial, int nch, IrState *st,
                            int force, hipStream_t s) {
     if (n <= 0) return hipSuccess;
-    dim3 g1(blocks_for(n, kRowsPerBlock), (unsigned)nch), b1(kRowsPerBlock);
+    // two rows per thread with vector loads when every column start is aligned
+    const size_t es = tw == MPIR_F64 ? 8 : 4;
+    const bool vec = ((uintptr_t)A % (2 * es) == 0) && (lda % 2 == 0);
+    const int rpt = vec ? 2 : 1;
+    dim3 g1((unsigned)((n + (int64_t)kRowsPerBlock * rpt - 1) / ((int64_t)kRowsPerBlock * rpt)), (unsigned)nch);
+    dim3 b1(kRowsPerBlock);
     dim3 g2(blocks_for(n, 256)), b2(256);
     if (tw == MPIR_F64) {
-        k_resid_partial<double, double><<<g1, b1, 0, s>>>(n, (const double *)A, lda, (const double *)x, partial, st, force);
+        if (vec) k_resid_partial<double, double, 2><<<g1, b1, 0, s>>>(n, (const double *)A, lda, (const double *)x, partial, st, force);
+        else k_resid_partial<double, double, 1><<<g1, b1, 0, s>>>(n, (const double *)A, lda, (const double *)x, partial, st, force);
         k_resid_reduce<double, double><<<g2, b2, 0, s>>>(n, (const double *)b, (const double *)x, partial, nch, (double *)r, st, force);
     } else if (tr == MPIR_F64) {
-        k_resid_partial<float, double><<<g1, b1, 0, s>>>(n, (const float *)A, lda, (const float *)x, partial, st, force);
+        if (vec) k_resid_partial<float, double, 2><<<g1, b1, 0, s>>>(n, (const float *)A, lda, (const float *)x, partial, st, force);
+        else k_resid_partial<float, double, 1><<<g1, b1, 0, s>>>(n, (const float *)A, lda, (const float *)x, partial, st, force);
         k_resid_reduce<float, double><<<g2, b2, 0, s>>>(n, (const float *)b, (const float *)x, partial, nch, (double *)r, st, force);
     } else {
-        k_resid_partial<float, float><<<g1, b1, 0, s>>>(n, (const float *)A, lda, (const float *)x, partial, st, force);
+        if (vec) k_resid_partial<float, float, 2><<<g1, b1, 0, s>>>(n, (const float *)A, lda, (const float *)x, partial, st, force);
+        else k_resid_partial<float, float, 1><<<g1, b1, 0, s>>>(n, (const float *)A, lda, (const float *)x, partial, st, force);
         k_resid_reduce<float, float><<<g2, b2, 0, s>>>(n, (const float *)b, (const float *)x, partial, nch, (float *)r, st, force);
     }
     return hipGetLastError();
