@@ -8,11 +8,15 @@
 // order, so a workgroup only waits on workgroups that are already running)
 // and owns block row t (from the top for L, from the bottom for U).  It
 // streams its block row of the factor (row-major: contiguous, coalesced),
-// multiplying each 64-column block by the matching solution block as soon
-// as the `done` counter says that block is final, then solves its 64 x 64
-// diagonal block in one wave with register broadcasts, publishes its 64
-// solution entries and advances `done`.  The bytes read are the factor
-// entries of that triangle, once.
+// multiplying each 64-column block by the matching solution block once that
+// block is final, then solves its 64 x 64 diagonal block in one wave with
+// register broadcasts and publishes its 64 solution entries.  Solution
+// entries travel as 64-bit words (32-bit payload | 32-bit epoch, two words
+// for binary64): a reader polls the words themselves, so seeing the epoch
+// means seeing the value -- no counter, no fences.  Only the last dependency
+// block is on the chain: the others are consumed while the previous block
+// row is still being solved.  The bytes read are the factor entries of that
+// triangle, once.
 #include "mpir_internal.h"
 
 namespace mpir {
@@ -40,34 +44,65 @@ template <> __device__ __forceinline__ double bcast<double>(double v, int lane) 
     return __longlong_as_double((long long)(((uint64_t)hi << 32) | lo));
 }
 
-// Wait until `done` exceeds q (relaxed coherent polling, then one acquire
-// fence); returns the observed count, or 0 after the spin limit.
-__device__ __forceinline__ uint32_t wait_done(uint32_t *done, uint32_t q, int lane, bool &timed_out) {
+template <typename Yt> struct YWords;
+template <> struct YWords<float> {
+    static constexpr int K = 1;
+    __device__ static uint32_t part(float v, int) { return __float_as_uint(v); }
+    __device__ static float from(const uint32_t *p) { return __uint_as_float(p[0]); }
+};
+template <> struct YWords<double> {
+    static constexpr int K = 2;
+    __device__ static uint32_t part(double v, int q) {
+        const uint64_t b = (uint64_t)__double_as_longlong(v);
+        return q == 0 ? (uint32_t)b : (uint32_t)(b >> 32);
+    }
+    __device__ static double from(const uint32_t *p) {
+        return __longlong_as_double((long long)(((uint64_t)p[1] << 32) | p[0]));
+    }
+};
+
+// Entry `col` of the solution once published with `epoch` (every lane of
+// the wave polls its own word; the wave leaves when all have arrived).
+template <typename Yt>
+__device__ __forceinline__ Yt get_y(const uint64_t *yw, int64_t col, bool valid, uint32_t epoch,
+                                    bool &timed_out) {
+    constexpr int K = YWords<Yt>::K;
+    uint32_t p[K];
+#pragma unroll
+    for (int q = 0; q < K; ++q) p[q] = 0;
+    bool ok = !valid;
     uint64_t spins = 0;
     for (;;) {
-        uint32_t d = 0;
-        if (lane == 0) d = __hip_atomic_load(done, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-        d = (uint32_t)__shfl((int)d, 0);
-        if (d > q) {
-            __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
-            return d;
+        if (!ok) {
+            ok = true;
+#pragma unroll
+            for (int q = 0; q < K; ++q) {
+                const uint64_t w = __hip_atomic_load(&yw[col * K + q], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+                ok = ok && (uint32_t)(w >> 32) == epoch;
+                p[q] = (uint32_t)w;
+            }
         }
-        if (++spins > kSpinLimit) { timed_out = true; return 0; }
+        if (__all(ok)) break;
+        if (++spins > kSpinLimit) { timed_out = true; break; }
         __builtin_amdgcn_s_sleep(1);
     }
+    return valid ? YWords<Yt>::from(p) : (Yt)0;
 }
 
 template <typename Ft, typename Yt, bool LOWER>
 __global__ __launch_bounds__(256) void k_trsv(const Ft *__restrict__ LU, int64_t n, int64_t ld,
-                                              Yt *__restrict__ y, uint32_t *ticket, uint32_t *done,
-                                              uint32_t *flags, const IrState *st, int force) {
+                                              Yt *__restrict__ y, uint64_t *__restrict__ yw,
+                                              TrsvSync *ts, uint32_t *flags, const IrState *st,
+                                              int force) {
     if (!force && st->done) return;
+    constexpr int K = YWords<Yt>::K;
     __shared__ Yt red[BS][BS + 1];
     __shared__ int s_t;
     __shared__ int s_bad;
     const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
     const int nblk = (int)((n + BS - 1) / BS);
-    if (tid == 0) { s_t = (int)atomicAdd(ticket, 1u); s_bad = 0; }
+    const uint32_t epoch = ts->epoch + (LOWER ? 0u : 1u);
+    if (tid == 0) { s_t = (int)atomicAdd(LOWER ? &ts->ticket_l : &ts->ticket_u, 1u); s_bad = 0; }
     __syncthreads();
     const int t = s_t;
     if (t >= nblk) return;
@@ -90,46 +125,21 @@ __global__ __launch_bounds__(256) void k_trsv(const Ft *__restrict__ LU, int64_t
         }
     }
 
-    // ---- phase 1 (all waves): dependency blocks 0 .. t-2, as they become
-    // final, streamed four at a time (16 factor rows x 4 blocks per lane) ----
+    // ---- phase 1 (all waves): dependency blocks 0 .. t-2 ----
     Yt acc[16];
 #pragma unroll
     for (int r = 0; r < 16; ++r) acc[r] = (Yt)0;
-    const int qlast = t - 1;
-    int q = 0;
-    while (q < qlast) {
-        const uint32_t avail = wait_done(done, (uint32_t)q, lane, timed_out);
-        if (timed_out) break;
-        const int qend = (int)avail < qlast ? (int)avail : qlast;
-        const Ft *base = LU + (i0 + wv * 16) * ld;
-        for (; q + 4 <= qend; q += 4) {
-            Yt yv[4];
-            int64_t col[4];
+    const Ft *base = LU + (i0 + wv * 16) * ld;
+    for (int q = 0; q < t - 1 && !timed_out; ++q) {
+        const int cb = LOWER ? q : nblk - 1 - q;
+        const int64_t col = (int64_t)cb * BS + lane;
+        const bool cv = col < n;
+        Ft lv[16];
 #pragma unroll
-            for (int u = 0; u < 4; ++u) {
-                const int cb = LOWER ? q + u : nblk - 1 - (q + u);
-                col[u] = (int64_t)cb * BS + lane;
-                yv[u] = col[u] < n ? ld_agent(&y[col[u]]) : (Yt)0;
-            }
+        for (int r = 0; r < 16; ++r) lv[r] = (cv && wv * 16 + r < rows) ? base[(int64_t)r * ld + col] : (Ft)0;
+        const Yt yv = get_y<Yt>(yw, col, cv, epoch, timed_out);
 #pragma unroll
-            for (int r = 0; r < 16; ++r) {
-                if (wv * 16 + r < rows) {
-#pragma unroll
-                    for (int u = 0; u < 4; ++u)
-                        if (col[u] < n) acc[r] += (Yt)to_d(base[(int64_t)r * ld + col[u]]) * yv[u];
-                }
-            }
-        }
-        for (; q < qend; ++q) {
-            const int cb = LOWER ? q : nblk - 1 - q;
-            const int64_t col = (int64_t)cb * BS + lane;
-            if (col < n) {
-                const Yt yv = ld_agent(&y[col]);
-#pragma unroll
-                for (int r = 0; r < 16; ++r)
-                    if (wv * 16 + r < rows) acc[r] += (Yt)to_d(base[(int64_t)r * ld + col]) * yv;
-            }
-        }
+        for (int r = 0; r < 16; ++r) acc[r] += (Yt)to_d(lv[r]) * yv;
     }
     if (timed_out) s_bad = 1;
 #pragma unroll
@@ -143,8 +153,7 @@ __global__ __launch_bounds__(256) void k_trsv(const Ft *__restrict__ LU, int64_t
             for (int c = 0; c < BS; ++c) s += red[lane][c];
         bool to = s_bad != 0;
         if (t > 0 && !to) {
-            wait_done(done, (uint32_t)qlast, lane, to);
-            const Yt yl = (lastc + lane < n && !to) ? ld_agent(&y[lastc + lane]) : (Yt)0;
+            const Yt yl = get_y<Yt>(yw, lastc + lane, lastc + lane < n, epoch, to);
 #pragma unroll
             for (int c = 0; c < BS; ++c) s += lrow[c] * bcast(yl, c);
         }
@@ -163,33 +172,37 @@ __global__ __launch_bounds__(256) void k_trsv(const Ft *__restrict__ LU, int64_t
                 if (lane < j) z -= drow[j] * yj;
             }
         }
-        if (lane < rows) st_agent(&y[i0 + lane], z);
+        if (lane < rows) {
+            y[i0 + lane] = z;
+#pragma unroll
+            for (int q = 0; q < K; ++q)
+                __hip_atomic_store(&yw[(i0 + lane) * K + q],
+                                   ((uint64_t)epoch << 32) | YWords<Yt>::part(z, q),
+                                   __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        }
         if (to && lane == 0) s_bad = 1;
     }
     __syncthreads();
-    if (tid == 0) {
-        if (s_bad) atomicOr(flags, (uint32_t)DF_TIMEOUT);
-        __hip_atomic_fetch_add(done, 1u, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
-    }
+    if (tid == 0 && s_bad) atomicOr(flags, (uint32_t)DF_TIMEOUT);
 }
 
 template <typename Ft, typename Yt>
-hipError_t go(const Ft *LU, int64_t n, int64_t ld, Yt *y, TrsvSync *ts, uint32_t *flags,
+hipError_t go(const Ft *LU, int64_t n, int64_t ld, Yt *y, uint64_t *yw, TrsvSync *ts, uint32_t *flags,
               const IrState *st, int force, hipStream_t s) {
     const unsigned nblk = (unsigned)((n + BS - 1) / BS);
-    k_trsv<Ft, Yt, true><<<nblk, 256, 0, s>>>(LU, n, ld, y, &ts->ticket_l, &ts->done_l, flags, st, force);
-    k_trsv<Ft, Yt, false><<<nblk, 256, 0, s>>>(LU, n, ld, y, &ts->ticket_u, &ts->done_u, flags, st, force);
+    k_trsv<Ft, Yt, true><<<nblk, 256, 0, s>>>(LU, n, ld, y, yw, ts, flags, st, force);
+    k_trsv<Ft, Yt, false><<<nblk, 256, 0, s>>>(LU, n, ld, y, yw, ts, flags, st, force);
     return hipGetLastError();
 }
 
 }  // namespace
 
-hipError_t launch_trsv(int tf, const void *LU, int64_t n, int64_t ld, void *y, TrsvSync *ts,
-                       uint32_t *flags, const IrState *st, int force, hipStream_t s) {
+hipError_t launch_trsv(int tf, const void *LU, int64_t n, int64_t ld, void *y, uint64_t *yw,
+                       TrsvSync *ts, uint32_t *flags, const IrState *st, int force, hipStream_t s) {
     if (n <= 0) return hipSuccess;
-    if (tf == MPIR_F64) return go<double, double>((const double *)LU, n, ld, (double *)y, ts, flags, st, force, s);
-    if (tf == MPIR_F32) return go<float, float>((const float *)LU, n, ld, (float *)y, ts, flags, st, force, s);
-    return go<__half, float>((const __half *)LU, n, ld, (float *)y, ts, flags, st, force, s);
+    if (tf == MPIR_F64) return go<double, double>((const double *)LU, n, ld, (double *)y, yw, ts, flags, st, force, s);
+    if (tf == MPIR_F32) return go<float, float>((const float *)LU, n, ld, (float *)y, yw, ts, flags, st, force, s);
+    return go<__half, float>((const __half *)LU, n, ld, (float *)y, yw, ts, flags, st, force, s);
 }
 
 }  // namespace mpir

@@ -146,7 +146,7 @@ __global__ __launch_bounds__(256) void k_scale_permute(int64_t n, const TRt *__r
                                                        TrsvSync *ts, int force) {
     if (!force && st->done) return;
     const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (i == 0) { ts->ticket_l = 0; ts->done_l = 0; ts->ticket_u = 0; ts->done_u = 0; }
+    if (i == 0) { ts->ticket_l = 0; ts->done_l = 0; ts->ticket_u = 0; ts->done_u = 0; ts->epoch += 2u; }
     if (i >= n) return;
     const double inv = 1.0 / st->sigma;      // exact: sigma is a power of two
     const double v = (double)r[perm[i]] * inv;

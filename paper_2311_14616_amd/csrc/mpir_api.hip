@@ -107,6 +107,7 @@ struct mpir_fact_s {
     int nchunks = 0;
     IrState *st = nullptr;
     TrsvSync *ts = nullptr;
+    uint64_t *yw = nullptr;         // epoch-tagged solution words of the solves
     double anorm = 0.0;
     int64_t info = 0;
     double t_factor_ms = 0.0;
@@ -155,6 +156,7 @@ void free_handle(mpir_fact f) {
     hipFree(f->partial);
     hipFree(f->st);
     hipFree(f->ts);
+    hipFree(f->yw);
     for (int i = 0; i < 2; ++i) {
         if (f->evA[i]) hipEventDestroy(f->evA[i]);
         if (f->evB[i]) hipEventDestroy(f->evB[i]);
@@ -180,8 +182,11 @@ mpir_status alloc_handle(mpir_fact f) {
         dalloc(&f->ps, panel_sync_bytes()) != hipSuccess || dalloc(&f->r, n * 8) != hipSuccess ||
         dalloc(&f->rhat, n * 8) != hipSuccess ||
         dalloc(&f->partial, (size_t)f->nchunks * n * 8) != hipSuccess ||
-        dalloc(&f->st, sizeof(IrState)) != hipSuccess || dalloc(&f->ts, sizeof(TrsvSync)) != hipSuccess)
+        dalloc(&f->st, sizeof(IrState)) != hipSuccess || dalloc(&f->ts, sizeof(TrsvSync)) != hipSuccess ||
+        dalloc(&f->yw, (size_t)n * 16) != hipSuccess)
         return MPIR_ERR_ALLOC;
+    if (hipMemset(f->ts, 0, sizeof(TrsvSync)) != hipSuccess || hipMemset(f->yw, 0, (size_t)n * 16) != hipSuccess)
+        return MPIR_ERR_HIP;
     // second stream (default priority) and ordering events for the look-ahead
     if (hipStreamCreateWithFlags(&f->stream2, hipStreamNonBlocking) != hipSuccess) return MPIR_ERR_HIP;
     for (int i = 0; i < 2; ++i)
@@ -469,8 +474,8 @@ mpir_status mpir_solve(mpir_fact f, const void *db, void *dx) {
     HIPCHK(launch_scale_permute(n, f->tr, f->tf, f->r, f->perm, f->rhat, f->st, f->ts, 1, s));
     {
         ProfScope ps_(2, 2.0 * (double)n * n, s);
-        HIPCHK(launch_trsv(f->tf, factors_ptr(f), n, f->tf == MPIR_F16 ? n : f->ld, f->rhat, f->ts,
-                           f->flags_d, f->st, 1, s));
+        HIPCHK(launch_trsv(f->tf, factors_ptr(f), n, f->tf == MPIR_F16 ? n : f->ld, f->rhat, f->yw,
+                           f->ts, f->flags_d, f->st, 1, s));
     }
     HIPCHK(launch_update(n, f->tw, f->tf, f->rhat, dx, f->st, 1, s));
     uint32_t flags = 0;
@@ -520,7 +525,7 @@ mpir_status mpir_ir_solve(mpir_fact f, const void *db, void *dx, const mpir_term
         HIPCHK(launch_scale_permute(n, f->tr, f->tf, f->r, f->perm, f->rhat, f->st, f->ts, 0, s));
         {
             ProfScope ps_(2, 2.0 * (double)n * n, s);
-            HIPCHK(launch_trsv(f->tf, LU, n, lld, f->rhat, f->ts, f->flags_d, f->st, 0, s));
+            HIPCHK(launch_trsv(f->tf, LU, n, lld, f->rhat, f->yw, f->ts, f->flags_d, f->st, 0, s));
         }
         HIPCHK(launch_update(n, f->tw, f->tf, f->rhat, dx, f->st, 0, s));
         {

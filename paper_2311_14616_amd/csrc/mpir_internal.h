@@ -49,9 +49,12 @@ struct IrState {
     double dhist[MPIR_HIST_MAX];
 };
 
-// Counters used by the ticket-ordered triangular solves (zeroed per solve).
+// Ticket counters of the ordered triangular solves (zeroed per solve) and the
+// epoch of the solution words (advanced by 2 per solve, never reset: a word
+// written by an earlier solve can never carry the current epoch).
 struct TrsvSync {
     uint32_t ticket_l, done_l, ticket_u, done_u;
+    uint32_t epoch;
 };
 
 // Bounded spin: ~seconds at most; an expired wait raises DF_TIMEOUT and the
@@ -168,7 +171,8 @@ hipError_t launch_batched(int tw, int tf, const BatchSys *sys, const int32_t *or
 
 // a7: triangular solves with the packed factors (row-major, TF storage).
 // y is float for TF in {F32, F16}, double for F64.
-hipError_t launch_trsv(int tf, const void *LU, int64_t n, int64_t ld, void *y,
+// yw: n * 2 epoch-tagged 64-bit words (zeroed once at allocation).
+hipError_t launch_trsv(int tf, const void *LU, int64_t n, int64_t ld, void *y, uint64_t *yw,
                        TrsvSync *ts, uint32_t *flags, const IrState *st, int force,
                        hipStream_t s);
 
