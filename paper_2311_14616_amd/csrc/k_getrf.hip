@@ -14,24 +14,27 @@
 namespace mpir {
 
 constexpr int kLeafMaxW = 32;     // columns per leaf
-constexpr int kLeafT = 1024;      // threads per leaf workgroup = rows it owns
-constexpr int kLeafMaxG = 64;     // workgroups per leaf (one wave reads all slots)
+constexpr int kLeafNT = 512;      // threads per leaf workgroup
+// rows per thread: two binary32 rows or one binary64 row (register budget)
+template <typename W> constexpr int leaf_rt() { return sizeof(W) == 4 ? 2 : 1; }
+template <typename W> constexpr int leaf_rows() { return kLeafNT * leaf_rt<W>(); }
+constexpr int kLeafMaxG = 64;     // workgroups per leaf (one wave reads every slot)
 
 // Exchange area of the cooperative leaf.  Every value travels in 64-bit
 // words (32-bit payload | 32-bit epoch), so a reader that sees the current
-// epoch in a word also sees its payload: no separate barrier, no fences.
-// Per column parity and workgroup: a header (|value| in 1-2 words, row
-// index) and the candidate row (1-2 words per column); plus the old
-// diagonal row posted by its owner.
+// epoch in a word also sees its payload: no barrier counter, no fences.
+// Per column parity and workgroup one slot holds the candidate header
+// (|value| in 2 words, row), the candidate row (1-2 words per column) and,
+// in workgroup 0's slot, the old row j -- all read in one round trip.
 constexpr int kHeadWords = 4;
 constexpr int kRowWords = 2 * kLeafMaxW;
 struct LeafSlot {
     uint64_t head[kHeadWords];
     uint64_t row[kRowWords];
+    uint64_t diag[kRowWords];
 };
 struct PanelSync {
     LeafSlot slot[2][kLeafMaxG];
-    uint64_t diag[2][kRowWords];
 };
 
 size_t panel_sync_bytes() { return sizeof(PanelSync); }
@@ -50,12 +53,14 @@ __device__ __forceinline__ uint64_t get_word(const uint64_t *p) {
 }
 __device__ __forceinline__ bool word_ok(uint64_t w, uint32_t epoch) { return (uint32_t)(w >> 32) == epoch; }
 
-// Values of type W split into 32-bit payloads (1 for float, 2 for double).
+// Values of type W as 32-bit parts (1 for float, 2 for double).
 template <typename W> struct Words;
 template <> struct Words<float> {
     static constexpr int K = 1;
     __device__ static uint32_t part(float v, int) { return __float_as_uint(v); }
-    __device__ static float join(const uint32_t *p) { return __uint_as_float(p[0]); }
+    __device__ static float from(uint32_t lo, uint32_t) { return __uint_as_float(lo); }
+    __device__ static float get(const uint32_t *w, int c) { return __uint_as_float(w[c]); }
+    __device__ static void put(uint32_t *w, int c, float v) { w[c] = __float_as_uint(v); }
 };
 template <> struct Words<double> {
     static constexpr int K = 2;
@@ -63,213 +68,308 @@ template <> struct Words<double> {
         const uint64_t b = (uint64_t)__double_as_longlong(v);
         return q == 0 ? (uint32_t)b : (uint32_t)(b >> 32);
     }
-    __device__ static double join(const uint32_t *p) {
-        return __longlong_as_double((long long)(((uint64_t)p[1] << 32) | p[0]));
+    __device__ static double from(uint32_t lo, uint32_t hi) {
+        return __longlong_as_double((long long)(((uint64_t)hi << 32) | lo));
+    }
+    __device__ static double get(const uint32_t *w, int c) {
+        const uint2 x = reinterpret_cast<const uint2 *>(w)[c];
+        return from(x.x, x.y);
+    }
+    __device__ static void put(uint32_t *w, int c, double v) {
+        reinterpret_cast<uint2 *>(w)[c] = make_uint2(part(v, 0), part(v, 1));
     }
 };
 
-__device__ __forceinline__ bool better(double v, int i, double bv, int bi) {
-    return v > bv || (v == bv && i < bi);
-}
+// Pivot candidate: larger |value| wins, then the smaller row (the first
+// maximum).  Binary32: one 64-bit key, |v| bits above the complemented row
+// (|v| >= 0 orders as its bits).  Binary64: the |v| bits and the row.
+template <typename W> struct Cand;
+template <> struct Cand<float> {
+    uint64_t key;
+    __device__ static Cand none() { return {0ull}; }
+    __device__ static Cand make(float v, int row) {
+        return {((uint64_t)__float_as_uint(fabsf(v)) << 32) | (uint64_t)(0xffffffffu - (uint32_t)row)};
+    }
+    __device__ bool valid() const { return key != 0ull; }
+    __device__ int row() const { return (int)(0xffffffffu - (uint32_t)key); }
+    __device__ uint64_t vbits() const { return key >> 32; }
+    __device__ static Cand from_words(uint64_t vb, int row) { return {(vb << 32) | (uint64_t)(0xffffffffu - (uint32_t)row)}; }
+    __device__ void take_max(const Cand &o) { key = o.key > key ? o.key : key; }
+    __device__ Cand shfl_xor(int off) const { return {(uint64_t)__shfl_xor((long long)key, off)}; }
+};
+template <> struct Cand<double> {
+    uint64_t vb;
+    int r;
+    __device__ static Cand none() { return {0ull, 0x7fffffff}; }
+    __device__ static Cand make(double v, int row) {
+        return {(uint64_t)__double_as_longlong(fabs(v)), row};
+    }
+    __device__ bool valid() const { return r != 0x7fffffff; }
+    __device__ int row() const { return r; }
+    __device__ uint64_t vbits() const { return vb; }
+    __device__ static Cand from_words(uint64_t b, int row) { return {b, row}; }
+    __device__ void take_max(const Cand &o) {
+        if (o.vb > vb || (o.vb == vb && o.r < r)) { vb = o.vb; r = o.r; }
+    }
+    __device__ Cand shfl_xor(int off) const {
+        return {(uint64_t)__shfl_xor((long long)vb, off), __shfl_xor(r, off)};
+    }
+};
 
 // Leaf factorization of rows [k0, n) x columns [k0, k0+w) of the working
-// array.  Workgroup g owns relative rows [g*1024, g*1024+1024), one row per
-// thread, the w leaf entries of the row in registers.  For every column:
-// local argmax (first maximum), candidate posted as epoch-tagged words,
-// winner chosen identically by every workgroup, swap, scale, rank-1 update.
-// F16: the pivot row is rounded to binary16 when it becomes the pivot row,
-// each multiplier to binary16 when formed (products of binary16 numbers are
-// exact in binary32).
+// array.  Workgroup g owns relative rows [g*R, g*R+R) (R = 512 per row of a
+// thread: 1024 binary32, 512 binary64), thread t rows g*R + t (+ 512), the
+// 32 leaf entries of each in registers.
+// The registers rotate: before column j, R[c] holds column j+c for
+// c < 32-j and the finished column c-(32-j) above; each column shifts them
+// left by one as it updates, so the column loop is not unrolled and every
+// register index is static.  Per column: argmax (first maximum) in the
+// wave, then over the waves; the best row of each workgroup is posted with
+// the old row j in one slot of epoch-tagged words; every workgroup reads
+// every slot in one round trip and picks the same winner; swap; scale;
+// rank-1 update.  F16: the pivot row is rounded to binary16 when it becomes
+// the pivot row, each multiplier to binary16 when formed (products of
+// binary16 numbers are exact in binary32).
 template <typename W, bool F16>
-__global__ __launch_bounds__(kLeafT) void k_leaf(W *__restrict__ a, int64_t n, int64_t ld,
-                                                 int64_t k0, int w, int G,
-                                                 int32_t *__restrict__ ipiv, int64_t *info,
-                                                 PanelSync *ps, uint32_t base, uint32_t *flags) {
+__global__ __launch_bounds__(kLeafNT) void k_leaf(W *__restrict__ a, int64_t n, int64_t ld,
+                                                  int64_t k0, int w, int G,
+                                                  int32_t *__restrict__ ipiv, int64_t *info,
+                                                  PanelSync *ps, uint32_t base, uint32_t *flags) {
     using Wd = Words<W>;
+    using Cd = Cand<W>;
     constexpr int K = Wd::K;
-    __shared__ double red_v[kLeafT / 64];
-    __shared__ int red_i[kLeafT / 64];
-    __shared__ W crow[kLeafMaxW];      // this workgroup's candidate row
-    __shared__ W jrow[kLeafMaxW];      // row j (if owned here)
-    __shared__ W prow[kLeafMaxW];      // pivot row
-    __shared__ W orow[kLeafMaxW];      // old row j
-    __shared__ double s_bv;
-    __shared__ int s_bi, s_p, s_bad;
+    constexpr int C = kLeafMaxW;
+    constexpr int NWV = kLeafNT / 64;
+    __shared__ Cd red[NWV];
+    // rows in LDS as 32-bit words (value c in words K c .. K c + K-1)
+    __shared__ __align__(16) uint32_t crow[C * K];   // this workgroup's candidate row (rotated)
+    __shared__ __align__(16) uint32_t prow[C * K];   // pivot row (rotated; F16: current part rounded)
+    __shared__ __align__(16) uint32_t pupd[C * K];   // pivot row with the finished part zeroed
+    __shared__ __align__(16) uint32_t orow[C * K];   // old row j
+    __shared__ int s_p, s_bad;
 
     const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
     const int64_t m = n - k0;
-    const int64_t r0 = (int64_t)blockIdx.x * kLeafT;
-    const int rows = (int)((m - r0) < kLeafT ? (m - r0) : kLeafT);
+    constexpr int kLeafRT = leaf_rt<W>();
+    const int64_t r0 = (int64_t)blockIdx.x * leaf_rows<W>();
     // an earlier launch already timed out: every workgroup returns at once
     if (__hip_atomic_load(flags, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) & DF_TIMEOUT) return;
     if (tid == 0) s_bad = 0;
-    if (tid < kLeafMaxW) { prow[tid] = (W)0; orow[tid] = (W)0; crow[tid] = (W)0; jrow[tid] = (W)0; }
-    __syncthreads();
-    const bool mine = tid < rows;
-    const int64_t rr = r0 + tid;               // relative row of this thread
-    W v[kLeafMaxW];
-#pragma unroll
-    for (int c = 0; c < kLeafMaxW; ++c) v[c] = (W)0;
-    if (mine) {
-        const W *src = a + (k0 + rr) * ld + k0;
-#pragma unroll
-        for (int c = 0; c < kLeafMaxW; ++c)
-            if (c < w) v[c] = src[c];
-    }
 
+    W v[kLeafRT][C];
+    int rr[kLeafRT];
+    bool mine[kLeafRT];
 #pragma unroll
-    for (int j = 0; j < kLeafMaxW; ++j) {
-        if (j >= w) break;
+    for (int q = 0; q < kLeafRT; ++q) {
+        rr[q] = (int)r0 + tid + q * kLeafNT;
+        mine[q] = rr[q] < m;
+#pragma unroll
+        for (int c = 0; c < C; ++c) v[q][c] = (W)0;
+        if (mine[q]) {
+            const W *src = a + (k0 + rr[q]) * ld + k0;
+#pragma unroll
+            for (int c = 0; c < C; ++c)
+                if (c < w) v[q][c] = src[c];
+        }
+    }
+    __syncthreads();
+
+#pragma unroll 1
+    for (int j = 0; j < w; ++j) {
         const uint32_t epoch = base + (uint32_t)j + 1u;
         const int par = j & 1;
-        // ---- local argmax of |a_rj| over owned rows r >= j ----
-        double bv = (mine && rr >= j) ? fabs((double)v[j]) : -1.0;
-        int bi = (mine && rr >= j) ? (int)rr : INT_MAX;
-        for (int off = 32; off > 0; off >>= 1) {
-            const double ov = __shfl_xor(bv, off);
-            const int oi = __shfl_xor(bi, off);
-            if (better(ov, oi, bv, bi)) { bv = ov; bi = oi; }
-        }
-        if (lane == 0) { red_v[wv] = bv; red_i[wv] = bi; }
-        __syncthreads();
-        if (wv == 0) {
-            bv = lane < kLeafT / 64 ? red_v[lane] : -1.0;
-            bi = lane < kLeafT / 64 ? red_i[lane] : INT_MAX;
-            for (int off = 8; off > 0; off >>= 1) {
-                const double ov = __shfl_xor(bv, off);
-                const int oi = __shfl_xor(bi, off);
-                if (better(ov, oi, bv, bi)) { bv = ov; bi = oi; }
-            }
-            if (lane == 0) { s_bv = bv; s_bi = bi; }
-        }
-        __syncthreads();
-        if (mine && rr == s_bi) {
+        const int cur = C - j;             // rotated positions [0, cur) are current
+        // ---- argmax over the workgroup's rows r >= j ----
+        Cd best = Cd::none();
 #pragma unroll
-            for (int c = 0; c < kLeafMaxW; ++c) crow[c] = v[c];
-        }
-        if (mine && rr == j) {
+        for (int q = 0; q < kLeafRT; ++q)
+            if (mine[q] && rr[q] >= j) best.take_max(Cd::make(v[q][0], rr[q]));
+        for (int off = 32; off > 0; off >>= 1) best.take_max(best.shfl_xor(off));
+        if (lane == 0) red[wv] = best;
+        __syncthreads();                                   // (A)
+        best = red[0];
 #pragma unroll
-            for (int c = 0; c < kLeafMaxW; ++c) jrow[c] = v[c];
-        }
-        __syncthreads();
-
+        for (int q = 1; q < NWV; ++q) best.take_max(red[q]);
+        const int bi = best.row();
         if (G == 1) {
-            if (tid < kLeafMaxW) { prow[tid] = crow[tid]; orow[tid] = jrow[tid]; }
-            if (tid == 0) s_p = s_bi;
-        } else if (wv == 0) {
-            // ---- post this workgroup's candidate and (if owned) row j ----
-            LeafSlot *my = &ps->slot[par][blockIdx.x];
-            const bool own_j = j >= r0 && j < r0 + rows;
-            if (lane < w) {
 #pragma unroll
-                for (int q = 0; q < K; ++q) {
-                    put_word(&my->row[lane * K + q], Wd::part(crow[lane], q), epoch);
-                    if (own_j) put_word(&ps->diag[par][lane * K + q], Wd::part(jrow[lane], q), epoch);
+            for (int q = 0; q < kLeafRT; ++q) {
+                if (mine[q] && rr[q] == bi) {
+#pragma unroll
+                    for (int c = 0; c < C; ++c) {
+                        const W x = (F16 && c < cur) ? (W)round_f16((float)v[q][c]) : v[q][c];
+                        Wd::put(prow, c, x);
+                        Wd::put(pupd, c, c < cur ? x : (W)0);
+                    }
+                }
+                if (mine[q] && rr[q] == j) {
+#pragma unroll
+                    for (int c = 0; c < C; ++c) Wd::put(orow, c, v[q][c]);
                 }
             }
-            if (lane == 32) {
-                const uint64_t b = (uint64_t)__double_as_longlong(s_bv);
-                put_word(&my->head[0], (uint32_t)b, epoch);
-                put_word(&my->head[1], (uint32_t)(b >> 32), epoch);
-                put_word(&my->head[2], (uint32_t)s_bi, epoch);
+            if (tid == 0) s_p = bi;
+            __syncthreads();                               // (B)
+        } else {
+#pragma unroll
+            for (int q = 0; q < kLeafRT; ++q) {
+                if (mine[q] && rr[q] == bi) {
+#pragma unroll
+                    for (int c = 0; c < C; ++c) Wd::put(crow, c, v[q][c]);
+                }
+                if (mine[q] && rr[q] == j) {
+#pragma unroll
+                    for (int c = 0; c < C; ++c) Wd::put(orow, c, v[q][c]);
+                }
             }
-            // ---- read every workgroup's header (lane g <-> workgroup g) ----
-            double gv = -1.0;
-            int gi = INT_MAX, gw = 0;
-            {
+            __syncthreads();                               // (B)
+            // Waves 0 .. K-1 each move 32 of the 32*K words of a row: wave
+            // wv posts and reads words [32 wv, 32 wv + 32) of every slot
+            // (value c lives in words K c .. K c + K-1, low word first).
+            if (wv < K) {
+                LeafSlot *my = &ps->slot[par][blockIdx.x];
+                const bool own_j = blockIdx.x == 0;        // relative row j < 32 <= R
+                const int wb0 = wv * 32;
+                const uint32_t *cw = crow;
+                const uint32_t *ow = orow;
+                if (lane < 32) {
+                    put_word(&my->row[wb0 + lane], cw[wb0 + lane], epoch);
+                    if (own_j) put_word(&my->diag[wb0 + lane], ow[wb0 + lane], epoch);
+                }
+                if (wv == 0 && lane == 32) {
+                    const uint64_t vb = best.vbits();
+                    put_word(&my->head[0], (uint32_t)vb, epoch);
+                    put_word(&my->head[1], (uint32_t)(vb >> 32), epoch);
+                    put_word(&my->head[2], (uint32_t)(best.valid() ? bi : 0x7fffffff), epoch);
+                }
+                // ---- every slot (lane g <-> workgroup g), one round trip ----
+                uint32_t rw[32];
+#pragma unroll
+                for (int q = 0; q < 32; ++q) rw[q] = 0;
+                uint32_t dw = 0;
+                const LeafSlot *sl = &ps->slot[par][lane < G ? lane : 0];
+                const LeafSlot *s0 = &ps->slot[par][0];
+                bool okh = lane >= G, okr = lane >= G, okd = own_j || lane >= 32;
                 uint64_t h0 = 0, h1 = 0, h2 = 0;
-                bool ok = lane >= G;
                 uint64_t spins = 0;
                 for (;;) {
-                    if (!ok) {
-                        const LeafSlot *sl = &ps->slot[par][lane];
+                    if (!okh) {
                         h0 = get_word(&sl->head[0]);
                         h1 = get_word(&sl->head[1]);
                         h2 = get_word(&sl->head[2]);
-                        ok = word_ok(h0, epoch) && word_ok(h1, epoch) && word_ok(h2, epoch);
+                        okh = word_ok(h0, epoch) && word_ok(h1, epoch) && word_ok(h2, epoch);
                     }
-                    if (__all(ok)) break;
-                    if (++spins > kSpinLimit) { if (lane == 0) s_bad = 1; break; }
-                    __builtin_amdgcn_s_sleep(1);
-                }
-                if (lane < G && ok) {
-                    gv = __longlong_as_double((long long)((h1 << 32) | (uint32_t)h0));
-                    gi = (int)(uint32_t)h2;
-                    gw = lane;
-                }
-            }
-            for (int off = 32; off > 0; off >>= 1) {
-                const double ov = __shfl_xor(gv, off);
-                const int oi = __shfl_xor(gi, off);
-                const int og = __shfl_xor(gw, off);
-                if (better(ov, oi, gv, gi)) { gv = ov; gi = oi; gw = og; }
-            }
-            // ---- winner's row and the old row j ----
-            {
-                uint32_t pw[K], ow[K];
-                bool ok = lane >= w;
-                uint64_t spins = 0;
-                for (;;) {
-                    if (!ok) {
-                        ok = true;
+                    if (!okr) {
+                        bool ok = true;
 #pragma unroll
-                        for (int q = 0; q < K; ++q) {
-                            const uint64_t x = get_word(&ps->slot[par][gw].row[lane * K + q]);
-                            const uint64_t y = get_word(&ps->diag[par][lane * K + q]);
-                            ok = ok && word_ok(x, epoch) && word_ok(y, epoch);
-                            pw[q] = (uint32_t)x;
-                            ow[q] = (uint32_t)y;
+                        for (int q = 0; q < 32; ++q) {
+                            const uint64_t x = get_word(&sl->row[wb0 + q]);
+                            ok = ok && word_ok(x, epoch);
+                            rw[q] = (uint32_t)x;
                         }
+                        okr = ok;
                     }
-                    if (__all(ok)) break;
+                    if (!okd) {
+                        const uint64_t x = get_word(&s0->diag[wb0 + lane]);
+                        okd = word_ok(x, epoch);
+                        dw = (uint32_t)x;
+                    }
+                    if (__all(okh && okr && okd)) break;
                     if (++spins > kSpinLimit) { if (lane == 0) s_bad = 1; break; }
                     __builtin_amdgcn_s_sleep(1);
                 }
-                if (lane < w) { prow[lane] = Wd::join(pw); orow[lane] = Wd::join(ow); }
+                Cd gbest = Cd::none();
+                if (lane < G && okh) {
+                    const int hr = (int)(uint32_t)h2;
+                    if (hr != 0x7fffffff)
+                        gbest = Cd::from_words(((uint64_t)(uint32_t)h1 << 32) | (uint32_t)h0, hr);
+                }
+                Cd wbst = gbest;
+                for (int off = 32; off > 0; off >>= 1) wbst.take_max(wbst.shfl_xor(off));
+                const int p = wbst.row();
+                // the lane holding the winning candidate writes its words of
+                // the pivot row
+                if (lane < G && gbest.valid() && gbest.row() == p) {
+                    uint32_t *pw = prow;
+                    uint32_t *uw = pupd;
+#pragma unroll
+                    for (int q = 0; q < 32; ++q) {
+                        const int c = (wb0 + q) / K;
+                        uint32_t x = rw[q];
+                        if (F16 && c < cur) x = __float_as_uint(round_f16(__uint_as_float(x)));
+                        pw[wb0 + q] = x;
+                        uw[wb0 + q] = c < cur ? x : 0u;
+                    }
+                }
+                if (!own_j && lane < 32) orow[wb0 + lane] = dw;
+                if (wv == 0 && lane == 0) s_p = p;
             }
-            if (lane == 0) s_p = gi;
+            __syncthreads();                               // (C)
         }
-        __syncthreads();
         const int p = s_p;
-        if (s_bad || p == INT_MAX) {
+        if (s_bad || p == 0x7fffffff) {
             if (tid == 0) atomicOr(flags, (uint32_t)DF_TIMEOUT);
             break;
         }
-        if (F16 && tid < kLeafMaxW && tid >= j) prow[tid] = (W)round_f16((float)prow[tid]);
-        __syncthreads();
         // ---- swap rows j and p, record the pivot ----
-        if (mine && p != j && rr == p) {
 #pragma unroll
-            for (int c = 0; c < kLeafMaxW; ++c) v[c] = orow[c];
-        }
-        if (mine && rr == j) {
+        for (int q = 0; q < kLeafRT; ++q) {
+            if (mine[q] && p != j && rr[q] == p) {
 #pragma unroll
-            for (int c = 0; c < kLeafMaxW; ++c) v[c] = prow[c];
-        }
-        if (blockIdx.x == 0 && tid == 0) {
-            ipiv[k0 + j] = (int32_t)(k0 + p);
-            if (prow[j] == (W)0 && *info == 0) *info = k0 + j + 1;
-        }
-        // ---- scale and rank-1 update of the rows below the pivot ----
-        const W piv = prow[j];
-        if (mine && rr > j && piv != (W)0) {
-            W l = v[j] / piv;
-            if (F16) l = (W)round_f16((float)l);
-            v[j] = l;
+                for (int c = 0; c < C; ++c) v[q][c] = Wd::get(orow, c);
+            }
+            if (mine[q] && rr[q] == j) {
 #pragma unroll
-            for (int c = j + 1; c < kLeafMaxW; ++c) {
-                const W prod = l * prow[c];
-                v[c] = v[c] - prod;
+                for (int c = 0; c < C; ++c) v[q][c] = Wd::get(prow, c);
             }
         }
-        // prow/orow/crow are rewritten only after the next column's first
-        // __syncthreads, which every thread reaches after this point.
-    }
-    if (mine) {
-        W *dst = a + (k0 + rr) * ld + k0;
+        const W piv = Wd::get(prow, 0);
+        if (blockIdx.x == 0 && tid == 0) {
+            ipiv[k0 + j] = (int32_t)(k0 + p);
+            if (piv == (W)0 && *info == 0) *info = k0 + j + 1;
+        }
+        // ---- scale, rank-1 update and rotate by one ----
+        // (with a zero pivot the column below it is zero: no update)
 #pragma unroll
-        for (int c = 0; c < kLeafMaxW; ++c)
-            if (c < w) dst[c] = v[c];
+        for (int q = 0; q < kLeafRT; ++q) {
+            if (rr[q] > j && piv != (W)0) {
+                W l = v[q][0] / piv;
+                if (F16) l = (W)round_f16((float)l);
+#pragma unroll
+                for (int c = 0; c < C - 1; ++c) {
+                    const W prod = l * Wd::get(pupd, c + 1);
+                    v[q][c] = v[q][c + 1] - prod;
+                }
+                v[q][C - 1] = l;
+            } else {
+                const W x0 = v[q][0];
+#pragma unroll
+                for (int c = 0; c < C - 1; ++c) v[q][c] = v[q][c + 1];
+                v[q][C - 1] = x0;
+            }
+        }
+        (void)cur;
+        // red/crow/prow/pupd/orow are rewritten only after the next (A),
+        // which every thread reaches after its reads here.
+    }
+    // w < 32: rotate the remaining 32 - w places so that v[c] is column c
+#pragma unroll 1
+    for (int t = w; t < C; ++t) {
+#pragma unroll
+        for (int q = 0; q < kLeafRT; ++q) {
+            const W x0 = v[q][0];
+#pragma unroll
+            for (int c = 0; c < C - 1; ++c) v[q][c] = v[q][c + 1];
+            v[q][C - 1] = x0;
+        }
+    }
+#pragma unroll
+    for (int q = 0; q < kLeafRT; ++q) {
+        if (mine[q]) {
+            W *dst = a + (k0 + rr[q]) * ld + k0;
+#pragma unroll
+            for (int c = 0; c < C; ++c)
+                if (c < w) dst[c] = v[q][c];
+        }
     }
 }
 
@@ -401,17 +501,17 @@ template <typename W, bool F16>
 hipError_t leaf_go(W *a, int64_t n, int64_t ld, int64_t k0, int w, int32_t *ipiv, int64_t *info,
                    PanelSync *ps, uint32_t *host_base, uint32_t *flags, hipStream_t s) {
     const int64_t m = n - k0;
-    const int64_t G64 = (m + kLeafT - 1) / kLeafT;
+    const int64_t G64 = (m + leaf_rows<W>() - 1) / leaf_rows<W>();
     if (G64 > kLeafMaxG) return hipErrorInvalidValue;
     const int G = (int)G64;
     uint32_t base = *host_base;
     if (G == 1) {
-        k_leaf<W, F16><<<1, kLeafT, 0, s>>>(a, n, ld, k0, w, G, ipiv, info, ps, base, flags);
+        k_leaf<W, F16><<<1, kLeafNT, 0, s>>>(a, n, ld, k0, w, G, ipiv, info, ps, base, flags);
         return hipGetLastError();
     }
     void *args[] = {&a, (void *)&n, (void *)&ld, (void *)&k0, (void *)&w, (void *)&G,
                     &ipiv, &info, &ps, &base, &flags};
-    hipError_t e = hipLaunchCooperativeKernel((const void *)k_leaf<W, F16>, dim3(G), dim3(kLeafT),
+    hipError_t e = hipLaunchCooperativeKernel((const void *)k_leaf<W, F16>, dim3(G), dim3(kLeafNT),
                                               args, 0, s);
     if (e == hipSuccess) *host_base = base + (uint32_t)w;
     return e;
@@ -420,9 +520,8 @@ hipError_t leaf_go(W *a, int64_t n, int64_t ld, int64_t k0, int w, int32_t *ipiv
 }  // namespace
 
 int leaf_max_rows(int mode) {
-    (void)mode;
     const int gmax = num_cus() < kLeafMaxG ? num_cus() : kLeafMaxG;
-    return gmax * kLeafT;
+    return gmax * (mode == LU_F64 ? leaf_rows<double>() : leaf_rows<float>());
 }
 
 hipError_t launch_leaf(int mode, void *a, int64_t n, int64_t ld, int64_t k0, int w, int32_t *ipiv,

@@ -295,9 +295,19 @@ hipError_t apply_step(mpir_fact f, int64_t K, int w, int64_t c0, int64_t c1, hip
 // factors panel p+1 (the latency-bound part), so the panel chain is hidden
 // behind the matrix-core work.  The two streams touch disjoint columns; one
 // event per stream and step parity orders them.
+// MPIR_LOOKAHEAD=0 runs the whole factorization on the caller's stream.
+bool lookahead_enabled() {
+    static int env = -1;
+    if (env < 0) {
+        const char *e = std::getenv("MPIR_LOOKAHEAD");
+        env = (e && e[0] == '0') ? 0 : 1;
+    }
+    return env == 1;
+}
+
 mpir_status getrf(mpir_fact f) {
     const int64_t n = f->n;
-    hipStream_t s = f->stream, s2 = f->stream2;
+    hipStream_t s = f->stream, s2 = lookahead_enabled() ? f->stream2 : f->stream;
     const int nb = panel_width(f->mode);
     if (n > leaf_max_rows(f->mode)) return MPIR_ERR_ARG;
     hipEvent_t *evA = f->evA, *evB = f->evB;
