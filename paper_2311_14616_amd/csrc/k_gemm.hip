@@ -316,20 +316,41 @@ template <> struct Cfg32<false> { static constexpr int BM = 64, BN = 64, BK = 16
 template <> struct Cfg32<true> { static constexpr int BM = 128, BN = 64, BK = 32, NBUF = 2; };
 struct Cfg64 { static constexpr int BM = 64, BN = 64, BK = 16; };
 
+// Dynamic LDS that limits a kernel with `stat` bytes of static LDS to at
+// most `cap` workgroups per compute unit (160 KB of LDS each); 0 = no limit.
+int cap_pad(const void *fn, int cap) {
+    if (cap <= 0) return 0;
+    hipFuncAttributes at;
+    if (hipFuncGetAttributes(&at, fn) != hipSuccess) return 0;
+    const int stat = (int)at.sharedSizeBytes, lds = 160 * 1024;
+    const int want = lds / (cap + 1) + 1024;     // cap + 1 must not fit
+    if (want <= stat || want * cap > lds) return 0;
+    return want - stat;
+}
+
 template <bool HALF>
 void go32(bool vec, float *a, int64_t ld, int64_t r0, int64_t m, int64_t c0, int64_t nc, int64_t k,
-          int64_t kk, hipStream_t s) {
+          int64_t kk, int cap, hipStream_t s) {
     using C = Cfg32<HALF>;
     const int64_t tiles_m = (m + C::BM - 1) / C::BM, tiles_n = (nc + C::BN - 1) / C::BN;
     const int64_t nblk = tiles_m * tiles_n;
-    if (vec) k_gemm_32<HALF, true, C::BM, C::BN, C::BK, C::NBUF><<<(unsigned)nblk, 256, 0, s>>>(a, ld, r0, m, c0, nc, k, kk, (int)tiles_n, (int)nblk);
-    else k_gemm_32<HALF, false, C::BM, C::BN, C::BK, C::NBUF><<<(unsigned)nblk, 256, 0, s>>>(a, ld, r0, m, c0, nc, k, kk, (int)tiles_n, (int)nblk);
+    auto kv = k_gemm_32<HALF, true, C::BM, C::BN, C::BK, C::NBUF>;
+    auto ks = k_gemm_32<HALF, false, C::BM, C::BN, C::BK, C::NBUF>;
+    static int pad_v[9] = {-1, -1, -1, -1, -1, -1, -1, -1, -1}, pad_s[9] = {-1, -1, -1, -1, -1, -1, -1, -1, -1};
+    const int ci = cap < 0 ? 0 : cap > 8 ? 8 : cap;
+    if (vec) {
+        if (pad_v[ci] < 0) pad_v[ci] = cap_pad((const void *)kv, ci);
+        kv<<<(unsigned)nblk, 256, pad_v[ci], s>>>(a, ld, r0, m, c0, nc, k, kk, (int)tiles_n, (int)nblk);
+    } else {
+        if (pad_s[ci] < 0) pad_s[ci] = cap_pad((const void *)ks, ci);
+        ks<<<(unsigned)nblk, 256, pad_s[ci], s>>>(a, ld, r0, m, c0, nc, k, kk, (int)tiles_n, (int)nblk);
+    }
 }
 
 }  // namespace
 
 hipError_t launch_gemm_update(int mode, void *a, int64_t ld, int64_t r0, int64_t m, int64_t c0,
-                              int64_t nc, int64_t k, int64_t kk, hipStream_t s) {
+                              int64_t nc, int64_t k, int64_t kk, int cap, hipStream_t s) {
     if (m <= 0 || nc <= 0 || kk <= 0) return hipSuccess;
     if ((m / 64 + 1) * (nc / 64 + 1) > 0x7fffffffll) return hipErrorInvalidValue;
     // 16-byte vector loads need every row start and offset 16-byte aligned
@@ -339,13 +360,22 @@ hipError_t launch_gemm_update(int mode, void *a, int64_t ld, int64_t r0, int64_t
         using C = Cfg64;
         const int64_t tiles_m = (m + C::BM - 1) / C::BM, tiles_n = (nc + C::BN - 1) / C::BN;
         const int64_t nblk = tiles_m * tiles_n;
-        if (vec) k_gemm_f64<true, C::BM, C::BN, C::BK><<<(unsigned)nblk, 256, 0, s>>>((double *)a, ld, r0, m, c0, nc, k, kk, (int)tiles_n, (int)nblk);
-        else k_gemm_f64<false, C::BM, C::BN, C::BK><<<(unsigned)nblk, 256, 0, s>>>((double *)a, ld, r0, m, c0, nc, k, kk, (int)tiles_n, (int)nblk);
+        auto kv = k_gemm_f64<true, C::BM, C::BN, C::BK>;
+        auto ks = k_gemm_f64<false, C::BM, C::BN, C::BK>;
+        static int pad_v[9] = {-1, -1, -1, -1, -1, -1, -1, -1, -1}, pad_s[9] = {-1, -1, -1, -1, -1, -1, -1, -1, -1};
+        const int ci = cap < 0 ? 0 : cap > 8 ? 8 : cap;
+        if (vec) {
+            if (pad_v[ci] < 0) pad_v[ci] = cap_pad((const void *)kv, ci);
+            kv<<<(unsigned)nblk, 256, pad_v[ci], s>>>((double *)a, ld, r0, m, c0, nc, k, kk, (int)tiles_n, (int)nblk);
+        } else {
+            if (pad_s[ci] < 0) pad_s[ci] = cap_pad((const void *)ks, ci);
+            ks<<<(unsigned)nblk, 256, pad_s[ci], s>>>((double *)a, ld, r0, m, c0, nc, k, kk, (int)tiles_n, (int)nblk);
+        }
         return hipGetLastError();
     }
     const bool vec = (ld % 4 == 0) && (k % 4 == 0) && (c0 % 4 == 0) && (base % 16 == 0);
-    if (mode == LU_F32) go32<false>(vec, (float *)a, ld, r0, m, c0, nc, k, kk, s);
-    else go32<true>(vec, (float *)a, ld, r0, m, c0, nc, k, kk, s);
+    if (mode == LU_F32) go32<false>(vec, (float *)a, ld, r0, m, c0, nc, k, kk, cap, s);
+    else go32<true>(vec, (float *)a, ld, r0, m, c0, nc, k, kk, cap, s);
     return hipGetLastError();
 }
 

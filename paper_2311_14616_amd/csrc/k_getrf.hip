@@ -8,6 +8,8 @@
 // or binary64 (TF = F64).  Row interchanges of a row-major matrix move
 // contiguous memory, which is why this layout was chosen.
 #include <climits>
+#include <cstdlib>
+#include <type_traits>
 
 #include "mpir_internal.h"
 
@@ -95,7 +97,6 @@ template <> struct Cand<float> {
     __device__ uint64_t vbits() const { return key >> 32; }
     __device__ static Cand from_words(uint64_t vb, int row) { return {(vb << 32) | (uint64_t)(0xffffffffu - (uint32_t)row)}; }
     __device__ void take_max(const Cand &o) { key = o.key > key ? o.key : key; }
-    __device__ Cand shfl_xor(int off) const { return {(uint64_t)__shfl_xor((long long)key, off)}; }
 };
 template <> struct Cand<double> {
     uint64_t vb;
@@ -111,10 +112,50 @@ template <> struct Cand<double> {
     __device__ void take_max(const Cand &o) {
         if (o.vb > vb || (o.vb == vb && o.r < r)) { vb = o.vb; r = o.r; }
     }
-    __device__ Cand shfl_xor(int off) const {
-        return {(uint64_t)__shfl_xor((long long)vb, off), __shfl_xor(r, off)};
-    }
 };
+
+// Wave maximum of a pivot candidate by DPP: within rows of 16 lanes by
+// shifts of 1, 2, 4, 8, then across rows by the row broadcasts of lanes 15
+// and 31; lane 63 ends with the maximum, which readlane makes uniform.
+// Lanes a shift moves no value into take the identity (old operand).
+template <int CTRL, int RM>
+__device__ __forceinline__ uint32_t dpp_mov(uint32_t old, uint32_t x) {
+    return (uint32_t)__builtin_amdgcn_update_dpp((int)old, (int)x, CTRL, RM, 0xf, false);
+}
+template <int CTRL, int RM>
+__device__ __forceinline__ void dpp_max_step(Cand<float> &c) {
+    const uint32_t lo = (uint32_t)c.key, hi = (uint32_t)(c.key >> 32);
+    const uint32_t tlo = dpp_mov<CTRL, RM>(0u, lo), thi = dpp_mov<CTRL, RM>(0u, hi);
+    const uint64_t t = ((uint64_t)thi << 32) | tlo;
+    c.key = t > c.key ? t : c.key;
+}
+template <int CTRL, int RM>
+__device__ __forceinline__ void dpp_max_step(Cand<double> &c) {
+    const uint32_t lo = (uint32_t)c.vb, hi = (uint32_t)(c.vb >> 32);
+    const uint32_t tlo = dpp_mov<CTRL, RM>(0u, lo), thi = dpp_mov<CTRL, RM>(0u, hi);
+    const int tr = (int)dpp_mov<CTRL, RM>(0x7fffffffu, (uint32_t)c.r);
+    c.take_max(Cand<double>{((uint64_t)thi << 32) | tlo, tr});
+}
+__device__ __forceinline__ Cand<float> lane63(const Cand<float> &c) {
+    const uint32_t lo = __builtin_amdgcn_readlane((int)(uint32_t)c.key, 63);
+    const uint32_t hi = __builtin_amdgcn_readlane((int)(uint32_t)(c.key >> 32), 63);
+    return {((uint64_t)hi << 32) | lo};
+}
+__device__ __forceinline__ Cand<double> lane63(const Cand<double> &c) {
+    const uint32_t lo = __builtin_amdgcn_readlane((int)(uint32_t)c.vb, 63);
+    const uint32_t hi = __builtin_amdgcn_readlane((int)(uint32_t)(c.vb >> 32), 63);
+    return {((uint64_t)hi << 32) | lo, __builtin_amdgcn_readlane(c.r, 63)};
+}
+template <typename Cd>
+__device__ __forceinline__ Cd wave_max(Cd c) {
+    dpp_max_step<0x111, 0xf>(c);   // row_shr:1
+    dpp_max_step<0x112, 0xf>(c);   // row_shr:2
+    dpp_max_step<0x114, 0xf>(c);   // row_shr:4
+    dpp_max_step<0x118, 0xf>(c);   // row_shr:8
+    dpp_max_step<0x142, 0xa>(c);   // row_bcast:15 into rows 1 and 3
+    dpp_max_step<0x143, 0xc>(c);   // row_bcast:31 into rows 2 and 3
+    return lane63(c);
+}
 
 // Leaf factorization of rows [k0, n) x columns [k0, k0+w) of the working
 // array.  Workgroup g owns relative rows [g*R, g*R+R) (R = 512 per row of a
@@ -184,7 +225,7 @@ __global__ __launch_bounds__(kLeafNT) void k_leaf(W *__restrict__ a, int64_t n, 
 #pragma unroll
         for (int q = 0; q < kLeafRT; ++q)
             if (mine[q] && rr[q] >= j) best.take_max(Cd::make(v[q][0], rr[q]));
-        for (int off = 32; off > 0; off >>= 1) best.take_max(best.shfl_xor(off));
+        best = wave_max(best);
         if (lane == 0) red[wv] = best;
         __syncthreads();                                   // (A)
         best = red[0];
@@ -283,8 +324,7 @@ __global__ __launch_bounds__(kLeafNT) void k_leaf(W *__restrict__ a, int64_t n, 
                     if (hr != 0x7fffffff)
                         gbest = Cd::from_words(((uint64_t)(uint32_t)h1 << 32) | (uint32_t)h0, hr);
                 }
-                Cd wbst = gbest;
-                for (int off = 32; off > 0; off >>= 1) wbst.take_max(wbst.shfl_xor(off));
+                const Cd wbst = wave_max(gbest);
                 const int p = wbst.row();
                 // the lane holding the winning candidate writes its words of
                 // the pivot row
@@ -380,12 +420,12 @@ __global__ __launch_bounds__(kLeafNT) void k_leaf(W *__restrict__ a, int64_t n, 
 // computes its own pair without a sequential pass.  The tile of moved rows
 // is staged in LDS (all reads before any write).  The last workgroup also
 // permutes `perm` (the row permutation used by the solves).
-template <typename W, int CB>
+template <typename W, int CB, int TR>
 __global__ __launch_bounds__(256) void k_laswp(W *__restrict__ a, int64_t ld, int64_t k0, int cnt,
                                                const int32_t *__restrict__ ipiv, int64_t c0,
                                                int64_t c1, int64_t c2, int64_t c3,
                                                int32_t *__restrict__ perm, int ncolblk) {
-    __shared__ W tile[512 * CB];                        // [2*cnt][CB]
+    __shared__ W tile[TR * CB];                         // [2*cnt <= TR][CB]
     __shared__ int32_t sp[256];
     __shared__ int32_t pdst[512], psrc[512];
     __shared__ int s_extra;
@@ -447,14 +487,14 @@ __global__ __launch_bounds__(256) void k_laswp(W *__restrict__ a, int64_t ld, in
     }
 }
 
-// U12 <- L11^{-1} U12 for rows [k, k+w), w <= 64, columns [c0, c1):
+// U12 <- L11^{-1} U12 for rows [k, k+w), w <= 32, columns [c0, c1):
 // right-looking substitution, row t final at step t (F16: rounded to
 // binary16 then), rows below updated in parallel.
 template <typename W, bool F16>
 __global__ __launch_bounds__(256) void k_trsm(W *__restrict__ a, int64_t ld, int64_t k, int w,
                                               int64_t c0, int64_t c1) {
-    __shared__ W L[64][65];
-    __shared__ W X[64][65];
+    __shared__ W L[32][33];
+    __shared__ W X[32][65];
     const int tid = threadIdx.x;
     const int64_t cb = c0 + (int64_t)blockIdx.x * 64;
     const int ncol = (int)((c1 - cb) < 64 ? (c1 - cb) : 64);
@@ -537,25 +577,39 @@ hipError_t launch_leaf(int mode, void *a, int64_t n, int64_t ld, int64_t k0, int
 
 hipError_t launch_laswp(int mode, void *a, int64_t n, int64_t ld, int64_t k0, int cnt,
                         const int32_t *ipiv, int64_t c0, int64_t c1, int64_t c2, int64_t c3,
-                        int32_t *perm, hipStream_t s) {
+                        int32_t *perm, bool compact, hipStream_t s) {
     (void)n;
     if (cnt <= 0 || cnt > 256) return hipErrorInvalidValue;
     const int64_t wtot = (c1 - c0) + (c3 - c2);
+    // compact: 16 KB of LDS, so that the launch fits on a compute unit that
+    // a concurrent trailing update already occupies; otherwise 128 KB tiles
+    // of long row segments.
+    auto go = [&](auto wtag, auto cbtag, auto trtag) {
+        using W = decltype(wtag);
+        constexpr int CB = decltype(cbtag)::value, TR = decltype(trtag)::value;
+        const int nb = (int)((wtot + CB - 1) / CB);
+        k_laswp<W, CB, TR><<<nb + 1, 256, 0, s>>>((W *)a, ld, k0, cnt, ipiv, c0, c1, c2, c3, perm, nb);
+    };
+    using I4 = std::integral_constant<int, 4>;
+    using I8 = std::integral_constant<int, 8>;
+    using I32 = std::integral_constant<int, 32>;
+    using I64 = std::integral_constant<int, 64>;
+    using I512 = std::integral_constant<int, 512>;
     if (mode == LU_F64) {
-        constexpr int CB = 32;
-        const int nb = (int)((wtot + CB - 1) / CB);
-        k_laswp<double, CB><<<nb + 1, 256, 0, s>>>((double *)a, ld, k0, cnt, ipiv, c0, c1, c2, c3, perm, nb);
+        if (!compact) go(double(), I32(), I512());
+        else if (cnt <= 32) go(double(), I32(), I64());
+        else go(double(), I4(), I512());
     } else {
-        constexpr int CB = 64;
-        const int nb = (int)((wtot + CB - 1) / CB);
-        k_laswp<float, CB><<<nb + 1, 256, 0, s>>>((float *)a, ld, k0, cnt, ipiv, c0, c1, c2, c3, perm, nb);
+        if (!compact) go(float(), I64(), I512());
+        else if (cnt <= 32) go(float(), I64(), I64());
+        else go(float(), I8(), I512());
     }
     return hipGetLastError();
 }
 
 hipError_t launch_trsm(int mode, void *a, int64_t ld, int64_t k, int w, int64_t c0, int64_t c1,
                        hipStream_t s) {
-    if (w <= 0 || w > 64 || c1 <= c0) return w <= 0 || w > 64 ? hipErrorInvalidValue : hipSuccess;
+    if (w <= 0 || w > 32 || c1 <= c0) return w <= 0 || w > 32 ? hipErrorInvalidValue : hipSuccess;
     const unsigned nb = (unsigned)((c1 - c0 + 63) / 64);
     if (mode == LU_F64) k_trsm<double, false><<<nb, 256, 0, s>>>((double *)a, ld, k, w, c0, c1);
     else if (mode == LU_F32) k_trsm<float, false><<<nb, 256, 0, s>>>((float *)a, ld, k, w, c0, c1);

@@ -215,10 +215,11 @@ int panel_width(int mode) {
 
 // Row interchanges of ipiv[k0 .. k0+cnt), in chunks the kernel accepts.
 hipError_t laswp_chunks(int mode, void *a, int64_t n, int64_t ld, int64_t k0, int cnt, const int32_t *ipiv,
-                        int64_t c0, int64_t c1, int64_t c2, int64_t c3, int32_t *perm, hipStream_t s) {
+                        int64_t c0, int64_t c1, int64_t c2, int64_t c3, int32_t *perm, bool compact,
+                        hipStream_t s) {
     for (int off = 0; off < cnt; off += 256) {
         const int c = cnt - off < 256 ? cnt - off : 256;
-        hipError_t e = launch_laswp(mode, a, n, ld, k0 + off, c, ipiv, c0, c1, c2, c3, perm, s);
+        hipError_t e = launch_laswp(mode, a, n, ld, k0 + off, c, ipiv, c0, c1, c2, c3, perm, compact, s);
         if (e != hipSuccess) return e;
     }
     return hipSuccess;
@@ -227,7 +228,7 @@ hipError_t laswp_chunks(int mode, void *a, int64_t n, int64_t ld, int64_t k0, in
 // Columns [c0, c1) of rows [K, K+w): U12 <- L11^{-1} U12, blocked by kIB
 // (small triangular solve of each kIB-row block, then the update of the
 // panel rows below it).
-hipError_t upper_solve(mpir_fact f, int64_t K, int w, int64_t c0, int64_t c1, hipStream_t s) {
+hipError_t upper_solve(mpir_fact f, int64_t K, int w, int64_t c0, int64_t c1, int cap, hipStream_t s) {
     if (c1 <= c0) return hipSuccess;
     const int mode = f->mode;
     for (int64_t k = K; k < K + w; k += kIB) {
@@ -235,7 +236,7 @@ hipError_t upper_solve(mpir_fact f, int64_t K, int w, int64_t c0, int64_t c1, hi
         hipError_t e = launch_trsm(mode, f->work, f->ld, k, wl, c0, c1, s);
         if (e != hipSuccess) return e;
         if (k + wl < K + w) {
-            e = launch_gemm_update(mode, f->work, f->ld, k + wl, K + w - k - wl, c0, c1 - c0, k, wl, s);
+            e = launch_gemm_update(mode, f->work, f->ld, k + wl, K + w - k - wl, c0, c1 - c0, k, wl, cap, s);
             if (e != hipSuccess) return e;
         }
     }
@@ -256,13 +257,13 @@ hipError_t factor_panel(mpir_fact f, int64_t K, int w, hipStream_t s) {
                                    f->flags_d, s);
         if (e != hipSuccess) return e;
         if (k > K || k + wl < K + w) {
-            e = launch_laswp(mode, a, n, ld, k, wl, f->ipiv, K, k, k + wl, K + w, nullptr, s);
+            e = launch_laswp(mode, a, n, ld, k, wl, f->ipiv, K, k, k + wl, K + w, nullptr, true, s);
             if (e != hipSuccess) return e;
         }
         if (k + wl < K + w) {
             e = launch_trsm(mode, a, ld, k, wl, k + wl, K + w, s);
             if (e != hipSuccess) return e;
-            e = launch_gemm_update(mode, a, ld, k + wl, n - k - wl, k + wl, K + w - k - wl, k, wl, s);
+            e = launch_gemm_update(mode, a, ld, k + wl, n - k - wl, k + wl, K + w - k - wl, k, wl, 0, s);
             if (e != hipSuccess) return e;
         }
     }
@@ -277,14 +278,14 @@ hipError_t apply_step(mpir_fact f, int64_t K, int w, int64_t c0, int64_t c1, hip
     hipError_t e;
     {
         ProfScope ps_(5, 0.0, s);
-        e = laswp_chunks(f->mode, f->work, n, f->ld, K, w, f->ipiv, c0, c1, c1, c1, nullptr, s);
+        e = laswp_chunks(f->mode, f->work, n, f->ld, K, w, f->ipiv, c0, c1, c1, c1, nullptr, true, s);
         if (e != hipSuccess) return e;
-        e = upper_solve(f, K, w, c0, c1, s);
+        e = upper_solve(f, K, w, c0, c1, 0, s);
         if (e != hipSuccess) return e;
     }
     if (K + w < n) {
         ProfScope ps_(0, 2.0 * (double)(n - K - w) * (double)(c1 - c0) * w, s);
-        e = launch_gemm_update(f->mode, f->work, f->ld, K + w, n - K - w, c0, c1 - c0, K, w, s);
+        e = launch_gemm_update(f->mode, f->work, f->ld, K + w, n - K - w, c0, c1 - c0, K, w, 0, s);
     }
     return e;
 }
@@ -305,9 +306,25 @@ bool lookahead_enabled() {
     return env == 1;
 }
 
+// Occupancy cap of the trailing update while the next panel is factored
+// beside it (MPIR_GEMM_CAP overrides; 0 = no cap).
+int trailing_cap(int mode) {
+    static int env = -2;
+    if (env == -2) {
+        const char *e = std::getenv("MPIR_GEMM_CAP");
+        env = e ? std::atoi(e) : -1;
+    }
+    if (env >= 0) return env;
+    // measured at N = 32768: the binary32 update keeps most of its rate at
+    // 4 workgroups per unit, the binary16 / binary64 ones leave more room
+    return mode == LU_F32 ? 4 : 2;
+}
+
 mpir_status getrf(mpir_fact f) {
     const int64_t n = f->n;
-    hipStream_t s = f->stream, s2 = lookahead_enabled() ? f->stream2 : f->stream;
+    const bool la = lookahead_enabled();
+    hipStream_t s = f->stream, s2 = la ? f->stream2 : f->stream;
+    const int cap2 = la ? trailing_cap(f->mode) : 0;
     const int nb = panel_width(f->mode);
     if (n > leaf_max_rows(f->mode)) return MPIR_ERR_ARG;
     hipEvent_t *evA = f->evA, *evB = f->evB;
@@ -329,12 +346,12 @@ mpir_status getrf(mpir_fact f) {
         HIPCHK(hipStreamWaitEvent(s2, evA[prev], 0));          // panel p factored
         {
             ProfScope ps_(5, 0.0, s2);
-            HIPCHK(laswp_chunks(f->mode, f->work, n, f->ld, K, w, f->ipiv, 0, K, K2, n, f->perm, s2));
-            HIPCHK(upper_solve(f, K, w, K2, n, s2));
+            HIPCHK(laswp_chunks(f->mode, f->work, n, f->ld, K, w, f->ipiv, 0, K, K2, n, f->perm, false, s2));
+            HIPCHK(upper_solve(f, K, w, K2, n, cap2, s2));
         }
         if (K2 < n) {
             ProfScope ps_(0, 2.0 * (double)(n - K1) * (double)(n - K2) * w, s2);
-            HIPCHK(launch_gemm_update(f->mode, f->work, f->ld, K1, n - K1, K2, n - K2, K, w, s2));
+            HIPCHK(launch_gemm_update(f->mode, f->work, f->ld, K1, n - K1, K2, n - K2, K, w, cap2, s2));
         }
         HIPCHK(hipEventRecord(evB[cur], s2));
         // ---- main stream: step p on panel p+1, then factor panel p+1 ----

@@ -130,17 +130,19 @@ size_t panel_sync_bytes();
 hipError_t panel_sync_reset(PanelSync *ps, hipStream_t s);
 
 // a3: row interchanges ipiv[k0 .. k0+cnt) applied to the column ranges
-// [c0, c1) and [c2, c3); perm (may be NULL) permuted alongside.
+// [c0, c1) and [c2, c3); perm (may be NULL) permuted alongside.  compact:
+// small LDS tiles (fits beside a running trailing update).
 hipError_t launch_laswp(int mode, void *a, int64_t n, int64_t ld, int64_t k0, int cnt,
                         const int32_t *ipiv, int64_t c0, int64_t c1, int64_t c2,
-                        int64_t c3, int32_t *perm, hipStream_t s);
-// a3: U12 <- L11^{-1} U12 for rows [k, k+w) (w <= 64), columns [c0, c1).
+                        int64_t c3, int32_t *perm, bool compact, hipStream_t s);
+// a3: U12 <- L11^{-1} U12 for rows [k, k+w) (w <= 32), columns [c0, c1).
 hipError_t launch_trsm(int mode, void *a, int64_t ld, int64_t k, int w, int64_t c0,
                        int64_t c1, hipStream_t s);
 // a4: C[r0:r0+m, c0:c0+nc] -= A[r0:, k:k+kk] * A[k:k+kk, c0:] on one
-// row-major matrix (ld).
+// row-major matrix (ld).  cap > 0: at most cap workgroups per compute unit
+// (the rest of each unit stays free for work on another stream).
 hipError_t launch_gemm_update(int mode, void *a, int64_t ld, int64_t r0, int64_t m,
-                              int64_t c0, int64_t nc, int64_t k, int64_t kk,
+                              int64_t c0, int64_t nc, int64_t k, int64_t kk, int cap,
                               hipStream_t s);
 
 // a5: residual r = b - A x in TR, partial sums over column chunks then a
