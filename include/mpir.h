@@ -149,6 +149,46 @@ mpir_status mpir_batch_create(int32_t batch, const int64_t *n, const void *const
 mpir_status mpir_batch_run(mpir_batch b, mpir_report *reps);
 void mpir_batch_destroy(mpir_batch b);
 
+/* Tuning of the batched kernel.  Systems are grouped into size classes
+ * (class k holds nmax[k-1] < n <= nmax[k], nmax increasing, the last one
+ * 1024); each class has its own panel width and trailing-update form:
+ *  - panel[k]: columns per panel of the blocked LU, 16 or 32 (a wider panel
+ *    passes over the trailing matrix fewer times, a narrower one shortens
+ *    the in-LDS panel factorization and the triangular solve per panel);
+ *  - update[k]: 0 = every 32 x 32 block of A22 -= L21 U12 reads both of its
+ *    operands from memory (good load balance on small trailing matrices),
+ *    1 = L21 staged in LDS once per panel and each wave keeping one column
+ *    block of U12 in registers while it sweeps the block rows.
+ * The library keeps one table per (TW, TF) pair for the whole process; it is
+ * applied when a batch is created (mpir_batch_create, mpir_ir_solve_batched).
+ * ms[k]: the measured time of the chosen configuration on the tuning batch
+ * of the class (0 when not measured).  from_cache: 1 when mpir_batch_autotune
+ * read the table from its cache file. */
+#define MPIR_TUNE_CLASSES 8
+typedef struct {
+    int32_t nclass, from_cache;
+    int32_t nmax[MPIR_TUNE_CLASSES];
+    int32_t panel[MPIR_TUNE_CLASSES];
+    int32_t update[MPIR_TUNE_CLASSES];
+    double ms[MPIR_TUNE_CLASSES];
+} mpir_batch_tuning;
+
+/* The current table for (tw, tf) (TW in {F64, F32}, TF in {F32, F16}). */
+mpir_status mpir_batch_get_tuning(mpir_prec tw, mpir_prec tf, mpir_batch_tuning *t);
+/* Replace it (t = NULL restores the built-in defaults); MPIR_ERR_ARG if a
+ * field is out of range.  Touches no device. */
+mpir_status mpir_batch_set_tuning(mpir_prec tw, mpir_prec tf, const mpir_batch_tuning *t);
+/* Autotuner: for each size class, time every (panel, update) candidate on a
+ * synthetic batch of systems of the class's middle size (diagonally
+ * dominant, seeded) on the current device, keep the fastest, install the
+ * table and return it in *t (may be NULL).  cache_path (may be NULL): a text
+ * file keyed by the device name, compute-unit count, TW and TF; a matching
+ * file is read instead of measuring, otherwise it is (re)written after the
+ * measurement.  Allocates and frees its own device memory; synchronises
+ * hip_stream. */
+mpir_status mpir_batch_autotune(mpir_prec tw, mpir_prec tf, const char *cache_path,
+                                void *hip_stream, mpir_batch_tuning *t);
+
 /* Release a handle (NULL is allowed). */
 void mpir_destroy(mpir_fact f);
 

@@ -71,7 +71,7 @@ template <typename TWt, bool F16>
 __global__ __launch_bounds__(NT) void k_batched(const BatchSys *__restrict__ sys,
                                                 const int32_t *__restrict__ order, int nsys,
                                                 uint32_t *queue, BatchTerm term,
-                                                mpir_report *__restrict__ reps) {
+                                                mpir_report *__restrict__ reps, double tick_ms) {
     __shared__ __align__(16) float panel[PANEL_FLOATS];   // LU: panel / staging tiles
     // refinement phase (the LU is finished): vectors carved from the panel
     double *const vr = reinterpret_cast<double *>(panel);  // residual (TR = FP64)
@@ -100,6 +100,7 @@ __global__ __launch_bounds__(NT) void k_batched(const BatchSys *__restrict__ sys
         __syncthreads();
         const int si = s_sys;
         if (si < 0) break;
+        const long long t_start = wall_clock64();
         const BatchSys S = sys[si];
         const int n = (int)S.n;
         const int64_t lda = S.lda;
@@ -108,6 +109,10 @@ __global__ __launch_bounds__(NT) void k_batched(const BatchSys *__restrict__ sys
         TWt *x = (TWt *)S.x;
         float *W = S.W;
         int32_t *perm = S.perm;
+        // tuned per size class: panel width (16 or 32) and update form
+        const int cfg = (int)S.pad;
+        const int pb = (cfg & 0xff) == 16 ? 16 : PB;
+        const int upd = (cfg >> 8) & 0xff;
 
         // ---------------- interchange-free copy A_F = fl_F(A), ||A||_inf ----
         // 64 x 64 tiles: coalesced column reads, LDS transpose, coalesced row
@@ -163,8 +168,8 @@ __global__ __launch_bounds__(NT) void k_batched(const BatchSys *__restrict__ sys
         }
 
         // ---------------- blocked LU with partial pivoting ----------------
-        for (int k = 0; k < n; k += PB) {
-            const int w = (n - k) < PB ? (n - k) : PB;
+        for (int k = 0; k < n; k += pb) {
+            const int w = (n - k) < pb ? (n - k) : pb;
             const int m = n - k;
             __syncthreads();
             for (int e = tid; e < m * w; e += NT) {
@@ -283,6 +288,7 @@ __global__ __launch_bounds__(NT) void k_batched(const BatchSys *__restrict__ sys
                 L11[r][c] = W[(int64_t)(k + r) * n + k + c];
             }
             __syncthreads();
+#pragma unroll 1
             for (int c = k + w + tid; c < n; c += NT) {
                 float xv[PB];
 #pragma unroll
@@ -301,7 +307,86 @@ __global__ __launch_bounds__(NT) void k_batched(const BatchSys *__restrict__ sys
             }
             __syncthreads();
             // trailing update A22 -= L21 U12 (K = w <= 32) in 32 x 32 blocks
-            {
+            if (upd == 1) {
+                // L21 staged in LDS once; wave wv takes block columns bj =
+                // wv, wv + NW, ..., holds that column's U12 block in
+                // registers and sweeps the block rows.
+                const int r0 = k + w, mm = n - r0;
+                const int nbk = (mm + 31) / 32;
+                for (int e = tid; e < mm * PB; e += NT) {
+                    const int r = e / PB, c = e - r * PB;
+                    panel[r * PP + c] = c < w ? W[(int64_t)(r0 + r) * n + k + c] : 0.0f;
+                }
+                __syncthreads();
+                for (int bj = wv; bj < nbk; bj += NW) {
+                    const int cb = r0 + bj * 32, bc = cb + (lane & 31);
+                    if (F16) {
+                        half8 bh[2];
+#pragma unroll
+                        for (int s2 = 0; s2 < 2; ++s2)
+#pragma unroll
+                            for (int q = 0; q < 8; ++q) {
+                                const int kq = 16 * s2 + 8 * (lane >> 5) + q;
+                                bh[s2][q] = (_Float16)((bc < n && kq < w) ? W[(int64_t)(k + kq) * n + bc] : 0.0f);
+                            }
+                        for (int bi = 0; bi < nbk; ++bi) {
+                            const int rb = r0 + bi * 32, lr = bi * 32 + (lane & 31);
+                            float cv[16];
+#pragma unroll
+                            for (int v = 0; v < 16; ++v) {
+                                const int row = rb + 8 * (v >> 2) + 4 * (lane >> 5) + (v & 3);
+                                cv[v] = (row < n && bc < n) ? W[(int64_t)row * n + bc] : 0.0f;
+                            }
+                            floatx16 acc = floatx16{0};
+#pragma unroll
+                            for (int s2 = 0; s2 < 2; ++s2) {
+                                if (16 * s2 < w) {
+                                    half8 av;
+#pragma unroll
+                                    for (int q = 0; q < 8; ++q)
+                                        av[q] = (_Float16)(lr < mm ? panel[lr * PP + 16 * s2 + 8 * (lane >> 5) + q] : 0.0f);
+                                    acc = __builtin_amdgcn_mfma_f32_32x32x16_f16(av, bh[s2], acc, 0, 0, 0);
+                                }
+                            }
+#pragma unroll
+                            for (int v = 0; v < 16; ++v) {
+                                const int row = rb + 8 * (v >> 2) + 4 * (lane >> 5) + (v & 3);
+                                if (row < n && bc < n) W[(int64_t)row * n + bc] = cv[v] - acc[v];
+                            }
+                        }
+                    } else {
+                        float bf[16];
+#pragma unroll
+                        for (int s1 = 0; s1 < 16; ++s1) {
+                            const int kq = 2 * s1 + (lane >> 5);
+                            bf[s1] = (bc < n && kq < w) ? W[(int64_t)(k + kq) * n + bc] : 0.0f;
+                        }
+                        for (int bi = 0; bi < nbk; ++bi) {
+                            const int rb = r0 + bi * 32, lr = bi * 32 + (lane & 31);
+                            float cv[16];
+#pragma unroll
+                            for (int v = 0; v < 16; ++v) {
+                                const int row = rb + 8 * (v >> 2) + 4 * (lane >> 5) + (v & 3);
+                                cv[v] = (row < n && bc < n) ? W[(int64_t)row * n + bc] : 0.0f;
+                            }
+                            floatx16 acc = floatx16{0};
+#pragma unroll
+                            for (int s1 = 0; s1 < 16; ++s1) {
+                                if (2 * s1 < w) {
+                                    const float av = lr < mm ? panel[lr * PP + 2 * s1 + (lane >> 5)] : 0.0f;
+                                    acc = __builtin_amdgcn_mfma_f32_32x32x2f32(av, bf[s1], acc, 0, 0, 0);
+                                }
+                            }
+#pragma unroll
+                            for (int v = 0; v < 16; ++v) {
+                                const int row = rb + 8 * (v >> 2) + 4 * (lane >> 5) + (v & 3);
+                                if (row < n && bc < n) W[(int64_t)row * n + bc] = cv[v] - acc[v];
+                            }
+                        }
+                    }
+                }
+            } else {
+                // every 32 x 32 block on its own: both operands from memory
                 const int r0 = k + w, mm = n - r0;
                 const int nbk = (mm + 31) / 32;
                 for (int blk = wv; blk < nbk * nbk; blk += NW) {
@@ -311,23 +396,27 @@ __global__ __launch_bounds__(NT) void k_batched(const BatchSys *__restrict__ sys
                     const int ar = rb + (lane & 31), bc = cb + (lane & 31);
                     if (F16) {
 #pragma unroll
-                        for (int s = 0; s < PB; s += 16) {
-                            half8 av, bvv;
+                        for (int s1 = 0; s1 < PB; s1 += 16) {
+                            if (s1 < w) {
+                                half8 av, bvv;
 #pragma unroll
-                            for (int q = 0; q < 8; ++q) {
-                                const int kq = s + 8 * (lane >> 5) + q;
-                                av[q] = (_Float16)((ar < n && kq < w) ? W[(int64_t)ar * n + k + kq] : 0.0f);
-                                bvv[q] = (_Float16)((bc < n && kq < w) ? W[(int64_t)(k + kq) * n + bc] : 0.0f);
+                                for (int q = 0; q < 8; ++q) {
+                                    const int kq = s1 + 8 * (lane >> 5) + q;
+                                    av[q] = (_Float16)((ar < n && kq < w) ? W[(int64_t)ar * n + k + kq] : 0.0f);
+                                    bvv[q] = (_Float16)((bc < n && kq < w) ? W[(int64_t)(k + kq) * n + bc] : 0.0f);
+                                }
+                                acc = __builtin_amdgcn_mfma_f32_32x32x16_f16(av, bvv, acc, 0, 0, 0);
                             }
-                            acc = __builtin_amdgcn_mfma_f32_32x32x16_f16(av, bvv, acc, 0, 0, 0);
                         }
                     } else {
 #pragma unroll
-                        for (int s = 0; s < PB; s += 2) {
-                            const int kq = s + (lane >> 5);
-                            const float av = (ar < n && kq < w) ? W[(int64_t)ar * n + k + kq] : 0.0f;
-                            const float bvv = (bc < n && kq < w) ? W[(int64_t)(k + kq) * n + bc] : 0.0f;
-                            acc = __builtin_amdgcn_mfma_f32_32x32x2f32(av, bvv, acc, 0, 0, 0);
+                        for (int s1 = 0; s1 < PB; s1 += 2) {
+                            if (s1 < w) {
+                                const int kq = s1 + (lane >> 5);
+                                const float av = (ar < n && kq < w) ? W[(int64_t)ar * n + k + kq] : 0.0f;
+                                const float bvv = (bc < n && kq < w) ? W[(int64_t)(k + kq) * n + bc] : 0.0f;
+                                acc = __builtin_amdgcn_mfma_f32_32x32x2f32(av, bvv, acc, 0, 0, 0);
+                            }
                         }
                     }
 #pragma unroll
@@ -344,6 +433,7 @@ __global__ __launch_bounds__(NT) void k_batched(const BatchSys *__restrict__ sys
         }
         __syncthreads();
         const int info = s_info;
+        const long long t_lu = wall_clock64();
 
         // ---------------- Algorithm IR ----------------
         int it = 0, stop = MPIR_STOP_CONVERGED;
@@ -509,8 +599,8 @@ __global__ __launch_bounds__(NT) void k_batched(const BatchSys *__restrict__ sys
             const double den = anorm * xnorm + bnorm;
             R.bwd_err = den > 0.0 ? rnorm / den : 0.0;
             R.info = info;
-            R.t_factor_ms = 0.0;
-            R.t_ir_ms = 0.0;
+            R.t_factor_ms = (double)(t_lu - t_start) * tick_ms;
+            R.t_ir_ms = (double)(wall_clock64() - t_lu) * tick_ms;
         }
         __syncthreads();
     }
@@ -523,12 +613,22 @@ int batched_max_n() { return NMAX; }
 hipError_t launch_batched(int tw, int tf, const BatchSys *sys, const int32_t *order, int nsys,
                           uint32_t *queue, const BatchTerm &term, mpir_report *reps, int nwg,
                           hipStream_t s) {
+    // device wall clock (kHz) for the per-system timings in the reports
+    static double tick_ms = -1.0;
+    if (tick_ms < 0.0) {
+        int dev = 0, khz = 0;
+        if (hipGetDevice(&dev) == hipSuccess &&
+            hipDeviceGetAttribute(&khz, hipDeviceAttributeWallClockRate, dev) == hipSuccess && khz > 0)
+            tick_ms = 1.0 / (double)khz;
+        else
+            tick_ms = 0.0;
+    }
     if (tw == MPIR_F64) {
-        if (tf == MPIR_F16) k_batched<double, true><<<nwg, NT, 0, s>>>(sys, order, nsys, queue, term, reps);
-        else k_batched<double, false><<<nwg, NT, 0, s>>>(sys, order, nsys, queue, term, reps);
+        if (tf == MPIR_F16) k_batched<double, true><<<nwg, NT, 0, s>>>(sys, order, nsys, queue, term, reps, tick_ms);
+        else k_batched<double, false><<<nwg, NT, 0, s>>>(sys, order, nsys, queue, term, reps, tick_ms);
     } else {
-        if (tf == MPIR_F16) k_batched<float, true><<<nwg, NT, 0, s>>>(sys, order, nsys, queue, term, reps);
-        else k_batched<float, false><<<nwg, NT, 0, s>>>(sys, order, nsys, queue, term, reps);
+        if (tf == MPIR_F16) k_batched<float, true><<<nwg, NT, 0, s>>>(sys, order, nsys, queue, term, reps, tick_ms);
+        else k_batched<float, false><<<nwg, NT, 0, s>>>(sys, order, nsys, queue, term, reps, tick_ms);
     }
     return hipGetLastError();
 }

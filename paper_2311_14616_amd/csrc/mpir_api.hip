@@ -750,12 +750,11 @@ int device_cus() {
 
 }  // namespace
 
-extern "C" {
-
-mpir_status mpir_batch_create(int32_t batch, const int64_t *n, const void *const *dA,
+mpir_status batch_create_with(int32_t batch, const int64_t *n, const void *const *dA,
                               const int64_t *lda, const void *const *db, void *const *dx,
                               mpir_prec tw, mpir_prec tf, mpir_prec tr, const mpir_term *t,
-                              int32_t use_graph, void *hip_stream, mpir_batch *out) {
+                              int32_t use_graph, void *hip_stream, const mpir_batch_tuning *tab,
+                              mpir_batch *out) {
     if (out) *out = nullptr;
     if (!out || batch <= 0 || !n || !dA || !lda || !db || !dx) return MPIR_ERR_ARG;
     if (!(tw == MPIR_F64 || tw == MPIR_F32) || !(tf == MPIR_F32 || tf == MPIR_F16) || tr != MPIR_F64)
@@ -799,7 +798,8 @@ mpir_status mpir_batch_create(int32_t batch, const int64_t *n, const void *const
     std::vector<BatchSys> sys(batch);
     int64_t wo = 0, po = 0;
     for (int32_t k = 0; k < batch; ++k) {
-        sys[k] = BatchSys{n[k], lda[k], dA[k], db[k], dx[k], b->work + wo, b->perm + po, 0};
+        sys[k] = BatchSys{n[k], lda[k], dA[k], db[k], dx[k], b->work + wo, b->perm + po,
+                          batch_cfg(tw, tf, n[k], tab)};
         wo += n[k] * n[k];
         po += n[k];
     }
@@ -834,6 +834,15 @@ mpir_status mpir_batch_create(int32_t batch, const int64_t *n, const void *const
     }
     *out = b;
     return MPIR_OK;
+}
+
+extern "C" {
+
+mpir_status mpir_batch_create(int32_t batch, const int64_t *n, const void *const *dA,
+                              const int64_t *lda, const void *const *db, void *const *dx,
+                              mpir_prec tw, mpir_prec tf, mpir_prec tr, const mpir_term *t,
+                              int32_t use_graph, void *hip_stream, mpir_batch *out) {
+    return batch_create_with(batch, n, dA, lda, db, dx, tw, tf, tr, t, use_graph, hip_stream, nullptr, out);
 }
 
 mpir_status mpir_batch_run(mpir_batch b, mpir_report *reps) {

@@ -167,6 +167,10 @@ hipError_t launch_terminate(IrState *st, hipStream_t s);
 struct BatchSys;
 struct BatchTerm;
 int batched_max_n();
+// Per-system configuration word of the batched kernel for a system of size n
+// (panel width | update form << 8) from the tuning table tab, or from the
+// process-wide table for (tw, tf) when tab is NULL.
+int64_t batch_cfg(int tw, int tf, int64_t n, const mpir_batch_tuning *tab);
 hipError_t launch_batched(int tw, int tf, const BatchSys *sys, const int32_t *order, int nsys,
                           uint32_t *queue, const BatchTerm &term, mpir_report *reps, int nwg,
                           hipStream_t s);
@@ -179,3 +183,11 @@ hipError_t launch_trsv(int tf, const void *LU, int64_t n, int64_t ld, void *y, u
                        hipStream_t s);
 
 }  // namespace mpir
+
+// Batch creation with an explicit tuning table (NULL: the process-wide one).
+mpir_status batch_create_with(int32_t batch, const int64_t *n, const void *const *dA,
+                              const int64_t *lda, const void *const *db, void *const *dx,
+                              mpir_prec tw, mpir_prec tf, mpir_prec tr, const mpir_term *t,
+                              int32_t use_graph, void *hip_stream, const mpir_batch_tuning *tab,
+                              mpir_batch *out);
+

@@ -31,6 +31,7 @@ EXPORTS = [
     "mpir_ir_solve_batched", "mpir_destroy", "mpir_status_str", "mpir_downcast",
     "mpir_get_factors", "mpir_residual", "mpir_prof_enable", "mpir_prof_reset", "mpir_prof_get",
     "mpir_batch_create", "mpir_batch_run", "mpir_batch_destroy",
+    "mpir_batch_get_tuning", "mpir_batch_set_tuning", "mpir_batch_autotune",
 ]
 
 
@@ -43,6 +44,23 @@ class MpirError(RuntimeError):
 class Term(C.Structure):
     _fields_ = [("Cr", C.c_double), ("Ce", C.c_double), ("Rmax", C.c_double),
                 ("litmax", C.c_int32), ("residterm", C.c_int32), ("tol_rel", C.c_double)]
+
+
+TUNE_CLASSES = 8
+
+
+class Tuning(C.Structure):
+    """mpir_batch_tuning: per size class (n <= nmax[k]) the panel width and
+    the trailing-update form of the batched kernel."""
+    _fields_ = [("nclass", C.c_int32), ("from_cache", C.c_int32),
+                ("nmax", C.c_int32 * TUNE_CLASSES), ("panel", C.c_int32 * TUNE_CLASSES),
+                ("update", C.c_int32 * TUNE_CLASSES), ("ms", C.c_double * TUNE_CLASSES)]
+
+    def as_dict(self):
+        k = self.nclass
+        return {"from_cache": bool(self.from_cache),
+                "classes": [{"nmax": self.nmax[i], "panel": self.panel[i], "update": self.update[i],
+                             "ms": round(self.ms[i], 4)} for i in range(k)]}
 
 
 class Report(C.Structure):
@@ -101,6 +119,12 @@ def lib():
         L.mpir_batch_run.restype = C.c_int
         L.mpir_batch_run.argtypes = [vp, vp]
         L.mpir_batch_destroy.argtypes = [vp]
+        L.mpir_batch_get_tuning.restype = C.c_int
+        L.mpir_batch_get_tuning.argtypes = [C.c_int, C.c_int, P(Tuning)]
+        L.mpir_batch_set_tuning.restype = C.c_int
+        L.mpir_batch_set_tuning.argtypes = [C.c_int, C.c_int, P(Tuning)]
+        L.mpir_batch_autotune.restype = C.c_int
+        L.mpir_batch_autotune.argtypes = [C.c_int, C.c_int, C.c_char_p, vp, P(Tuning)]
         L.mpir_prof_enable.argtypes = [i32]
         L.mpir_prof_get.restype = C.c_int
         L.mpir_prof_get.argtypes = [i32, P(d), P(i64), P(d)]
@@ -320,6 +344,26 @@ def ir_solve_batched(As, bs, xs, tf: int, tr: int | None = None, term_parms: Ter
     st = lib().mpir_ir_solve_batched(k, ns, pa, ldas, pb, px, tw, tf, tr, tp, reps,
                                      _stream_ptr(stream))
     return st, list(reps)
+
+
+def batch_get_tuning(tw: int, tf: int) -> Tuning:
+    t = Tuning()
+    _check(lib().mpir_batch_get_tuning(tw, tf, C.byref(t)), "mpir_batch_get_tuning")
+    return t
+
+
+def batch_set_tuning(tw: int, tf: int, t: Tuning | None):
+    _check(lib().mpir_batch_set_tuning(tw, tf, C.byref(t) if t is not None else None),
+           "mpir_batch_set_tuning")
+
+
+def batch_autotune(tw: int, tf: int, cache_path: str | None = None, stream=None) -> Tuning:
+    """Measure (or read from cache_path) the batched kernel's configuration
+    per size class and install it for (tw, tf)."""
+    t = Tuning()
+    cp = cache_path.encode() if cache_path else None
+    _check(lib().mpir_batch_autotune(tw, tf, cp, _stream_ptr(stream), C.byref(t)), "mpir_batch_autotune")
+    return t
 
 
 def prof_enable(on: bool = True):

@@ -75,3 +75,35 @@ def test_binding_has_no_cpu_fallback():
     src = open(os.path.join(ROOT, "paper_2311_14616_amd", "mpir.py")).read()
     assert "oracle" not in src.replace("no fallback", "")
     assert "numpy.linalg" not in src and "scipy" not in src and "torch.linalg" not in src
+
+
+def test_batch_tuning_table_host_logic():
+    """The tuning table is host state: defaults, validated replacement and
+    reset work without a device."""
+    from paper_2311_14616_amd import mpir as M
+    d0 = M.batch_get_tuning(M.F64, M.F16).as_dict()
+    assert d0["classes"][-1]["nmax"] == 1024 and not d0["from_cache"]
+    assert all(c["panel"] in (16, 32) and c["update"] in (0, 1) for c in d0["classes"])
+    t = M.batch_get_tuning(M.F64, M.F16)
+    t.panel[0], t.update[0] = 16, 1
+    M.batch_set_tuning(M.F64, M.F16, t)
+    c0 = M.batch_get_tuning(M.F64, M.F16).as_dict()["classes"][0]
+    assert (c0["panel"], c0["update"]) == (16, 1)
+    # other precision pairs keep their own table
+    assert M.batch_get_tuning(M.F64, M.F32).as_dict()["classes"][0]["panel"] == d0["classes"][0]["panel"]
+    for bad in ({"panel": 8}, {"update": 2}, {"nmax_last": 512}, {"nclass": 0}, {"nclass": 9}):
+        u = M.batch_get_tuning(M.F64, M.F16)
+        if "panel" in bad:
+            u.panel[1] = bad["panel"]
+        if "update" in bad:
+            u.update[1] = bad["update"]
+        if "nmax_last" in bad:
+            u.nmax[u.nclass - 1] = bad["nmax_last"]
+        if "nclass" in bad:
+            u.nclass = bad["nclass"]
+        with pytest.raises(M.MpirError):
+            M.batch_set_tuning(M.F64, M.F16, u)
+    with pytest.raises(M.MpirError):
+        M.batch_get_tuning(M.F16, M.F16)          # TW = F16 is not a working precision here
+    M.batch_set_tuning(M.F64, M.F16, None)
+    assert M.batch_get_tuning(M.F64, M.F16).as_dict() == d0

@@ -47,9 +47,33 @@ def _systems(seed=7, count=len(SIZES)):
     return out
 
 
+def _one_config(M, panel, update):
+    t = M.Tuning()
+    t.nclass = 1
+    t.nmax[0] = 1024
+    t.panel[0] = panel
+    t.update[0] = update
+    return t
+
+
+# every configuration the autotuner can pick: panel width x update form
+CONFIGS = [(None, None), (16, 0), (16, 1), (32, 0), (32, 1)]
+
+
+@pytest.mark.parametrize("cfg", CONFIGS, ids=lambda c: "default" if c[0] is None else f"p{c[0]}u{c[1]}")
 @pytest.mark.parametrize("tf", ["f32", "f16"])
-def test_batched_parity_against_oracle(M, orc, tf):
-    say(f"batched parity tf={tf}")
+def test_batched_parity_against_oracle(M, orc, tf, cfg):
+    say(f"batched parity tf={tf} cfg={cfg}")
+    T = {"f32": M.F32, "f16": M.F16}[tf]
+    if cfg[0] is not None:
+        M.batch_set_tuning(M.F64, T, _one_config(M, *cfg))
+    try:
+        _parity_run(M, orc, tf)
+    finally:
+        M.batch_set_tuning(M.F64, T, None)
+
+
+def _parity_run(M, orc, tf):
     systems = _systems()
     As = [dev(at) for _, at, _ in systems]
     bs = [dev(b) for _, _, b in systems]
@@ -160,3 +184,28 @@ def test_batched_full_workload_sampled(M, orc):
         ref = orc.ir_solve(at, b, orc.F32, tol_rel=1e-14, litmax=20)
         assert abs(reps[k].n_iter - ref.n_iter) <= 1
         assert np.abs(xs[k].cpu().numpy() - ref.x).max() <= 1e-13
+
+
+@pytest.mark.parametrize("tf", ["f32", "f16"])
+def test_autotune_table_and_cache(M, tmp_path, tf):
+    """The autotuner returns a valid table (every class measured, a
+    candidate chosen), installs it, writes its cache, and a second call with
+    the same cache reads the same table back instead of measuring."""
+    say(f"autotune tf={tf}")
+    T = {"f32": M.F32, "f16": M.F16}[tf]
+    cache = str(tmp_path / f"tune_{tf}.txt")
+    try:
+        t1 = M.batch_autotune(M.F64, T, cache)
+        d1 = t1.as_dict()
+        say(d1)
+        assert not d1["from_cache"] and d1["classes"][-1]["nmax"] == 1024
+        for c in d1["classes"]:
+            assert c["panel"] in (16, 32) and c["update"] in (0, 1) and c["ms"] > 0
+        assert M.batch_get_tuning(M.F64, T).as_dict()["classes"] == d1["classes"]
+        t2 = M.batch_autotune(M.F64, T, cache)
+        d2 = t2.as_dict()
+        assert d2["from_cache"]
+        assert [(c["nmax"], c["panel"], c["update"]) for c in d2["classes"]] == \
+            [(c["nmax"], c["panel"], c["update"]) for c in d1["classes"]]
+    finally:
+        M.batch_set_tuning(M.F64, T, None)
