@@ -29,6 +29,43 @@ def log(*a):
     print(*a, file=sys.stderr, flush=True)
 
 
+def trailing_bytes(n: int, nb: int, esz: int) -> float:
+    """Algorithmic HBM bytes of all trailing-update launches of one
+    factorization (the same two launches per step as the library: the next
+    panel's columns, then the rest): A21 and U12 read once, A22 read and
+    written once."""
+    tot = 0.0
+    for K in range(0, n, nb):
+        w = min(nb, n - K)
+        K1 = K + w
+        w1 = min(nb, n - K1) if K1 < n else 0
+        K2 = K1 + w1
+        m = n - K1
+        for nc in (w1, n - K2):
+            if m > 0 and nc > 0:
+                tot += esz * (m * w + w * nc + 2.0 * m * nc)
+    return tot
+
+
+def counter_traffic(tf_name: str, n: int):
+    """HBM bytes per trailing-update launch from the committed rocprofv3
+    FETCH_SIZE / WRITE_SIZE summary of this workload, scaled by the copy
+    calibration it records; None if there is none or if the GEMM source has
+    changed since the counters were taken."""
+    import hashlib
+    path = os.path.join(ROOT, "profiles", f"trailing_gemm_{tf_name}_n{n}_counters.json")
+    src = os.path.join(ROOT, "paper_2311_14616_amd", "csrc", "k_gemm.hip")
+    if not os.path.exists(path):
+        return None, None
+    with open(path) as fp:
+        rec = json.load(fp)
+    with open(src, "rb") as fp:
+        sha = hashlib.sha256(fp.read()).hexdigest()
+    if rec.get("source_sha256") != sha:
+        return None, rec
+    return rec.get("hbm_bytes_per_launch"), rec
+
+
 def cpu_baseline(n_sample: int, n_full: int):
     """Time the oracle (plain C, OpenMP) on a bounded sample of the workload
     and scale it to the full size (LU ~ N^3 dominates)."""
@@ -61,6 +98,11 @@ def batched_bench(M, I, torch, dev, tf_name: str, reps: int = 3):
         bs.append(at.sum(0))
         xs.append(torch.empty(int(n), dtype=torch.float64, device=dev))
     tf = {"f32": M.F32, "f16": M.F16}[tf_name]
+    # panel width and update form per size class: measured on this device
+    # (or read from the cache file) before the batch is created
+    t0 = time.perf_counter()
+    tuning = M.batch_autotune(M.F64, tf, os.environ.get("MPIR_TUNE_CACHE"))
+    tune_s = time.perf_counter() - t0
     bt = M.Batch(As, bs, xs, tf, term_parms=M.term(tol_rel=1e-14, litmax=20), use_graph=True)
     bt.run()                                    # warm-up
     torch.cuda.synchronize()
@@ -78,7 +120,109 @@ def batched_bench(M, I, torch, dev, tf_name: str, reps: int = 3):
             "all_converged": bool(all(r.stop == 0 for r in rep)),
             "n_iter_mean": float(iters.mean()), "n_iter_max": int(iters.max()),
             "ferr_p50": float(np.percentile(ferr, 50)), "ferr_p99": float(np.percentile(ferr, 99)),
-            "bwd_err_max": float(bwd.max())}
+            "bwd_err_max": float(bwd.max()),
+            "device_factor_ms_sum": round(float(sum(r.t_factor_ms for r in rep)), 1),
+            "device_ir_ms_sum": round(float(sum(r.t_ir_ms for r in rep)), 1),
+            "autotune_s": round(tune_s, 2), "tuning": tuning.as_dict()}
+
+
+def experiments(M, I, torch, dev):
+    """The remaining workloads of the method, one JSON line each:
+    (i)   TF=F32 IR at N=8192 against the FP64 LU solve;
+    (ii)  TF=F16 IR at N in {8192, 32768}, alpha in {1, 10, 100}: iteration
+          counts, stop reason and the level where it stalls, beside TF=F32;
+    (iii) the Wilkinson-type matrices A = H1 diag(sigma) H2 at N=16384,
+          kappa in {1e4, 1e6, 1e7}, TW=TF=F32, TR=F64: forward error of IR
+          against x* and against the FP64 LU solve of the same matrix, and
+          of one plain FP32 LU solve."""
+    import numpy as np
+    tp = M.term(tol_rel=1e-14, litmax=20)
+
+    def timed(fn):
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        r = fn()
+        torch.cuda.synchronize()
+        return r, (time.perf_counter() - t0) * 1e3
+
+    def ir(At, b, tf, tr=M.F64, term=tp):
+        x = torch.empty_like(b)
+
+        def go():
+            f = M.Factorization(At, tf, tr)
+            _, rep = f.ir_solve(b, x, term)
+            f.destroy()
+            return rep
+        timed(go)                                   # warm-up
+        rep, ms = timed(go)
+        return x, rep, ms
+
+    def lu64(At64, b64):
+        x = torch.empty_like(b64)
+
+        def go():
+            f = M.Factorization(At64, M.F64, M.F64)
+            f.solve(b64, x)
+            f.destroy()
+        timed(go)
+        _, ms = timed(go)
+        return x, ms
+
+    def rec(rep):
+        return {"n_iter": rep.n_iter, "stop": rep.stop_name, "relres": rep.relres,
+                "bwd_err": rep.bwd_err, "rhist_rel": [v / rep.rhist[0] for v in rep.rhist[:rep.n_iter + 1]]}
+
+    out = []
+    # (i)
+    n = 8192
+    At = I.gmat_operator_torch(n, 1.0, dev)
+    b = I.rhs_ones_torch(At)
+    x, rep, ms = ir(At, b, M.F32)
+    x64, ms64 = lu64(At, b)
+    out.append({"experiment": "plain IR TF=F32 vs FP64 LU", "n": n, "alpha": 1.0, "ir_ms": round(ms, 3),
+                "fp64_lu_ms": round(ms64, 3), "speedup": round(ms64 / ms, 3), **rec(rep),
+                "ferr_vs_ones": float((x - 1).abs().max()), "ferr_fp64_lu_vs_ones": float((x64 - 1).abs().max())})
+    print(json.dumps(out[-1]), flush=True)
+    del At, b
+    # (ii)
+    for n in (8192, 32768):
+        for alpha in (1.0, 10.0, 100.0):
+            At = I.gmat_operator_torch(n, alpha, dev)
+            b = I.rhs_ones_torch(At)
+            row = {"experiment": "half-precision factorization", "n": n, "alpha": alpha}
+            for name, tf in (("f16", M.F16), ("f32", M.F32)):
+                x, rep, ms = ir(At, b, tf)
+                r = rec(rep)
+                r["ms"] = round(ms, 3)
+                r["ferr_vs_ones"] = float((x - 1).abs().max())
+                r["stall_relres"] = min(r["rhist_rel"])
+                row[name] = r
+            print(json.dumps(row), flush=True)
+            out.append(row)
+            del At, b
+    # (iii)
+    n = 16384
+    for kappa in (1e4, 1e6, 1e7):
+        at32, b32, xstar, _ = I.wilkinson_operator_torch(n, kappa, dev)
+        wt = M.term(litmax=20)                      # TR wider than TW: eq. wilkterm
+        x, rep, ms = ir(at32, b32, M.F32, M.F64, wt)
+        x64, _ = lu64(at32.to(torch.float64), b32.to(torch.float64))
+        xp = torch.empty_like(b32)
+        f = M.Factorization(at32, M.F32, M.F32)
+        f.solve(b32, xp)
+        f.destroy()
+        xsn = float(xstar.abs().max())
+        row = {"experiment": "Wilkinson-type, TW=TF=F32, TR=F64", "n": n, "kappa": kappa, "ms": round(ms, 3),
+               "n_iter": rep.n_iter, "stop": rep.stop_name,
+               "ferr_ir_vs_xstar": float((x.double() - xstar).abs().max()) / xsn,
+               "ferr_ir_vs_fp64_lu": float((x.double() - x64).abs().max()) / float(x64.abs().max()),
+               "ferr_fp64_lu_vs_xstar": float((x64 - xstar).abs().max()) / xsn,
+               "ferr_plain_f32_lu_vs_xstar": float((xp.double() - xstar).abs().max()) / xsn,
+               "dhist": list(rep.dhist[:rep.n_iter])}
+        print(json.dumps(row), flush=True)
+        out.append(row)
+        del at32, b32
+    return out
 
 
 def main():
@@ -94,6 +238,12 @@ def main():
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--no-fp64", action="store_true")
     ap.add_argument("--no-batched", action="store_true")
+    ap.add_argument("--experiments", action="store_true",
+                    help="run the N=8192 comparison, the half-precision alpha sweep and the "
+                         "Wilkinson-type cases instead of the benchmark (one JSON line each)")
+    ap.add_argument("--calibrate-copy", action="store_true",
+                    help="first copy 1 GiB device to device once (the reference kernel for "
+                         "scaling rocprofv3 FETCH_SIZE / WRITE_SIZE counters)")
     args = ap.parse_args()
     if args.gpus != 1:
         print(json.dumps({"error": "this build runs on one GPU; multi-GPU sharding is "
@@ -105,6 +255,17 @@ def main():
     from paper_2311_14616_amd import inputs as I
 
     dev = torch.device("cuda:0")
+    if args.experiments:
+        experiments(M, I, torch, dev)
+        return
+    if args.calibrate_copy:
+        src = torch.ones(1 << 28, dtype=torch.float32, device=dev)
+        dst = torch.empty_like(src)
+        torch.cuda.synchronize()
+        dst.copy_(src)
+        torch.cuda.synchronize()
+        log("[bench] calibration copy: 1 GiB read, 1 GiB written")
+        del src, dst
     n = args.n
     tf = {"f32": M.F32, "f16": M.F16}[args.tf]
     log(f"[bench] generating A (N={n}) on the device")
@@ -141,6 +302,12 @@ def main():
     v_ms, v_cnt, v_bytes = M.prof_get(M.PROF_GEMV)
     d_ms, d_cnt, d_bytes = M.prof_get(M.PROF_DOWNCAST)
     gemm_tflops = g_flops / (g_ms * 1e-3) / 1e12 if g_ms > 0 else 0.0
+    # algorithmic bytes of the trailing updates: A21, U12 read, A22 read and
+    # written, in the working precision of the factorization (4 B; 8 B F64)
+    g_bytes = trailing_bytes(n, int(os.environ.get("MPIR_NB", "512")), 4) * args.steps
+    traffic, trec = counter_traffic(args.tf, n)
+    traffic_src = (f"profiles/trailing_gemm_{args.tf}_n{n}_counters.json"
+                   + ("" if traffic is not None else " (absent or stale)")) if trec is not None or traffic is None else None
     gemv_gbs = v_bytes / (v_ms * 1e-3) / 1e9 if v_ms > 0 else 0.0
     trsv_bytes_per = (4 if args.tf == "f32" else 2) * n * n
     trsv_gbs = trsv_bytes_per * t_cnt / (t_ms * 1e-3) / 1e9 if t_ms > 0 else 0.0
@@ -160,8 +327,10 @@ def main():
                "relres": rep.relres, "t_factor_ms": rep.t_factor_ms, "t_ir_ms": rep.t_ir_ms},
         "roofline": {"bound": "mfma", "achieved": round(gemm_tflops, 2), "peak": PEAK[args.tf],
                      "unit": "TFLOP/s", "frac": round(gemm_tflops / PEAK[args.tf], 4),
-                     "traffic": None, "kernel": f"trailing-update GEMM ({args.tf} MFMA)",
-                     "launches": g_cnt, "avg_launch_ms": g_ms / max(g_cnt, 1)},
+                     "traffic": traffic, "kernel": f"trailing-update GEMM ({args.tf} MFMA)",
+                     "launches": g_cnt, "avg_launch_ms": g_ms / max(g_cnt, 1),
+                     "algorithmic_bytes_per_launch": g_bytes / max(g_cnt, 1),
+                     "traffic_source": traffic_src},
         "kernels": {
             "gemm_ms_per_step": g_ms / args.steps, "panel_ms_per_step": p_ms / args.steps,
             "trsv_ms_per_step": t_ms / args.steps, "gemv_ms_per_step": v_ms / args.steps,

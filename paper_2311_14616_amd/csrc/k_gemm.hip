@@ -44,6 +44,19 @@ __device__ __forceinline__ int xcd_remap(int bid, int nblk) {
     return (bid % NX) * per + bid / NX;
 }
 
+// Tile (row, column) of a remapped tile id: bands of GM tile rows, column by
+// column inside a band, so the tiles in flight on one XCD (consecutive ids)
+// form a GM x (in-flight / GM) block that shares GM row panels of A and a
+// few column panels of B in that XCD's L2.
+constexpr int kGroupM = 16;
+__device__ __forceinline__ void tile_coords(int t, int tiles_m, int tiles_n, int &tr, int &tc) {
+    const int band = kGroupM * tiles_n;
+    const int g = t / band, r = t - g * band;
+    const int rows = (tiles_m - g * kGroupM) < kGroupM ? (tiles_m - g * kGroupM) : kGroupM;
+    tr = g * kGroupM + r % rows;
+    tc = r / rows;
+}
+
 template <bool VEC, int NV>
 __device__ __forceinline__ void load_row_f32(float (&dst)[NV], const float *src, bool rowok,
                                              int64_t k0, int64_t klim) {
@@ -68,7 +81,7 @@ __device__ __forceinline__ void load_row_f32(float (&dst)[NV], const float *src,
 // columns.  Binary32 tiles are stored k-major in LDS (lanes read consecutive
 // rows or columns of one k); binary16 tiles row-major for A and transposed
 // for B (8 consecutive k per lane, one 16-byte LDS read per operand).
-template <bool HALF, bool VEC, int BM, int BN, int BK, int NBUF>
+template <bool HALF, bool VEC, int BM, int BN, int BK, int NBUF, int ROLE>
 __global__ __launch_bounds__(256) void k_gemm_32(float *__restrict__ a, int64_t ld, int64_t r0,
                                                  int64_t m, int64_t c0, int64_t nc, int64_t k,
                                                  int64_t kk, int tiles_n, int nblk) {
@@ -87,7 +100,9 @@ __global__ __launch_bounds__(256) void k_gemm_32(float *__restrict__ a, int64_t 
 
     const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
     const int bid = xcd_remap(blockIdx.x, nblk);
-    const int64_t tm = (int64_t)(bid / tiles_n) * BM, tn = (int64_t)(bid % tiles_n) * BN;
+    int trow, tcol;
+    tile_coords(bid, nblk / tiles_n, tiles_n, trow, tcol);
+    const int64_t tm = (int64_t)trow * BM, tn = (int64_t)tcol * BN;
     const int wm = (wv >> 1) * (BM / 2), wn = (wv & 1) * (BN / 2);
 
     const int arow = tid / TPR, ak0 = (tid % TPR) * AK;
@@ -210,7 +225,7 @@ __global__ __launch_bounds__(256) void k_gemm_32(float *__restrict__ a, int64_t 
 // grid, each wave (BM/2) x (BN/2) of C in 16 x 16 MFMA blocks.  A: TPR =
 // 256/BM threads per row, each BK/TPR consecutive k; B: TPK = 256/BK threads
 // per k-row, each BN/TPK consecutive columns.
-template <bool VEC, int BM, int BN, int BK>
+template <bool VEC, int BM, int BN, int BK, int ROLE>
 __global__ __launch_bounds__(256) void k_gemm_f64(double *__restrict__ a, int64_t ld, int64_t r0,
                                                   int64_t m, int64_t c0, int64_t nc, int64_t k,
                                                   int64_t kk, int tiles_n, int nblk) {
@@ -222,7 +237,9 @@ __global__ __launch_bounds__(256) void k_gemm_f64(double *__restrict__ a, int64_
     __shared__ __align__(16) double Bs[2][BK][BN + 2];
     const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
     const int bid = xcd_remap(blockIdx.x, nblk);
-    const int64_t tm = (int64_t)(bid / tiles_n) * BM, tn = (int64_t)(bid % tiles_n) * BN;
+    int trow, tcol;
+    tile_coords(bid, nblk / tiles_n, tiles_n, trow, tcol);
+    const int64_t tm = (int64_t)trow * BM, tn = (int64_t)tcol * BN;
     const int wm = (wv >> 1) * (BM / 2), wn = (wv & 1) * (BN / 2);
     const int arow = tid / TPR, ak0 = (tid % TPR) * AK;
     const int bk = tid / TPK, bc0 = (tid % TPK) * BCOL;
@@ -328,14 +345,14 @@ int cap_pad(const void *fn, int cap) {
     return want - stat;
 }
 
-template <bool HALF>
+template <bool HALF, int ROLE>
 void go32(bool vec, float *a, int64_t ld, int64_t r0, int64_t m, int64_t c0, int64_t nc, int64_t k,
           int64_t kk, int cap, hipStream_t s) {
     using C = Cfg32<HALF>;
     const int64_t tiles_m = (m + C::BM - 1) / C::BM, tiles_n = (nc + C::BN - 1) / C::BN;
     const int64_t nblk = tiles_m * tiles_n;
-    auto kv = k_gemm_32<HALF, true, C::BM, C::BN, C::BK, C::NBUF>;
-    auto ks = k_gemm_32<HALF, false, C::BM, C::BN, C::BK, C::NBUF>;
+    auto kv = k_gemm_32<HALF, true, C::BM, C::BN, C::BK, C::NBUF, ROLE>;
+    auto ks = k_gemm_32<HALF, false, C::BM, C::BN, C::BK, C::NBUF, ROLE>;
     static int pad_v[9] = {-1, -1, -1, -1, -1, -1, -1, -1, -1}, pad_s[9] = {-1, -1, -1, -1, -1, -1, -1, -1, -1};
     const int ci = cap < 0 ? 0 : cap > 8 ? 8 : cap;
     if (vec) {
@@ -347,10 +364,9 @@ void go32(bool vec, float *a, int64_t ld, int64_t r0, int64_t m, int64_t c0, int
     }
 }
 
-}  // namespace
-
-hipError_t launch_gemm_update(int mode, void *a, int64_t ld, int64_t r0, int64_t m, int64_t c0,
-                              int64_t nc, int64_t k, int64_t kk, int cap, hipStream_t s) {
+template <int ROLE>
+hipError_t gemm_go(int mode, void *a, int64_t ld, int64_t r0, int64_t m, int64_t c0,
+                   int64_t nc, int64_t k, int64_t kk, int cap, hipStream_t s) {
     if (m <= 0 || nc <= 0 || kk <= 0) return hipSuccess;
     if ((m / 64 + 1) * (nc / 64 + 1) > 0x7fffffffll) return hipErrorInvalidValue;
     // 16-byte vector loads need every row start and offset 16-byte aligned
@@ -360,8 +376,8 @@ hipError_t launch_gemm_update(int mode, void *a, int64_t ld, int64_t r0, int64_t
         using C = Cfg64;
         const int64_t tiles_m = (m + C::BM - 1) / C::BM, tiles_n = (nc + C::BN - 1) / C::BN;
         const int64_t nblk = tiles_m * tiles_n;
-        auto kv = k_gemm_f64<true, C::BM, C::BN, C::BK>;
-        auto ks = k_gemm_f64<false, C::BM, C::BN, C::BK>;
+        auto kv = k_gemm_f64<true, C::BM, C::BN, C::BK, ROLE>;
+        auto ks = k_gemm_f64<false, C::BM, C::BN, C::BK, ROLE>;
         static int pad_v[9] = {-1, -1, -1, -1, -1, -1, -1, -1, -1}, pad_s[9] = {-1, -1, -1, -1, -1, -1, -1, -1, -1};
         const int ci = cap < 0 ? 0 : cap > 8 ? 8 : cap;
         if (vec) {
@@ -374,9 +390,17 @@ hipError_t launch_gemm_update(int mode, void *a, int64_t ld, int64_t r0, int64_t
         return hipGetLastError();
     }
     const bool vec = (ld % 4 == 0) && (k % 4 == 0) && (c0 % 4 == 0) && (base % 16 == 0);
-    if (mode == LU_F32) go32<false>(vec, (float *)a, ld, r0, m, c0, nc, k, kk, cap, s);
-    else go32<true>(vec, (float *)a, ld, r0, m, c0, nc, k, kk, cap, s);
+    if (mode == LU_F32) go32<false, ROLE>(vec, (float *)a, ld, r0, m, c0, nc, k, kk, cap, s);
+    else go32<true, ROLE>(vec, (float *)a, ld, r0, m, c0, nc, k, kk, cap, s);
     return hipGetLastError();
+}
+
+}  // namespace
+
+hipError_t launch_gemm_update(int mode, void *a, int64_t ld, int64_t r0, int64_t m, int64_t c0,
+                              int64_t nc, int64_t k, int64_t kk, int cap, int role, hipStream_t s) {
+    return role == 0 ? gemm_go<0>(mode, a, ld, r0, m, c0, nc, k, kk, cap, s)
+                     : gemm_go<1>(mode, a, ld, r0, m, c0, nc, k, kk, cap, s);
 }
 
 }  // namespace mpir

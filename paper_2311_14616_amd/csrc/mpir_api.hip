@@ -236,7 +236,7 @@ hipError_t upper_solve(mpir_fact f, int64_t K, int w, int64_t c0, int64_t c1, in
         hipError_t e = launch_trsm(mode, f->work, f->ld, k, wl, c0, c1, s);
         if (e != hipSuccess) return e;
         if (k + wl < K + w) {
-            e = launch_gemm_update(mode, f->work, f->ld, k + wl, K + w - k - wl, c0, c1 - c0, k, wl, cap, s);
+            e = launch_gemm_update(mode, f->work, f->ld, k + wl, K + w - k - wl, c0, c1 - c0, k, wl, cap, 1, s);
             if (e != hipSuccess) return e;
         }
     }
@@ -263,7 +263,7 @@ hipError_t factor_panel(mpir_fact f, int64_t K, int w, hipStream_t s) {
         if (k + wl < K + w) {
             e = launch_trsm(mode, a, ld, k, wl, k + wl, K + w, s);
             if (e != hipSuccess) return e;
-            e = launch_gemm_update(mode, a, ld, k + wl, n - k - wl, k + wl, K + w - k - wl, k, wl, 0, s);
+            e = launch_gemm_update(mode, a, ld, k + wl, n - k - wl, k + wl, K + w - k - wl, k, wl, 0, 1, s);
             if (e != hipSuccess) return e;
         }
     }
@@ -285,7 +285,7 @@ hipError_t apply_step(mpir_fact f, int64_t K, int w, int64_t c0, int64_t c1, hip
     }
     if (K + w < n) {
         ProfScope ps_(0, 2.0 * (double)(n - K - w) * (double)(c1 - c0) * w, s);
-        e = launch_gemm_update(f->mode, f->work, f->ld, K + w, n - K - w, c0, c1 - c0, K, w, 0, s);
+        e = launch_gemm_update(f->mode, f->work, f->ld, K + w, n - K - w, c0, c1 - c0, K, w, 0, 0, s);
     }
     return e;
 }
@@ -351,7 +351,7 @@ mpir_status getrf(mpir_fact f) {
         }
         if (K2 < n) {
             ProfScope ps_(0, 2.0 * (double)(n - K1) * (double)(n - K2) * w, s2);
-            HIPCHK(launch_gemm_update(f->mode, f->work, f->ld, K1, n - K1, K2, n - K2, K, w, cap2, s2));
+            HIPCHK(launch_gemm_update(f->mode, f->work, f->ld, K1, n - K1, K2, n - K2, K, w, cap2, 0, s2));
         }
         HIPCHK(hipEventRecord(evB[cur], s2));
         // ---- main stream: step p on panel p+1, then factor panel p+1 ----

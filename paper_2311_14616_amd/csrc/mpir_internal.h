@@ -140,10 +140,12 @@ hipError_t launch_trsm(int mode, void *a, int64_t ld, int64_t k, int w, int64_t 
                        int64_t c1, hipStream_t s);
 // a4: C[r0:r0+m, c0:c0+nc] -= A[r0:, k:k+kk] * A[k:k+kk, c0:] on one
 // row-major matrix (ld).  cap > 0: at most cap workgroups per compute unit
-// (the rest of each unit stays free for work on another stream).
+// (the rest of each unit stays free for work on another stream).  role: 0 =
+// trailing update, 1 = update inside a panel or a U12 block (a separate
+// kernel symbol, so that profiles tell them apart).
 hipError_t launch_gemm_update(int mode, void *a, int64_t ld, int64_t r0, int64_t m,
                               int64_t c0, int64_t nc, int64_t k, int64_t kk, int cap,
-                              hipStream_t s);
+                              int role, hipStream_t s);
 
 // a5: residual r = b - A x in TR, partial sums over column chunks then a
 // fixed-order reduction; ||r|| and ||x|| bits into the state.

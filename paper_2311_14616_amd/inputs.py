@@ -169,6 +169,42 @@ def wilkinson_operator(n: int, kappa: float, seed: int = 14616):
     return at32, b, xstar, sigma
 
 
+def wilkinson_operator_torch(n: int, kappa: float, device, seed: int = 14616,
+                             cols_per_chunk: int = 2048):
+    """``wilkinson_operator`` built on a torch device in column chunks (the
+    same draws; A32 bit for bit: the same elementwise FP64 operations in the
+    same order).  b = fl32(A32 * x*) is summed over columns in increasing
+    order in FP64 on the device.  Returns (At32 column-major, b32, xstar64,
+    sigma) as device tensors."""
+    import torch
+    rng = np.random.default_rng(seed)
+    v1 = rng.standard_normal(n)
+    v2 = rng.standard_normal(n)
+    xstar = rng.standard_normal(n)
+    i = np.arange(n, dtype=np.float64)
+    sigma = kappa ** (-(i / (n - 1)))
+    c1 = 2.0 / np.dot(v1, v1)
+    c2 = 2.0 / np.dot(v2, v2)
+    s = np.dot(v1 * sigma, v2)
+    T = lambda a: torch.from_numpy(np.ascontiguousarray(a)).to(device)
+    v1t, v2t, sgt, xt = T(v1), T(v2), T(sigma), T(xstar)
+    sv2, v1s = sgt * v2t, v1t * sgt
+    at = torch.empty((n, n), dtype=torch.float32, device=device)
+    b = torch.zeros(n, dtype=torch.float64, device=device)
+    for j0 in range(0, n, cols_per_chunk):
+        j1 = min(n, j0 + cols_per_chunk)
+        # column j of A: rows i -> a[i, j]; stored as at[j, i]
+        blk = ((-c2 * (sv2[None, :] * v2t[j0:j1, None])) - c1 * (v1t[None, :] * v1s[j0:j1, None])
+               + (c1 * c2 * s) * (v1t[None, :] * v2t[j0:j1, None]))
+        idx = torch.arange(j0, j1, device=device)
+        blk[idx - j0, idx] += sgt[idx]
+        at[j0:j1] = blk.to(torch.float32)
+        del blk
+    for j in range(n):
+        b += at[j].to(torch.float64) * xt[j]
+    return at, b.to(torch.float32), xt, sgt
+
+
 def random_dense(n: int, seed: int, dtype=np.float64, diag_shift: float = 0.0):
     """Gaussian matrix (column-major storage) for generic parity cases."""
     rng = np.random.default_rng(seed)

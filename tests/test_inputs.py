@@ -110,3 +110,24 @@ def test_wilkinson_singular_values():
     assert np.abs(np.sort(sv) - np.sort(sigma)).max() <= da
     assert abs(sigma[0] - 1.0) < 1e-15 and abs(sigma[-1] - 1 / kappa) < 1e-15 / kappa
     assert b.dtype == np.float32
+
+
+def test_wilkinson_torch_matches_host_generator():
+    """The device-side Wilkinson generator gives the same A32 bits as the
+    host one (same draws, same elementwise FP64 operations); b agrees to
+    FP32 rounding (its FP64 sum runs in another order)."""
+    torch = pytest.importorskip("torch")
+    for n, kappa in ((7, 1e4), (130, 1e7)):
+        at, b, xs, sg = I.wilkinson_operator(n, kappa, seed=5)
+        at2, b2, xs2, sg2 = I.wilkinson_operator_torch(n, kappa, "cpu", seed=5, cols_per_chunk=48)
+        assert np.array_equal(at, at2.numpy())
+        assert np.array_equal(xs, xs2.numpy()) and np.array_equal(sg, sg2.numpy())
+        assert np.allclose(b, b2.numpy(), rtol=2e-7, atol=0)
+
+
+def test_random_dense_is_seeded_column_major():
+    a = I.random_dense(5, 3)
+    b = I.random_dense(5, 3)
+    assert a.shape == (5, 5) and a.flags["C_CONTIGUOUS"] and np.array_equal(a, b)
+    c = I.random_dense(5, 3, dtype=np.float32, diag_shift=10.0)
+    assert c.dtype == np.float32 and np.all(np.diag(c) > 5.0)
