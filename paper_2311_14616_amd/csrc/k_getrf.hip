@@ -487,41 +487,39 @@ __global__ __launch_bounds__(256) void k_laswp(W *__restrict__ a, int64_t ld, in
     }
 }
 
-// U12 <- L11^{-1} U12 for rows [k, k+w), w <= 32, columns [c0, c1):
-// right-looking substitution, row t final at step t (F16: rounded to
-// binary16 then), rows below updated in parallel.
+// U12 <- L11^{-1} U12 for rows [k, k+w), w <= 32, columns [c0, c1): one
+// thread per column, L11 in LDS, the w entries of the column in registers,
+// no barrier inside the substitution.  Right-looking: row t is final at step
+// t (F16: rounded to binary16 then) and updates the rows below it.
 template <typename W, bool F16>
-__global__ __launch_bounds__(256) void k_trsm(W *__restrict__ a, int64_t ld, int64_t k, int w,
-                                              int64_t c0, int64_t c1) {
+__global__ __launch_bounds__(256) void k_trsm_col(W *__restrict__ a, int64_t ld, int64_t k, int w,
+                                                  int64_t c0, int64_t c1) {
     __shared__ W L[32][33];
-    __shared__ W X[32][65];
     const int tid = threadIdx.x;
-    const int64_t cb = c0 + (int64_t)blockIdx.x * 64;
-    const int ncol = (int)((c1 - cb) < 64 ? (c1 - cb) : 64);
     for (int e = tid; e < w * w; e += 256) {
         const int r = e / w, c = e - r * w;
         L[r][c] = a[(k + r) * ld + k + c];
     }
-    for (int e = tid; e < w * 64; e += 256) {
-        const int r = e / 64, c = e - r * 64;
-        if (c < ncol) X[r][c] = a[(k + r) * ld + cb + c];
-    }
     __syncthreads();
-    const int c = tid & 63, g = tid >> 6;
-    for (int t = 0; t < w; ++t) {
-        if (F16 && tid < 64) X[t][tid] = (W)round_f16((float)X[t][tid]);
-        __syncthreads();
-        const W xt = X[t][c];
-        for (int r = t + 1 + g; r < w; r += 4) {
-            const W prod = L[r][t] * xt;
-            X[r][c] = X[r][c] - prod;
+    const int64_t c = c0 + (int64_t)blockIdx.x * 256 + tid;
+    if (c >= c1) return;
+    W x[32];
+#pragma unroll
+    for (int t = 0; t < 32; ++t) x[t] = t < w ? a[(k + t) * ld + c] : (W)0;
+#pragma unroll
+    for (int t = 0; t < 32; ++t) {
+        if (t < w) {
+            if (F16) x[t] = (W)round_f16((float)x[t]);
+#pragma unroll
+            for (int s2 = t + 1; s2 < 32; ++s2) {
+                const W prod = L[s2][t] * x[t];
+                x[s2] = x[s2] - prod;
+            }
         }
-        __syncthreads();
     }
-    for (int e = tid; e < w * 64; e += 256) {
-        const int r = e / 64, cc = e - r * 64;
-        if (cc < ncol) a[(k + r) * ld + cb + cc] = X[r][cc];
-    }
+#pragma unroll
+    for (int t = 0; t < 32; ++t)
+        if (t < w) a[(k + t) * ld + c] = x[t];
 }
 
 int g_num_cus = 0;
@@ -537,6 +535,23 @@ int num_cus() {
     return g_num_cus;
 }
 
+// The leaf is launched as an ordinary kernel on the caller's queue: a
+// cooperative launch goes through a queue of its own, which costs a queue
+// switch before and after each leaf (about 10 ms per factorization at
+// N = 32768).  Every workgroup still becomes resident: at most 64
+// workgroups of one compute unit each, and whatever else runs on the device
+// meanwhile (the trailing update on the second stream) finishes on its own
+// and frees its units; the bounded waits turn anything else into
+// MPIR_ERR_DEVICE.  MPIR_LEAF_COOP=1 restores the cooperative launch.
+bool leaf_cooperative() {
+    static int env = -1;
+    if (env < 0) {
+        const char *e = std::getenv("MPIR_LEAF_COOP");
+        env = (e && e[0] == '1') ? 1 : 0;
+    }
+    return env == 1;
+}
+
 template <typename W, bool F16>
 hipError_t leaf_go(W *a, int64_t n, int64_t ld, int64_t k0, int w, int32_t *ipiv, int64_t *info,
                    PanelSync *ps, uint32_t *host_base, uint32_t *flags, hipStream_t s) {
@@ -548,6 +563,12 @@ hipError_t leaf_go(W *a, int64_t n, int64_t ld, int64_t k0, int w, int32_t *ipiv
     if (G == 1) {
         k_leaf<W, F16><<<1, kLeafNT, 0, s>>>(a, n, ld, k0, w, G, ipiv, info, ps, base, flags);
         return hipGetLastError();
+    }
+    if (!leaf_cooperative()) {
+        k_leaf<W, F16><<<G, kLeafNT, 0, s>>>(a, n, ld, k0, w, G, ipiv, info, ps, base, flags);
+        hipError_t e = hipGetLastError();
+        if (e == hipSuccess) *host_base = base + (uint32_t)w;
+        return e;
     }
     void *args[] = {&a, (void *)&n, (void *)&ld, (void *)&k0, (void *)&w, (void *)&G,
                     &ipiv, &info, &ps, &base, &flags};
@@ -610,10 +631,10 @@ hipError_t launch_laswp(int mode, void *a, int64_t n, int64_t ld, int64_t k0, in
 hipError_t launch_trsm(int mode, void *a, int64_t ld, int64_t k, int w, int64_t c0, int64_t c1,
                        hipStream_t s) {
     if (w <= 0 || w > 32 || c1 <= c0) return w <= 0 || w > 32 ? hipErrorInvalidValue : hipSuccess;
-    const unsigned nb = (unsigned)((c1 - c0 + 63) / 64);
-    if (mode == LU_F64) k_trsm<double, false><<<nb, 256, 0, s>>>((double *)a, ld, k, w, c0, c1);
-    else if (mode == LU_F32) k_trsm<float, false><<<nb, 256, 0, s>>>((float *)a, ld, k, w, c0, c1);
-    else k_trsm<float, true><<<nb, 256, 0, s>>>((float *)a, ld, k, w, c0, c1);
+    const unsigned nb = (unsigned)((c1 - c0 + 255) / 256);
+    if (mode == LU_F64) k_trsm_col<double, false><<<nb, 256, 0, s>>>((double *)a, ld, k, w, c0, c1);
+    else if (mode == LU_F32) k_trsm_col<float, false><<<nb, 256, 0, s>>>((float *)a, ld, k, w, c0, c1);
+    else k_trsm_col<float, true><<<nb, 256, 0, s>>>((float *)a, ld, k, w, c0, c1);
     return hipGetLastError();
 }
 
