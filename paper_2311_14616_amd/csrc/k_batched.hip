@@ -288,22 +288,23 @@ __global__ __launch_bounds__(NT) void k_batched(const BatchSys *__restrict__ sys
                 L11[r][c] = W[(int64_t)(k + r) * n + k + c];
             }
             __syncthreads();
-#pragma unroll 1
-            for (int c = k + w + tid; c < n; c += NT) {
-                float xv[PB];
-#pragma unroll
-                for (int t = 0; t < PB; ++t) xv[t] = t < w ? W[(int64_t)(k + t) * n + c] : 0.0f;
-#pragma unroll
-                for (int t = 0; t < PB; ++t) {
-                    if (F16) xv[t] = round_f16(xv[t]);
-#pragma unroll
-                    for (int s = t + 1; s < PB; ++s) {
-                        const float prod = L11[s][t] * xv[t];
-                        xv[s] = xv[s] - prod;
+            // one thread per column; the column lives in LDS (the panel
+            // buffer is free here), L11 is read from LDS by broadcast
+            for (int c0 = k + w; c0 < n; c0 += NT) {
+                const int c = c0 + tid;
+                float *xs = panel + tid;                    // xs[t * NT]
+                if (c < n) {
+                    for (int t = 0; t < w; ++t) xs[t * NT] = W[(int64_t)(k + t) * n + c];
+                    for (int t = 0; t < w; ++t) {
+                        float xt = xs[t * NT];
+                        if (F16) { xt = round_f16(xt); xs[t * NT] = xt; }
+                        for (int s2 = t + 1; s2 < w; ++s2) {
+                            const float prod = L11[s2][t] * xt;
+                            xs[s2 * NT] = xs[s2 * NT] - prod;
+                        }
                     }
+                    for (int t = 0; t < w; ++t) W[(int64_t)(k + t) * n + c] = xs[t * NT];
                 }
-#pragma unroll
-                for (int t = 0; t < PB; ++t) if (t < w) W[(int64_t)(k + t) * n + c] = xv[t];
             }
             __syncthreads();
             // trailing update A22 -= L21 U12 (K = w <= 32) in 32 x 32 blocks
