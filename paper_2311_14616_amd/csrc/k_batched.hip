@@ -47,10 +47,6 @@ __device__ __forceinline__ double pow2_ceil(double m) {
     return f == 0.5 ? ldexp(1.0, e - 1) : ldexp(1.0, e);
 }
 
-__device__ __forceinline__ bool better(double v, int i, double bv, int bi) {
-    return v > bv || (v == bv && i < bi);
-}
-
 // Max of a non-negative double over the workgroup (NaN wins), via bits.
 __device__ __forceinline__ double block_max(double v, uint64_t *red) {
     uint64_t b = (uint64_t)__double_as_longlong(v) & 0x7fffffffffffffffull;
@@ -80,12 +76,11 @@ __global__ __launch_bounds__(NT) void k_batched(const BatchSys *__restrict__ sys
     __shared__ float L11[PB][PB + 1];
     __shared__ int32_t piv[PB];
     __shared__ int32_t pdst[2 * PB], psrc[2 * PB];
-    __shared__ double red_v[NW];
-    __shared__ int red_i[NW];
+    __shared__ uint64_t redk[NW];
     __shared__ uint64_t redb[NW];
     __shared__ double tmp64[64];
     __shared__ double hist_r[MPIR_HIST_MAX], hist_d[MPIR_HIST_MAX];
-    __shared__ int s_sys, s_p, s_extra, s_info, s_flags;
+    __shared__ int s_sys, s_extra, s_info, s_flags;
     (void)tmp64;
 
     const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
@@ -178,30 +173,24 @@ __global__ __launch_bounds__(NT) void k_batched(const BatchSys *__restrict__ sys
             }
             __syncthreads();
             for (int j = 0; j < w; ++j) {
-                double bv = -1.0;
-                int bi = 0x7fffffff;
+                // first maximum of |a_rj|, r >= j: key = |v| bits above the
+                // complemented row, maximised by DPP in each wave, then over
+                // the waves by every thread
+                uint64_t key = 0;
                 for (int r = tid; r < m; r += NT)
                     if (r >= j) {
-                        const double v = fabs((double)panel[r * PP + j]);
-                        if (v > bv) { bv = v; bi = r; }
+                        const uint64_t kk = ((uint64_t)__float_as_uint(fabsf(panel[r * PP + j])) << 32) |
+                                            (uint64_t)(0xffffffffu - (uint32_t)r);
+                        key = kk > key ? kk : key;
                     }
-                for (int off = 32; off > 0; off >>= 1) {
-                    const double ov = __shfl_xor(bv, off);
-                    const int oi = __shfl_xor(bi, off);
-                    if (better(ov, oi, bv, bi)) { bv = ov; bi = oi; }
-                }
-                if (lane == 0) { red_v[wv] = bv; red_i[wv] = bi; }
+                key = wave_max_u64(key);
+                if (lane == 0) redk[wv] = key;
                 __syncthreads();
-                if (tid == 0) {
-                    double v0 = red_v[0];
-                    int i0 = red_i[0];
-                    for (int q = 1; q < NW; ++q)
-                        if (better(red_v[q], red_i[q], v0, i0)) { v0 = red_v[q]; i0 = red_i[q]; }
-                    s_p = i0;
-                    piv[j] = i0;
-                }
-                __syncthreads();
-                const int p = s_p;
+                uint64_t kb = redk[0];
+#pragma unroll
+                for (int q = 1; q < NW; ++q) kb = redk[q] > kb ? redk[q] : kb;
+                const int p = (int)(0xffffffffu - (uint32_t)kb);
+                if (tid == 0) piv[j] = p;
                 if (tid < w) {
                     const int c = tid;
                     const float t = panel[j * PP + c];
@@ -475,13 +464,23 @@ __global__ __launch_bounds__(NT) void k_batched(const BatchSys *__restrict__ sys
                 for (int i0 = 0; i0 < n; i0 += 64) {
                     const int rows = (n - i0) < 64 ? (n - i0) : 64;
                     // off-diagonal: wave wv handles rows i0 + wv*8 .. +8
-                    for (int rr = 0; rr < 8; ++rr) {
-                        const int i = i0 + wv * 8 + rr;
-                        float acc = 0.0f;
-                        if (wv * 8 + rr < rows)
-                            for (int c = lane; c < i0; c += 64) acc += W[(int64_t)i * n + c] * vy[c];
-                        for (int off = 32; off > 0; off >>= 1) acc += __shfl_xor(acc, off);
-                        if (lane == 0) tmp64[wv * 8 + rr] = acc;
+                    {
+                        // the wave's 8 rows side by side: 8 loads in flight
+                        float acc[8];
+#pragma unroll
+                        for (int rr = 0; rr < 8; ++rr) acc[rr] = 0.0f;
+                        for (int c = lane; c < i0; c += 64) {
+                            const float yc = vy[c];
+#pragma unroll
+                            for (int rr = 0; rr < 8; ++rr)
+                                if (wv * 8 + rr < rows) acc[rr] += W[(int64_t)(i0 + wv * 8 + rr) * n + c] * yc;
+                        }
+#pragma unroll
+                        for (int rr = 0; rr < 8; ++rr) {
+                            float a = acc[rr];
+                            for (int off = 32; off > 0; off >>= 1) a += __shfl_xor(a, off);
+                            if (lane == 0) tmp64[wv * 8 + rr] = a;
+                        }
                     }
                     __syncthreads();
                     if (wv == 0) {
@@ -507,13 +506,22 @@ __global__ __launch_bounds__(NT) void k_batched(const BatchSys *__restrict__ sys
                 // back substitution with U
                 for (int i0 = ((n - 1) / 64) * 64; i0 >= 0; i0 -= 64) {
                     const int rows = (n - i0) < 64 ? (n - i0) : 64;
-                    for (int rr = 0; rr < 8; ++rr) {
-                        const int i = i0 + wv * 8 + rr;
-                        float acc = 0.0f;
-                        if (wv * 8 + rr < rows)
-                            for (int c = i0 + 64 + lane; c < n; c += 64) acc += W[(int64_t)i * n + c] * vy[c];
-                        for (int off = 32; off > 0; off >>= 1) acc += __shfl_xor(acc, off);
-                        if (lane == 0) tmp64[wv * 8 + rr] = acc;
+                    {
+                        float acc[8];
+#pragma unroll
+                        for (int rr = 0; rr < 8; ++rr) acc[rr] = 0.0f;
+                        for (int c = i0 + 64 + lane; c < n; c += 64) {
+                            const float yc = vy[c];
+#pragma unroll
+                            for (int rr = 0; rr < 8; ++rr)
+                                if (wv * 8 + rr < rows) acc[rr] += W[(int64_t)(i0 + wv * 8 + rr) * n + c] * yc;
+                        }
+#pragma unroll
+                        for (int rr = 0; rr < 8; ++rr) {
+                            float a = acc[rr];
+                            for (int off = 32; off > 0; off >>= 1) a += __shfl_xor(a, off);
+                            if (lane == 0) tmp64[wv * 8 + rr] = a;
+                        }
                     }
                     __syncthreads();
                     if (wv == 0) {
@@ -553,7 +561,16 @@ __global__ __launch_bounds__(NT) void k_batched(const BatchSys *__restrict__ sys
                 for (int i = tid; i < n; i += NT) {
                     double acc = 0.0;
                     const TWt *col = A + i;
-                    for (int j = 0; j < n; ++j) acc += (double)col[(int64_t)j * lda] * vx[j];
+                    // 16 loads in flight per thread, then the sums in order
+                    int j = 0;
+                    for (; j + 16 <= n; j += 16) {
+                        TWt av[16];
+#pragma unroll
+                        for (int q = 0; q < 16; ++q) av[q] = col[(int64_t)(j + q) * lda];
+#pragma unroll
+                        for (int q = 0; q < 16; ++q) acc += (double)av[q] * vx[j + q];
+                    }
+                    for (; j < n; ++j) acc += (double)col[(int64_t)j * lda] * vx[j];
                     const double ri = (double)b[i] - acc;
                     vr[i] = ri;
                     rm = fmax(rm, fabs(ri));

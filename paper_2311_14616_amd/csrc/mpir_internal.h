@@ -98,6 +98,29 @@ template <> __device__ __forceinline__ float to_f<__half>(__half v) { return __h
 // Atomic max of a non-negative double through its bit pattern (IEEE order of
 // non-negative doubles equals the unsigned order of their bits; NaN maps to a
 // pattern above every finite value and infinity).
+// Maximum of a 64-bit key over the wave: DPP row shifts by 1, 2, 4, 8 inside
+// rows of 16 lanes, then the row broadcasts of lanes 15 and 31 (lanes that
+// receive nothing keep 0, the identity for keys >= 0); lane 63 ends with the
+// maximum, which readlane makes uniform.
+template <int CTRL, int RM>
+__device__ __forceinline__ uint64_t dpp_max_u64_step(uint64_t k) {
+    const uint32_t lo = (uint32_t)__builtin_amdgcn_update_dpp(0, (int)(uint32_t)k, CTRL, RM, 0xf, false);
+    const uint32_t hi = (uint32_t)__builtin_amdgcn_update_dpp(0, (int)(uint32_t)(k >> 32), CTRL, RM, 0xf, false);
+    const uint64_t t = ((uint64_t)hi << 32) | lo;
+    return t > k ? t : k;
+}
+__device__ __forceinline__ uint64_t wave_max_u64(uint64_t k) {
+    k = dpp_max_u64_step<0x111, 0xf>(k);
+    k = dpp_max_u64_step<0x112, 0xf>(k);
+    k = dpp_max_u64_step<0x114, 0xf>(k);
+    k = dpp_max_u64_step<0x118, 0xf>(k);
+    k = dpp_max_u64_step<0x142, 0xa>(k);
+    k = dpp_max_u64_step<0x143, 0xc>(k);
+    const uint32_t lo = (uint32_t)__builtin_amdgcn_readlane((int)(uint32_t)k, 63);
+    const uint32_t hi = (uint32_t)__builtin_amdgcn_readlane((int)(uint32_t)(k >> 32), 63);
+    return ((uint64_t)hi << 32) | lo;
+}
+
 __device__ __forceinline__ void atomic_max_nonneg(uint64_t *p, double v) {
     uint64_t bits = __double_as_longlong(v);
     atomicMax((unsigned long long *)p, (unsigned long long)bits);
