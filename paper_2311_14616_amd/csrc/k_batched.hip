@@ -110,29 +110,32 @@ __global__ __launch_bounds__(NT) void k_batched(const BatchSys *__restrict__ sys
         const int upd = (cfg >> 8) & 0xff;
 
         // ---------------- interchange-free copy A_F = fl_F(A), ||A||_inf ----
-        // 64 x 64 tiles: coalesced column reads, LDS transpose, coalesced row
-        // writes; row sums by one thread per row in increasing column order.
-        double *tile = reinterpret_cast<double *>(panel);   // [64][65] doubles
+        // 256 x 64 tiles: coalesced column reads, LDS transpose, coalesced
+        // row writes; row sums by one thread per row in increasing column
+        // order (256 rows summed side by side).
+        constexpr int TR = 256, TC = 64, TP = TR + 1;
+        double *tile = reinterpret_cast<double *>(panel);   // [TC][TP] doubles
+        static_assert(TC * TP * 2 <= PANEL_FLOATS, "tile fits the panel buffer");
         double amax = 0.0;                                  // max row sum seen by this thread
-        for (int i0 = 0; i0 < n; i0 += 64) {
+        for (int i0 = 0; i0 < n; i0 += TR) {
             double racc = 0.0;
-            for (int j0 = 0; j0 < n; j0 += 64) {
-                for (int e = tid; e < 64 * 64; e += NT) {
-                    const int r = e & 63, c = e >> 6;
+            for (int j0 = 0; j0 < n; j0 += TC) {
+                for (int e = tid; e < TR * TC; e += NT) {
+                    const int r = e % TR, c = e / TR;
                     const int i = i0 + r, j = j0 + c;
-                    tile[c * 65 + r] = (i < n && j < n) ? (double)A[i + (int64_t)j * lda] : 0.0;
+                    tile[c * TP + r] = (i < n && j < n) ? (double)A[i + (int64_t)j * lda] : 0.0;
                 }
                 __syncthreads();
-                if (tid < 64 && i0 + tid < n) {
-                    const int cmax = (n - j0) < 64 ? (n - j0) : 64;
-                    for (int c = 0; c < cmax; ++c) racc = racc + fabs(tile[c * 65 + tid]);
+                if (tid < TR && i0 + tid < n) {
+                    const int cmax = (n - j0) < TC ? (n - j0) : TC;
+                    for (int c = 0; c < cmax; ++c) racc = racc + fabs(tile[c * TP + tid]);
                 }
                 int fl = 0;
-                for (int e = tid; e < 64 * 64; e += NT) {
-                    const int c = e & 63, r = e >> 6;
+                for (int e = tid; e < TR * TC; e += NT) {
+                    const int c = e % TC, r = e / TC;
                     const int i = i0 + r, j = j0 + c;
                     if (i < n && j < n) {
-                        const double v = tile[c * 65 + r];
+                        const double v = tile[c * TP + r];
                         const float f = F16 ? d2h_as_float(v) : (float)v;
                         if (!isfinite(v)) fl |= DF_NONFINITE;
                         else if (isinf(f)) fl |= DF_RANGE;
@@ -142,7 +145,7 @@ __global__ __launch_bounds__(NT) void k_batched(const BatchSys *__restrict__ sys
                 if (fl) atomicOr(&s_flags, fl);
                 __syncthreads();
             }
-            if (tid < 64 && i0 + tid < n) {
+            if (tid < TR && i0 + tid < n) {
                 amax = fmax(amax, racc);
                 if (isnan(racc)) amax = racc;
             }
@@ -319,13 +322,20 @@ __global__ __launch_bounds__(NT) void k_batched(const BatchSys *__restrict__ sys
                                 const int kq = 16 * s2 + 8 * (lane >> 5) + q;
                                 bh[s2][q] = (_Float16)((bc < n && kq < w) ? W[(int64_t)(k + kq) * n + bc] : 0.0f);
                             }
+                        // C of the next block row is loaded while this one
+                        // is multiplied and stored
+                        float cv[16], cn[16];
+#pragma unroll
+                        for (int v = 0; v < 16; ++v) {
+                            const int row = r0 + 8 * (v >> 2) + 4 * (lane >> 5) + (v & 3);
+                            cv[v] = (row < n && bc < n) ? W[(int64_t)row * n + bc] : 0.0f;
+                        }
                         for (int bi = 0; bi < nbk; ++bi) {
                             const int rb = r0 + bi * 32, lr = bi * 32 + (lane & 31);
-                            float cv[16];
 #pragma unroll
                             for (int v = 0; v < 16; ++v) {
-                                const int row = rb + 8 * (v >> 2) + 4 * (lane >> 5) + (v & 3);
-                                cv[v] = (row < n && bc < n) ? W[(int64_t)row * n + bc] : 0.0f;
+                                const int row = rb + 32 + 8 * (v >> 2) + 4 * (lane >> 5) + (v & 3);
+                                cn[v] = (bi + 1 < nbk && row < n && bc < n) ? W[(int64_t)row * n + bc] : 0.0f;
                             }
                             floatx16 acc = floatx16{0};
 #pragma unroll
@@ -342,6 +352,7 @@ __global__ __launch_bounds__(NT) void k_batched(const BatchSys *__restrict__ sys
                             for (int v = 0; v < 16; ++v) {
                                 const int row = rb + 8 * (v >> 2) + 4 * (lane >> 5) + (v & 3);
                                 if (row < n && bc < n) W[(int64_t)row * n + bc] = cv[v] - acc[v];
+                                cv[v] = cn[v];
                             }
                         }
                     } else {
@@ -351,13 +362,18 @@ __global__ __launch_bounds__(NT) void k_batched(const BatchSys *__restrict__ sys
                             const int kq = 2 * s1 + (lane >> 5);
                             bf[s1] = (bc < n && kq < w) ? W[(int64_t)(k + kq) * n + bc] : 0.0f;
                         }
+                        float cv[16], cn[16];
+#pragma unroll
+                        for (int v = 0; v < 16; ++v) {
+                            const int row = r0 + 8 * (v >> 2) + 4 * (lane >> 5) + (v & 3);
+                            cv[v] = (row < n && bc < n) ? W[(int64_t)row * n + bc] : 0.0f;
+                        }
                         for (int bi = 0; bi < nbk; ++bi) {
                             const int rb = r0 + bi * 32, lr = bi * 32 + (lane & 31);
-                            float cv[16];
 #pragma unroll
                             for (int v = 0; v < 16; ++v) {
-                                const int row = rb + 8 * (v >> 2) + 4 * (lane >> 5) + (v & 3);
-                                cv[v] = (row < n && bc < n) ? W[(int64_t)row * n + bc] : 0.0f;
+                                const int row = rb + 32 + 8 * (v >> 2) + 4 * (lane >> 5) + (v & 3);
+                                cn[v] = (bi + 1 < nbk && row < n && bc < n) ? W[(int64_t)row * n + bc] : 0.0f;
                             }
                             floatx16 acc = floatx16{0};
 #pragma unroll
@@ -371,6 +387,7 @@ __global__ __launch_bounds__(NT) void k_batched(const BatchSys *__restrict__ sys
                             for (int v = 0; v < 16; ++v) {
                                 const int row = rb + 8 * (v >> 2) + 4 * (lane >> 5) + (v & 3);
                                 if (row < n && bc < n) W[(int64_t)row * n + bc] = cv[v] - acc[v];
+                                cv[v] = cn[v];
                             }
                         }
                     }
@@ -469,11 +486,22 @@ __global__ __launch_bounds__(NT) void k_batched(const BatchSys *__restrict__ sys
                         float acc[8];
 #pragma unroll
                         for (int rr = 0; rr < 8; ++rr) acc[rr] = 0.0f;
-                        for (int c = lane; c < i0; c += 64) {
-                            const float yc = vy[c];
+                        // four column strides per step: 32 loads in flight
+                        for (int cb = lane; cb < i0; cb += 256) {
+                            float yc[4], wr[8][4];
+#pragma unroll
+                            for (int u = 0; u < 4; ++u) yc[u] = cb + 64 * u < i0 ? vy[cb + 64 * u] : 0.0f;
 #pragma unroll
                             for (int rr = 0; rr < 8; ++rr)
-                                if (wv * 8 + rr < rows) acc[rr] += W[(int64_t)(i0 + wv * 8 + rr) * n + c] * yc;
+#pragma unroll
+                                for (int u = 0; u < 4; ++u)
+                                    wr[rr][u] = (wv * 8 + rr < rows && cb + 64 * u < i0)
+                                                    ? W[(int64_t)(i0 + wv * 8 + rr) * n + cb + 64 * u] : 0.0f;
+#pragma unroll
+                            for (int u = 0; u < 4; ++u)
+#pragma unroll
+                                for (int rr = 0; rr < 8; ++rr)
+                                    if (cb + 64 * u < i0) acc[rr] += wr[rr][u] * yc[u];
                         }
 #pragma unroll
                         for (int rr = 0; rr < 8; ++rr) {
@@ -496,7 +524,7 @@ __global__ __launch_bounds__(NT) void k_batched(const BatchSys *__restrict__ sys
                         }
 #pragma unroll
                         for (int jj = 0; jj < 64; ++jj) {
-                            const float yj = __shfl(z, jj);
+                            const float yj = __int_as_float(__builtin_amdgcn_readlane(__float_as_int(z), jj));
                             if (lane > jj) z -= drow[jj] * yj;
                         }
                         if (lane < rows) vy[i0 + lane] = z;
@@ -510,11 +538,21 @@ __global__ __launch_bounds__(NT) void k_batched(const BatchSys *__restrict__ sys
                         float acc[8];
 #pragma unroll
                         for (int rr = 0; rr < 8; ++rr) acc[rr] = 0.0f;
-                        for (int c = i0 + 64 + lane; c < n; c += 64) {
-                            const float yc = vy[c];
+                        for (int cb = i0 + 64 + lane; cb < n; cb += 256) {
+                            float yc[4], wr[8][4];
+#pragma unroll
+                            for (int u = 0; u < 4; ++u) yc[u] = cb + 64 * u < n ? vy[cb + 64 * u] : 0.0f;
 #pragma unroll
                             for (int rr = 0; rr < 8; ++rr)
-                                if (wv * 8 + rr < rows) acc[rr] += W[(int64_t)(i0 + wv * 8 + rr) * n + c] * yc;
+#pragma unroll
+                                for (int u = 0; u < 4; ++u)
+                                    wr[rr][u] = (wv * 8 + rr < rows && cb + 64 * u < n)
+                                                    ? W[(int64_t)(i0 + wv * 8 + rr) * n + cb + 64 * u] : 0.0f;
+#pragma unroll
+                            for (int u = 0; u < 4; ++u)
+#pragma unroll
+                                for (int rr = 0; rr < 8; ++rr)
+                                    if (cb + 64 * u < n) acc[rr] += wr[rr][u] * yc[u];
                         }
 #pragma unroll
                         for (int rr = 0; rr < 8; ++rr) {
@@ -538,7 +576,7 @@ __global__ __launch_bounds__(NT) void k_batched(const BatchSys *__restrict__ sys
 #pragma unroll
                         for (int jj = 63; jj >= 0; --jj) {
                             if (lane == jj && lane < rows) z = z / drow[jj];
-                            const float yj = __shfl(z, jj);
+                            const float yj = __int_as_float(__builtin_amdgcn_readlane(__float_as_int(z), jj));
                             if (lane < jj) z -= drow[jj] * yj;
                         }
                         if (lane < rows) vy[i0 + lane] = z;
