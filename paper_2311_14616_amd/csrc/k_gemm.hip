@@ -220,6 +220,142 @@ __global__ __launch_bounds__(256) void k_gemm_32(float *__restrict__ a, int64_t 
             }
 }
 
+// --------------------------------------- binary16 operands packed per step
+// For TF = F16, L21 and U12 hold binary16 numbers in the binary32 working
+// array.  They are packed once per update into binary16 copies with k
+// contiguous (A as m x kp, B transposed as n x kp; kp = kk rounded up to 32,
+// rows padded to 128, the padding zero), so the update reads half the bytes
+// with 16-byte loads that land directly in the MFMA operand layout.
+constexpr int kHT = 128;     // tile edge of the packed-operand update
+constexpr int kHK = 32;      // k per LDS stage
+
+__global__ __launch_bounds__(256) void k_pack_rows_h(const float *__restrict__ a, int64_t ld,
+                                                     int64_t r0, int64_t m, int64_t mp, int64_t k,
+                                                     int64_t kk, int64_t kp, _Float16 *__restrict__ out) {
+    // out[i][t] = a[r0 + i][k + t] (i < m, t < kk), zero padding
+    const int64_t tot = mp * (kp / 8);
+    for (int64_t e = (int64_t)blockIdx.x * 256 + threadIdx.x; e < tot; e += (int64_t)gridDim.x * 256) {
+        const int64_t i = e / (kp / 8), t0 = (e - i * (kp / 8)) * 8;
+        half8 h;
+#pragma unroll
+        for (int q = 0; q < 8; ++q)
+            h[q] = (_Float16)((i < m && t0 + q < kk) ? a[(r0 + i) * ld + k + t0 + q] : 0.0f);
+        *reinterpret_cast<half8 *>(out + i * kp + t0) = h;
+    }
+}
+
+__global__ __launch_bounds__(256) void k_pack_cols_h(const float *__restrict__ a, int64_t ld,
+                                                     int64_t k, int64_t kk, int64_t kp, int64_t c0,
+                                                     int64_t nc, int64_t np_, _Float16 *__restrict__ out) {
+    // out[j][t] = a[k + t][c0 + j] (j < nc, t < kk), zero padding; 64 x 64
+    // tiles transposed through LDS
+    __shared__ float tl[64][65];
+    const int tid = threadIdx.x;
+    const int64_t j0 = (int64_t)blockIdx.x * 64, t0 = (int64_t)blockIdx.y * 64;
+    for (int e = tid; e < 64 * 64; e += 256) {
+        const int tt = e / 64, jj = e % 64;
+        const int64_t t = t0 + tt, j = j0 + jj;
+        tl[tt][jj] = (t < kk && j < nc) ? a[(k + t) * ld + c0 + j] : 0.0f;
+    }
+    __syncthreads();
+    for (int e = tid; e < 64 * 8; e += 256) {
+        const int jj = e / 8, tq = (e % 8) * 8;
+        const int64_t j = j0 + jj, t = t0 + tq;
+        if (j < np_ && t < kp) {
+            half8 h;
+#pragma unroll
+            for (int q = 0; q < 8; ++q) h[q] = (_Float16)tl[tq + q][jj];
+            *reinterpret_cast<half8 *>(out + j * kp + t) = h;
+        }
+    }
+}
+
+// C[r0 + i][c0 + j] -= sum_t Ah[i][t] Bt[j][t]: 128 x 128 tiles, four waves
+// in a 2 x 2 grid of 64 x 64 (2 x 2 blocks of v_mfma_f32_32x32x16_f16),
+// double-buffered LDS stages of BK k; binary32 accumulators.
+template <int ROLE, int BK, int MINB>
+__global__ __launch_bounds__(256, MINB) void k_gemm_h16(float *__restrict__ a, int64_t ld, int64_t r0,
+                                                        int64_t m, int64_t c0, int64_t nc,
+                                                        const _Float16 *__restrict__ Ah,
+                                                        const _Float16 *__restrict__ Bt, int64_t kp,
+                                                        int tiles_n, int nblk) {
+    constexpr int P = BK + 8;                         // LDS pitch (halves)
+    constexpr int NV = BK / 16;                       // 8-half vectors per thread and operand
+    __shared__ __align__(16) _Float16 As[2][kHT * P];
+    __shared__ __align__(16) _Float16 Bs[2][kHT * P];
+    const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
+    const int bid = xcd_remap(blockIdx.x, nblk);
+    int trow, tcol;
+    tile_coords(bid, nblk / tiles_n, tiles_n, trow, tcol);
+    const int64_t tm = (int64_t)trow * kHT, tn = (int64_t)tcol * kHT;
+    const int wm = (wv >> 1) * 64, wn = (wv & 1) * 64;
+    // loads: thread -> row tid / 2, BK/2 consecutive k at (tid % 2) * BK/2
+    const int lr = tid >> 1, lk = (tid & 1) * (BK / 2);
+    const _Float16 *ap = Ah + (tm + lr) * kp + lk;
+    const _Float16 *bp = Bt + (tn + lr) * kp + lk;
+    half8 ra[NV], rb[NV];
+    auto load = [&](int64_t kc) {
+#pragma unroll
+        for (int q = 0; q < NV; ++q) {
+            ra[q] = *reinterpret_cast<const half8 *>(ap + kc + 8 * q);
+            rb[q] = *reinterpret_cast<const half8 *>(bp + kc + 8 * q);
+        }
+    };
+    auto store = [&](int buf) {
+#pragma unroll
+        for (int q = 0; q < NV; ++q) {
+            *reinterpret_cast<half8 *>(&As[buf][lr * P + lk + 8 * q]) = ra[q];
+            *reinterpret_cast<half8 *>(&Bs[buf][lr * P + lk + 8 * q]) = rb[q];
+        }
+    };
+    floatx16 acc[2][2];
+#pragma unroll
+    for (int i = 0; i < 2; ++i)
+#pragma unroll
+        for (int j = 0; j < 2; ++j) acc[i][j] = floatx16{0};
+    load(0);
+    store(0);
+    __syncthreads();
+    int buf = 0;
+    for (int64_t kc = 0; kc < kp; kc += BK) {
+        const bool more = kc + BK < kp;
+        if (more) load(kc + BK);
+#pragma unroll
+        for (int s2 = 0; s2 < BK; s2 += 16) {
+            const int kb = s2 + 8 * (lane >> 5);
+            half8 af[2], bf[2];
+#pragma unroll
+            for (int i = 0; i < 2; ++i)
+                af[i] = *reinterpret_cast<const half8 *>(&As[buf][(wm + i * 32 + (lane & 31)) * P + kb]);
+#pragma unroll
+            for (int j = 0; j < 2; ++j)
+                bf[j] = *reinterpret_cast<const half8 *>(&Bs[buf][(wn + j * 32 + (lane & 31)) * P + kb]);
+#pragma unroll
+            for (int i = 0; i < 2; ++i)
+#pragma unroll
+                for (int j = 0; j < 2; ++j)
+                    acc[i][j] = __builtin_amdgcn_mfma_f32_32x32x16_f16(af[i], bf[j], acc[i][j], 0, 0, 0);
+        }
+        if (more) store(buf ^ 1);
+        __syncthreads();
+        buf ^= 1;
+    }
+    // epilogue: lane l, register v -> row 8*(v/4) + 4*(l/32) + v%4, col l%32
+#pragma unroll
+    for (int i = 0; i < 2; ++i)
+#pragma unroll
+        for (int j = 0; j < 2; ++j)
+#pragma unroll
+            for (int v = 0; v < 16; ++v) {
+                const int64_t row = tm + wm + i * 32 + 8 * (v >> 2) + 4 * (lane >> 5) + (v & 3);
+                const int64_t col = tn + wn + j * 32 + (lane & 31);
+                if (row < m && col < nc) {
+                    float *p = a + (r0 + row) * ld + c0 + col;
+                    *p = *p - acc[i][j][v];
+                }
+            }
+}
+
 // ---------------------------------------------------------------- binary64
 // Workgroup tile BM x BN, K-chunk BK, two LDS buffers, four waves in a 2 x 2
 // grid, each wave (BM/2) x (BN/2) of C in 16 x 16 MFMA blocks.  A: TPR =
@@ -396,6 +532,35 @@ hipError_t gemm_go(int mode, void *a, int64_t ld, int64_t r0, int64_t m, int64_t
 }
 
 }  // namespace
+
+size_t gemm_h16_ws_halves(int64_t rows, int64_t kk) {
+    const int64_t rp = (rows + kHT - 1) / kHT * kHT, kp = (kk + kHK - 1) / kHK * kHK;
+    return (size_t)(rp * kp);
+}
+
+hipError_t launch_gemm_update_h16(float *a, int64_t ld, int64_t r0, int64_t m, int64_t c0, int64_t nc,
+                                  int64_t k, int64_t kk, __half *wa, __half *wb, int cap,
+                                  hipStream_t s) {
+    if (m <= 0 || nc <= 0 || kk <= 0) return hipSuccess;
+    const int64_t mp = (m + kHT - 1) / kHT * kHT, np_ = (nc + kHT - 1) / kHT * kHT;
+    const int64_t kp = (kk + kHK - 1) / kHK * kHK;
+    const int64_t tiles_m = mp / kHT, tiles_n = np_ / kHT, nblk = tiles_m * tiles_n;
+    if (nblk > 0x7fffffffll) return hipErrorInvalidValue;
+    _Float16 *Ah = reinterpret_cast<_Float16 *>(wa), *Bt = reinterpret_cast<_Float16 *>(wb);
+    {
+        const int64_t work = mp * (kp / 8);
+        const unsigned g = (unsigned)((work + 255) / 256 < 8192 ? (work + 255) / 256 : 8192);
+        k_pack_rows_h<<<g, 256, 0, s>>>(a, ld, r0, m, mp, k, kk, kp, Ah);
+        dim3 gb((unsigned)(np_ / 64), (unsigned)((kp + 63) / 64));
+        k_pack_cols_h<<<gb, 256, 0, s>>>(a, ld, k, kk, kp, c0, nc, np_, Bt);
+    }
+    auto kv = k_gemm_h16<0, kHK, 2>;
+    static int pad[9] = {-1, -1, -1, -1, -1, -1, -1, -1, -1};
+    const int ci = cap < 0 ? 0 : cap > 8 ? 8 : cap;
+    if (pad[ci] < 0) pad[ci] = cap_pad((const void *)kv, ci);
+    kv<<<(unsigned)nblk, 256, pad[ci], s>>>(a, ld, r0, m, c0, nc, Ah, Bt, kp, (int)tiles_n, (int)nblk);
+    return hipGetLastError();
+}
 
 hipError_t launch_gemm_update(int mode, void *a, int64_t ld, int64_t r0, int64_t m, int64_t c0,
                               int64_t nc, int64_t k, int64_t kk, int cap, int role, hipStream_t s) {

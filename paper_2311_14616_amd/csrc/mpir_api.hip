@@ -95,6 +95,7 @@ struct mpir_fact_s {
     hipStream_t stream = nullptr;
     void *work = nullptr;           // row-major working array (ld x n)
     __half *lu16 = nullptr;         // F16: packed binary16 factors
+    __half *hws[2][2] = {{nullptr, nullptr}, {nullptr, nullptr}};   // F16: binary16 update operands per stream
     int32_t *ipiv = nullptr, *perm = nullptr;
     int64_t *info_d = nullptr;
     uint32_t *flags_d = nullptr;
@@ -145,6 +146,8 @@ void free_handle(mpir_fact f) {
     if (!f) return;
     hipFree(f->work);
     hipFree(f->lu16);
+    for (auto &pr : f->hws)
+        for (auto *q : pr) hipFree(q);
     hipFree(f->ipiv);
     hipFree(f->perm);
     hipFree(f->info_d);
@@ -165,6 +168,8 @@ void free_handle(mpir_fact f) {
     delete f;
 }
 
+int panel_width(int mode);
+
 mpir_status alloc_handle(mpir_fact f) {
     const int64_t n = f->n;
     const size_t wes = f->mode == LU_F64 ? 8 : 4;
@@ -175,6 +180,12 @@ mpir_status alloc_handle(mpir_fact f) {
     if (f->ld % 1024 == 0) f->ld += 32;
     if (dalloc(&f->work, (size_t)f->ld * n * wes) != hipSuccess) return MPIR_ERR_ALLOC;
     if (f->tf == MPIR_F16 && dalloc(&f->lu16, (size_t)n * n * 2) != hipSuccess) return MPIR_ERR_ALLOC;
+    if (f->tf == MPIR_F16) {
+        const size_t hw = gemm_h16_ws_halves(n, panel_width(LU_F16)) * 2;
+        for (auto &pr : f->hws)
+            for (auto &q : pr)
+                if (dalloc(&q, hw) != hipSuccess) return MPIR_ERR_ALLOC;
+    }
     f->nchunks = residual_chunks(n);
     if (dalloc(&f->ipiv, n * 4) != hipSuccess || dalloc(&f->perm, n * 4) != hipSuccess ||
         dalloc(&f->info_d, 8) != hipSuccess || dalloc(&f->flags_d, 8) != hipSuccess ||
@@ -272,6 +283,16 @@ hipError_t factor_panel(mpir_fact f, int64_t K, int w, hipStream_t s) {
 
 // Step of panel [K, K+w) applied to the columns [c0, c1): interchanges,
 // U12, trailing update of rows [K+w, n).
+// Trailing update of rows [r0, r0+m) x columns [c0, c0+nc) by the panel
+// [k, k+kk); F16: binary16 operands packed first (workspace slot ws).
+hipError_t trailing_update(mpir_fact f, int64_t r0, int64_t m, int64_t c0, int64_t nc, int64_t k,
+                           int64_t kk, int cap, int ws, hipStream_t s) {
+    if (f->mode == LU_F16)
+        return launch_gemm_update_h16((float *)f->work, f->ld, r0, m, c0, nc, k, kk, f->hws[ws][0],
+                                      f->hws[ws][1], cap, s);
+    return launch_gemm_update(f->mode, f->work, f->ld, r0, m, c0, nc, k, kk, cap, 0, s);
+}
+
 hipError_t apply_step(mpir_fact f, int64_t K, int w, int64_t c0, int64_t c1, hipStream_t s) {
     if (c1 <= c0) return hipSuccess;
     const int64_t n = f->n;
@@ -285,7 +306,7 @@ hipError_t apply_step(mpir_fact f, int64_t K, int w, int64_t c0, int64_t c1, hip
     }
     if (K + w < n) {
         ProfScope ps_(0, 2.0 * (double)(n - K - w) * (double)(c1 - c0) * w, s);
-        e = launch_gemm_update(f->mode, f->work, f->ld, K + w, n - K - w, c0, c1 - c0, K, w, 0, 0, s);
+        e = trailing_update(f, K + w, n - K - w, c0, c1 - c0, K, w, 0, 0, s);
     }
     return e;
 }
@@ -351,7 +372,7 @@ mpir_status getrf(mpir_fact f) {
         }
         if (K2 < n) {
             ProfScope ps_(0, 2.0 * (double)(n - K1) * (double)(n - K2) * w, s2);
-            HIPCHK(launch_gemm_update(f->mode, f->work, f->ld, K1, n - K1, K2, n - K2, K, w, cap2, 0, s2));
+            HIPCHK(trailing_update(f, K1, n - K1, K2, n - K2, K, w, cap2, 1, s2));
         }
         HIPCHK(hipEventRecord(evB[cur], s2));
         // ---- main stream: step p on panel p+1, then factor panel p+1 ----

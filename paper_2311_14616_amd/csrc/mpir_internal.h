@@ -169,6 +169,13 @@ hipError_t launch_trsm(int mode, void *a, int64_t ld, int64_t k, int w, int64_t 
 hipError_t launch_gemm_update(int mode, void *a, int64_t ld, int64_t r0, int64_t m,
                               int64_t c0, int64_t nc, int64_t k, int64_t kk, int cap,
                               int role, hipStream_t s);
+// a4, TF = F16: the same trailing update with L21 and U12 first packed into
+// binary16 (k contiguous) in the workspaces wa (>= gemm_h16_ws_halves(m, kk)
+// halves) and wb (>= gemm_h16_ws_halves(nc, kk)).
+size_t gemm_h16_ws_halves(int64_t rows, int64_t kk);
+hipError_t launch_gemm_update_h16(float *a, int64_t ld, int64_t r0, int64_t m, int64_t c0,
+                                  int64_t nc, int64_t k, int64_t kk, __half *wa, __half *wb,
+                                  int cap, hipStream_t s);
 
 // a5: residual r = b - A x in TR, partial sums over column chunks then a
 // fixed-order reduction; ||r|| and ||x|| bits into the state.
