@@ -58,12 +58,21 @@ typedef enum {
 /* Termination parameters: the paper's TERM structure (Cr, Ce, Rmax, litmax)
  * plus the choice between eq. residterm (residterm = 1) and eq. term
  * (residterm = 0).  tol_rel > 0 replaces the factor C*u_w of either test
- * (u_w = eps(TW): 2^-52 for F64, 2^-23 for F32). */
+ * (u_w = eps(TW): 2^-52 for F64, 2^-23 for F32).
+ * onthefly selects the solve of each correction (section "Options and data
+ * structures for mplu", the onthefly keyword): 0 = low-precision solve (LPS:
+ * the scaled residual is rounded to TF and the substitutions run in binary32
+ * on the stored factors); 1 = mixed-precision solve (MPS: the residual stays
+ * in TW and the substitutions run in TW arithmetic, the stored TF factors
+ * promoted as they are read).  Single-system calls only: the batched calls
+ * take LPS and reject onthefly != 0 with MPIR_ERR_ARG. */
 typedef struct {
     double Cr, Ce, Rmax;
     int32_t litmax;             /* 1 .. MPIR_HIST_MAX-1 */
     int32_t residterm;
     double tol_rel;
+    int32_t onthefly;           /* 0 = LPS, 1 = MPS */
+    int32_t reserved;           /* must be 0 */
 } mpir_term;
 
 /* Iteration statistics (the paper's reporting=true output: rhist, dhist).
@@ -82,7 +91,7 @@ typedef struct {
 typedef struct mpir_fact_s *mpir_fact;
 
 /* Defaults of the paper's term_parms_default: Cr = Ce = 1, Rmax = .5,
- * litmax = 10, residterm = 1, tol_rel = 0. */
+ * litmax = 10, residterm = 1, tol_rel = 0; onthefly = 0. */
 void mpir_term_default(mpir_term *t);
 
 /* mplu (section "Options and data structures for mplu"): build the

@@ -384,7 +384,7 @@ double orc_pow2_ceil(double m)
  * info (first zero pivot).  hist_cap bounds rhist/dhist (>= litmax+1).
  * Returns ORC_OK, ORC_SINGULAR (no refinement done), or a negative error. */
 int orc_ir_solve(int64_t n, const void *A, int64_t lda, int tw, int tf, int tr,
-                 int lu_mode, int ts, const void *b, void *x,
+                 int lu_mode, int ts, int rhat_prec, const void *b, void *x,
                  double Cr, double Ce, double Rmax, int litmax, int residterm,
                  double tol_rel, int hist_cap,
                  int32_t *n_iter, int32_t *stop, double *rhist, double *dhist,
@@ -434,10 +434,12 @@ int orc_ir_solve(int64_t n, const void *A, int64_t lda, int tw, int tf, int tr,
         const double sigma = orc_pow2_ceil(rnorm);
         for (int64_t i = 0; i < n; ++i) y[i] = r[i];
         orc_apply_pivots(n, ipiv, y);
+        /* the scaled residual in the precision the solve takes it in: TF
+           for the low-precision solve, TW for the on-the-fly solve */
         for (int64_t i = 0; i < n; ++i) {
             double s = y[i] / sigma;
-            if (tf == ORC_F32) s = fl_s(s);
-            else if (tf == ORC_F16) s = orc_fl_h(s);
+            if (rhat_prec == ORC_F32) s = fl_s(s);
+            else if (rhat_prec == ORC_F16) s = orc_fl_h(s);
             y[i] = s;
         }
         orc_trsv_lu(n, af, ts, y);

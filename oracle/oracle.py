@@ -55,7 +55,7 @@ def lib():
         L.orc_pow2_ceil.argtypes = [d]
         L.orc_ir_solve.restype = C.c_int
         L.orc_ir_solve.argtypes = [i64, vp, i64, C.c_int, C.c_int, C.c_int,
-                                   C.c_int, C.c_int, vp, vp,
+                                   C.c_int, C.c_int, C.c_int, vp, vp,
                                    d, d, d, C.c_int, C.c_int, d, C.c_int,
                                    p(i32), p(i32), vp, vp, vp, p(i64)]
         L.orc_solve_f64.restype = C.c_int
@@ -180,13 +180,20 @@ def ir_solve(at: np.ndarray, b: np.ndarray, tf: int, tr: int | None = None,
              lu_mode: int | None = None, ts: int | None = None,
              Cr: float = 1.0, Ce: float = 1.0, Rmax: float = 0.5,
              litmax: int = 10, residterm: bool = True, tol_rel: float = 0.0,
-             lda: int | None = None) -> IRResult:
-    """Run Algorithm IR on A x = b (A given in column-major storage)."""
+             lda: int | None = None, onthefly: bool = False) -> IRResult:
+    """Run Algorithm IR on A x = b (A given in column-major storage).
+
+    onthefly: the mixed-precision solve of each correction (the package's
+    onthefly option): the scaled residual is not rounded to TF and the
+    substitutions run in TW arithmetic on the TF factors."""
     at = np.ascontiguousarray(at)
     tw = _prec_of(at)
     tr = tw if tr is None else tr
     lu_mode = default_lu_mode(tf) if lu_mode is None else lu_mode
-    ts = default_ts(tf) if ts is None else ts
+    mps = onthefly and tf != tw
+    if ts is None:
+        ts = (TS_F64 if tw == F64 else TS_F32) if mps else default_ts(tf)
+    rhat = tw if mps else tf
     n = at.shape[1]
     lda = n if lda is None else lda
     b = np.ascontiguousarray(b, dtype=_NP[tw])
@@ -196,7 +203,7 @@ def ir_solve(at: np.ndarray, b: np.ndarray, tf: int, tr: int | None = None,
     dh = np.zeros(cap, dtype=np.float64)
     out = np.zeros(5, dtype=np.float64)
     nit, stop, info = C.c_int32(0), C.c_int32(0), C.c_int64(0)
-    st = lib().orc_ir_solve(n, _ptr(at), lda, tw, tf, tr, lu_mode, ts,
+    st = lib().orc_ir_solve(n, _ptr(at), lda, tw, tf, tr, lu_mode, ts, rhat,
                             _ptr(b), _ptr(x), Cr, Ce, Rmax, litmax,
                             1 if residterm else 0, tol_rel, cap,
                             C.byref(nit), C.byref(stop), _ptr(rh), _ptr(dh),

@@ -197,10 +197,15 @@ hipError_t go(const Ft *LU, int64_t n, int64_t ld, Yt *y, uint64_t *yw, TrsvSync
 
 }  // namespace
 
-hipError_t launch_trsv(int tf, const void *LU, int64_t n, int64_t ld, void *y, uint64_t *yw,
+hipError_t launch_trsv(int tf, int ysol, const void *LU, int64_t n, int64_t ld, void *y, uint64_t *yw,
                        TrsvSync *ts, uint32_t *flags, const IrState *st, int force, hipStream_t s) {
     if (n <= 0) return hipSuccess;
     if (tf == MPIR_F64) return go<double, double>((const double *)LU, n, ld, (double *)y, yw, ts, flags, st, force, s);
+    if (ysol == MPIR_F64) {
+        // binary64 substitutions on binary32 / binary16 factors (MPS)
+        if (tf == MPIR_F32) return go<float, double>((const float *)LU, n, ld, (double *)y, yw, ts, flags, st, force, s);
+        return go<__half, double>((const __half *)LU, n, ld, (double *)y, yw, ts, flags, st, force, s);
+    }
     if (tf == MPIR_F32) return go<float, float>((const float *)LU, n, ld, (float *)y, yw, ts, flags, st, force, s);
     return go<__half, float>((const __half *)LU, n, ld, (float *)y, yw, ts, flags, st, force, s);
 }

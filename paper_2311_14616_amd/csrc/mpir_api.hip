@@ -455,6 +455,8 @@ void mpir_term_default(mpir_term *t) {
     t->litmax = 10;
     t->residterm = 1;
     t->tol_rel = 0.0;
+    t->onthefly = 0;
+    t->reserved = 0;
 }
 
 const char *mpir_status_str(mpir_status s) {
@@ -522,7 +524,8 @@ mpir_status mpir_solve(mpir_fact f, const void *db, void *dx) {
     HIPCHK(launch_scale_permute(n, f->tr, f->tf, f->r, f->perm, f->rhat, f->st, f->ts, 1, s));
     {
         ProfScope ps_(2, 2.0 * (double)n * n, s);
-        HIPCHK(launch_trsv(f->tf, factors_ptr(f), n, f->tf == MPIR_F16 ? n : f->ld, f->rhat, f->yw,
+        HIPCHK(launch_trsv(f->tf, f->tf == MPIR_F64 ? MPIR_F64 : MPIR_F32, factors_ptr(f), n,
+                           f->tf == MPIR_F16 ? n : f->ld, f->rhat, f->yw,
                            f->ts, f->flags_d, f->st, 1, s));
     }
     HIPCHK(launch_update(n, f->tw, f->tf, f->rhat, dx, f->st, 1, s));
@@ -540,6 +543,7 @@ mpir_status mpir_ir_solve(mpir_fact f, const void *db, void *dx, const mpir_term
     if (t) term = *t;
     else mpir_term_default(&term);
     if (term.litmax < 1 || term.litmax > MPIR_HIST_MAX - 1 || !(term.Rmax > 0.0)) return MPIR_ERR_ARG;
+    if ((term.onthefly != 0 && term.onthefly != 1) || term.reserved != 0) return MPIR_ERR_ARG;
     if (rep) {
         std::memset(rep, 0, sizeof(*rep));
         rep->info = f->info;
@@ -569,13 +573,19 @@ mpir_status mpir_ir_solve(mpir_fact f, const void *db, void *dx, const mpir_term
     const void *LU = factors_ptr(f);
     const int64_t lld = f->tf == MPIR_F16 ? n : f->ld;
     const size_t twes = esize(f->tw);
+    // LPS: the scaled residual rounded to TF, binary32 substitutions (binary64
+    // for TF = F64).  MPS: the residual kept in TW, substitutions in TW
+    // arithmetic on the promoted factors (the same solve when TF = TW).
+    const bool mps = term.onthefly && f->tf != f->tw;
+    const int rprec = mps ? f->tw : f->tf;                     // rounding of rhat
+    const int yprec = mps ? f->tw : (f->tf == MPIR_F64 ? MPIR_F64 : MPIR_F32);
     for (int it = 0; it < term.litmax; ++it) {
-        HIPCHK(launch_scale_permute(n, f->tr, f->tf, f->r, f->perm, f->rhat, f->st, f->ts, 0, s));
+        HIPCHK(launch_scale_permute(n, f->tr, rprec, f->r, f->perm, f->rhat, f->st, f->ts, 0, s));
         {
             ProfScope ps_(2, 2.0 * (double)n * n, s);
-            HIPCHK(launch_trsv(f->tf, LU, n, lld, f->rhat, f->yw, f->ts, f->flags_d, f->st, 0, s));
+            HIPCHK(launch_trsv(f->tf, yprec, LU, n, lld, f->rhat, f->yw, f->ts, f->flags_d, f->st, 0, s));
         }
-        HIPCHK(launch_update(n, f->tw, f->tf, f->rhat, dx, f->st, 0, s));
+        HIPCHK(launch_update(n, f->tw, rprec, f->rhat, dx, f->st, 0, s));
         {
             ProfScope ps_(3, (double)n * n * twes, s);
             HIPCHK(launch_residual(n, f->A, f->lda, f->tw, f->tr, db, dx, f->r, f->partial, f->nchunks,
@@ -787,6 +797,7 @@ mpir_status batch_create_with(int32_t batch, const int64_t *n, const void *const
     if (t) term = *t;
     else mpir_term_default(&term);
     if (term.litmax < 1 || term.litmax > MPIR_HIST_MAX - 1 || !(term.Rmax > 0.0)) return MPIR_ERR_ARG;
+    if (term.onthefly != 0 || term.reserved != 0) return MPIR_ERR_ARG;   // batched: LPS only
     int64_t total = 0, totn = 0;
     for (int32_t k = 0; k < batch; ++k) {
         if (n[k] <= 0 || n[k] > batched_max_n() || lda[k] < n[k] || !dA[k] || !db[k] || !dx[k])

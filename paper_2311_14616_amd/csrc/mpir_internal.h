@@ -210,7 +210,7 @@ hipError_t launch_batched(int tw, int tf, const BatchSys *sys, const int32_t *or
 // a7: triangular solves with the packed factors (row-major, TF storage).
 // y is float for TF in {F32, F16}, double for F64.
 // yw: n * 2 epoch-tagged 64-bit words (zeroed once at allocation).
-hipError_t launch_trsv(int tf, const void *LU, int64_t n, int64_t ld, void *y, uint64_t *yw,
+hipError_t launch_trsv(int tf, int ysol, const void *LU, int64_t n, int64_t ld, void *y, uint64_t *yw,
                        TrsvSync *ts, uint32_t *flags, const IrState *st, int force,
                        hipStream_t s);
 

@@ -43,7 +43,8 @@ class MpirError(RuntimeError):
 
 class Term(C.Structure):
     _fields_ = [("Cr", C.c_double), ("Ce", C.c_double), ("Rmax", C.c_double),
-                ("litmax", C.c_int32), ("residterm", C.c_int32), ("tol_rel", C.c_double)]
+                ("litmax", C.c_int32), ("residterm", C.c_int32), ("tol_rel", C.c_double),
+                ("onthefly", C.c_int32), ("reserved", C.c_int32)]
 
 
 TUNE_CLASSES = 8
@@ -178,9 +179,11 @@ def _dev_ptr(t) -> C.c_void_p:
     return C.c_void_p(t.data_ptr())
 
 
-def term(Cr=1.0, Ce=1.0, Rmax=0.5, litmax=10, residterm=True, tol_rel=0.0) -> Term:
-    """The paper's TERM parameters (defaults = term_parms_default)."""
-    return Term(Cr, Ce, Rmax, litmax, 1 if residterm else 0, tol_rel)
+def term(Cr=1.0, Ce=1.0, Rmax=0.5, litmax=10, residterm=True, tol_rel=0.0,
+         onthefly=False) -> Term:
+    """The paper's TERM parameters (defaults = term_parms_default) and the
+    solve form (onthefly: MPS instead of LPS)."""
+    return Term(Cr, Ce, Rmax, litmax, 1 if residterm else 0, tol_rel, 1 if onthefly else 0, 0)
 
 
 class Factorization:

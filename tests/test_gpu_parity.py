@@ -249,6 +249,49 @@ def test_ir_parity(M, orc, name, n, alpha, tf):
     say(f"  n_iter gpu={rep.n_iter} oracle={ref.n_iter} bwd={rep.bwd_err:.2e} ferr={ferr:.2e}")
 
 
+MPS_CASES = [("gmat", 512, 1.0, "f32"), ("gmat", 1100, 10.0, "f32"), ("gmat", 700, 10.0, "f16"),
+             ("gmat", 300, 100.0, "f16"), ("rand", 650, 0.0, "f16")]
+
+
+@pytest.mark.parametrize("name,n,alpha,tf", MPS_CASES)
+def test_ir_onthefly_parity(M, orc, name, n, alpha, tf):
+    """The mixed-precision (onthefly) solve: binary64 substitutions on the
+    TF factors, the residual not rounded to TF, against the oracle's."""
+    say(f"ir onthefly {name} n={n} alpha={alpha} tf={tf}")
+    if name == "gmat":
+        at = I.gmat_operator(n, alpha)
+    else:
+        at = I.random_dense(n, 17, diag_shift=2.0 * np.sqrt(n))
+    b = I.rhs_ones(at)
+    tp = M.term(tol_rel=1e-14, litmax=20, onthefly=True)
+    x, rep = M.ir_solve(dev(at), dev(b), TF[tf], term_parms=tp)
+    ref = orc.ir_solve(at, b, TF[tf], tol_rel=1e-14, litmax=20, onthefly=True)
+    lps = orc.ir_solve(at, b, TF[tf], tol_rel=1e-14, litmax=20)
+    xg = x.cpu().numpy()
+    assert rep.stop_name == ref.stop_name == "converged"
+    assert abs(rep.n_iter - ref.n_iter) <= 1
+    assert rep.bwd_err <= 1e-14 and ref.bwd_err <= 1e-14
+    xref, _, _ = orc.solve_f64(at, b)
+    ferr = np.abs(xg - xref).max() / np.abs(xref).max()
+    kappa = np.abs(at).sum(0).max() * np.abs(np.linalg.inv(at.T)).sum(1).max()
+    assert ferr <= 1e-12 * kappa * (2.0**-53 / 1e-16)
+    say(f"  n_iter gpu={rep.n_iter} oracle={ref.n_iter} (LPS oracle {lps.n_iter}) bwd={rep.bwd_err:.2e}")
+
+
+def test_ir_onthefly_single_working_precision(M, orc):
+    """TW = F32, TF = F16, TR = F64 (eq. wilkterm) with the onthefly solve:
+    the substitutions run in binary32 on the binary16 factors."""
+    say("ir onthefly tw=f32 tf=f16")
+    at32, b32, xstar, _ = I.wilkinson_operator(500, 1e3, seed=77)
+    tp = M.term(litmax=20, onthefly=True)
+    x, rep = M.ir_solve(dev(at32), dev(b32), M.F16, tr=M.F64, term_parms=tp)
+    ref = orc.ir_solve(at32, b32, orc.F16, tr=orc.F64, litmax=20, onthefly=True)
+    assert rep.stop_name == ref.stop_name
+    assert abs(rep.n_iter - ref.n_iter) <= 1
+    xg = x.cpu().numpy().astype(np.float64)
+    assert np.abs(xg - ref.x).max() <= 4 * 2.0**-24 * np.abs(ref.x).max()
+
+
 def test_ir_zero_rhs_and_nonfinite(M):
     say("ir zero rhs / nonfinite")
     n = 50

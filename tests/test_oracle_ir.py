@@ -169,3 +169,52 @@ def test_tiny_rhs_is_scaled_before_half_downcast(orc):
     b = I.rhs_ones(at) * 1e-10
     r = orc.ir_solve(at, b, orc.F16, tol_rel=1e-14, litmax=20)
     assert r.stop_name == "converged" and np.abs(r.x - 1e-10).max() <= 1e-23
+
+
+@pytest.mark.parametrize("tf", ["F32", "F16"])
+def test_onthefly_first_correction_is_binary64_solve_with_tf_factors(orc, tf):
+    """MPS (the onthefly solve): the first correction is b pushed through the
+    TF factors in binary64 arithmetic, without rounding b to TF.  Pinned
+    against scipy's triangular solves (LAPACK trtrs) on the same factors."""
+    sl = pytest.importorskip("scipy.linalg")
+    n = 160
+    at = I.random_dense(n, 31, diag_shift=4.0 * np.sqrt(n))
+    b = np.random.default_rng(4).standard_normal(n)
+    T = getattr(orc, tf)
+    r = orc.ir_solve(at, b, T, litmax=1, onthefly=True)
+    af, _, _ = orc.downcast(at, T)
+    lu, ipiv, info, _ = orc.lu(af, {"F32": orc.LU_F32, "F16": orc.LU_F16MIXED}[tf])
+    y = b.copy()
+    for k, p in enumerate(ipiv):
+        y[[k, p]] = y[[p, k]]
+    L = np.tril(lu, -1) + np.eye(n)
+    U = np.triu(lu)
+    ref = sl.solve_triangular(U, sl.solve_triangular(L, y, lower=True, unit_diagonal=True))
+    assert r.n_iter == 1
+    assert np.abs(r.x - ref).max() <= 1e-12 * np.abs(ref).max()
+    # the low-precision solve rounds b to TF first: visibly different for F16
+    r_lps = orc.ir_solve(at, b, T, litmax=1)
+    if tf == "F16":
+        assert np.abs(r_lps.x - ref).max() > 1e3 * np.abs(r.x - ref).max()
+
+
+def test_onthefly_equals_lps_when_tf_is_tw(orc):
+    n = 120
+    at = I.random_dense(n, 8)
+    b = np.random.default_rng(9).standard_normal(n)
+    a = orc.ir_solve(at, b, orc.F64, litmax=3)
+    c = orc.ir_solve(at, b, orc.F64, litmax=3, onthefly=True)
+    assert np.array_equal(a.x, c.x) and a.n_iter == c.n_iter
+
+
+def test_onthefly_half_converges_at_least_as_fast(orc):
+    """On the paper's operator with alpha = 10 the half-precision MPS solve
+    needs no more corrections than LPS (the residual is not rounded to FP16)."""
+    n = 1024
+    at = I.gmat_operator(n, 10.0)
+    b = I.rhs_ones(at)
+    lps = orc.ir_solve(at, b, orc.F16, tol_rel=1e-14, litmax=20)
+    mps = orc.ir_solve(at, b, orc.F16, tol_rel=1e-14, litmax=20, onthefly=True)
+    assert lps.stop_name == mps.stop_name == "converged"
+    assert mps.n_iter <= lps.n_iter
+    assert mps.bwd_err <= 1e-14
