@@ -346,3 +346,68 @@ def test_refactor_reuses_handle(M, orc):
     x, rep = f.ir_solve(dev(b), term_parms=M.term(tol_rel=1e-14, litmax=20))
     f.destroy()
     assert rep.stop_name == "converged" and rep.bwd_err <= 1e-14
+
+
+@pytest.mark.parametrize("tf", ["f32", "f16"])
+def test_full_size_factorization_and_solve(M, tf):
+    """The benchmark's configuration (N = 32768, A = I - Gmat, b = A*ones,
+    TW = TR = F64, the look-ahead schedule bench.py times).  Too large for
+    the oracle, so checked by properties that hold at any size: partial
+    pivoting keeps every |l_ij| <= 1; sampled entries of P A_F - L U within
+    eq. comperr's bound gamma_{3n}(u_F) (|L||U|)_ij (each entry computed on
+    its own in FP64); the refined x has backward error <= 1e-14 by an
+    independent FP64 residual and matches x* = ones."""
+    n = 32768
+    say(f"full size tf={tf} n={n}")
+    At = I.gmat_operator_torch(n, 1.0, DEV)
+    b = I.rhs_ones_torch(At)
+    T = TF[tf]
+    f = M.Factorization(At, T, M.F64)
+    lu, ipiv = f.factors()
+    L32 = lu.float() if tf == "f16" else lu
+    # |L| <= 1 everywhere below the diagonal
+    assert float(torch.tril(L32, -1).abs().max()) <= 1.0
+    # row permutation from the interchanges
+    perm = np.arange(n)
+    for k, p in enumerate(ipiv):
+        perm[[k, p]] = perm[[p, k]]
+    rng = np.random.default_rng(5)
+    ii = np.concatenate([rng.integers(0, n, 48), [0, 1, n - 1, n // 2]])
+    jj = np.concatenate([rng.integers(0, n, 48), [n - 1, 0, n - 1, n // 2]])
+    us = 2.0**-24
+    gam = 3 * n * us / (1 - 3 * n * us)          # gamma_3n(u_s): binary32 accumulation
+    if tf == "f16":
+        gam += 3 * 2.0**-11                     # binary16 L and U (the f16mixed bound)
+    for i, j in zip(ii.tolist(), jj.tolist()):
+        # (LU)_ij = sum_{k <= min(i,j)} l_ik u_kj with l_ii = 1
+        kmax = min(i, j)
+        lrow = L32[i, :kmax + 1].double().clone()
+        if i <= j:
+            lrow[i] = 1.0
+        ucol = L32[:kmax + 1, j].double()
+        prod = lrow * ucol
+        lu_ij = float(prod.sum())
+        bound_ij = float(prod.abs().sum())
+        a_ij = float(At[j, perm[i]])                       # A[perm[i], j], column-major storage
+        af = float(np.float32(a_ij)) if tf == "f32" else float(np.float16(a_ij))
+        # F16: binary16 multipliers below 2^-14 are subnormal (absolute
+        # error <= 2^-25 each), hence the absolute term
+        tol = gam * bound_ij + (2.0**-24 * (1.0 + float(ucol.abs().sum())) if tf == "f16" else 0.0)
+        assert abs(af - lu_ij) <= tol, (i, j, af, lu_ij, tol)
+    del lu, L32
+    x, rep = f.ir_solve(b, term_parms=M.term(tol_rel=1e-14, litmax=20))
+    f.destroy()
+    assert rep.stop_name == "converged"
+    # independent FP64 residual (row-block matvec of the caller's A)
+    r = b.clone()
+    for c0 in range(0, n, 4096):
+        r -= At[c0:c0 + 4096].t().matmul(x[c0:c0 + 4096])
+    rn = float(r.abs().max())
+    anorm = float(At.abs().sum(0).max())
+    bwd = rn / (anorm * float(x.abs().max()) + float(b.abs().max()))
+    say(f"  n_iter={rep.n_iter} bwd(gpu)={rep.bwd_err:.2e} bwd(torch)={bwd:.2e}")
+    assert bwd <= 1e-14 and rep.bwd_err <= 1e-14
+    # both residuals sit at the FP64 rounding floor of a length-32768 sum,
+    # where the summation order alone changes them by their own size
+    assert rep.relres <= 1e-14 and rn / float(b.abs().max()) <= 2e-14
+    assert float((x - 1.0).abs().max()) <= 1e-11
