@@ -17,26 +17,52 @@ namespace mpir {
 
 constexpr int kLeafMaxW = 32;     // columns per leaf
 constexpr int kLeafNT = 512;      // threads per leaf workgroup
-// rows per thread: two binary32 rows or one binary64 row (register budget)
-template <typename W> constexpr int leaf_rt() { return sizeof(W) == 4 ? 2 : 1; }
-template <typename W> constexpr int leaf_rows() { return kLeafNT * leaf_rt<W>(); }
+// Rows per thread: one, so that the local part of a column (argmax, swap,
+// rank-1 update) is as short as it can be; binary32 panels that would need
+// more than kLeafMaxG workgroups, or fit one workgroup at two rows per
+// thread (no exchange at all), take two (register budget: binary64 one).
+template <typename W> constexpr int leaf_rt_max() { return sizeof(W) == 4 ? 2 : 1; }
 constexpr int kLeafMaxG = 64;     // workgroups per leaf (one wave reads every slot)
 
-// Exchange area of the cooperative leaf.  Every value travels in 64-bit
-// words (32-bit payload | 32-bit epoch), so a reader that sees the current
-// epoch in a word also sees its payload: no barrier counter, no fences.
-// Per column parity and workgroup one slot holds the candidate header
-// (|value| in 2 words, row), the candidate row (1-2 words per column) and,
-// in workgroup 0's slot, the old row j -- all read in one round trip.
+// Exchange area of the leaf.  Every value travels in 64-bit words (32-bit
+// payload | 32-bit epoch), so a reader that sees the current epoch in a word
+// also sees its payload: no barrier counter, no fences.  Per column parity
+// each workgroup g posts its candidate header (|value| in 2 words, row) and
+// its candidate row (1-2 words per column); workgroup 0 also posts the old
+// row j.  Binary32 leaves use areas indexed [word][g]: lane g of the reading
+// wave loads word q of every workgroup with one coalesced load, so a poll of
+// all workgroups is a few dozen cache lines.  Binary64 leaves (two posting
+// and reading waves) keep one contiguous slot per workgroup: measured with a
+// concurrent binary64 update, the [word][g] form slowed them down many times
+// over, while binary32 leaves gain from it with or without that load.
 constexpr int kHeadWords = 4;
 constexpr int kRowWords = 2 * kLeafMaxW;
-struct LeafSlot {
+struct XchgWordMajor {
+    uint64_t head[2][kHeadWords][kLeafMaxG];
+    uint64_t row[2][kRowWords][kLeafMaxG];
+    uint64_t diag[2][kRowWords];
+};
+struct XchgSlot {
     uint64_t head[kHeadWords];
     uint64_t row[kRowWords];
     uint64_t diag[kRowWords];
 };
 struct PanelSync {
-    LeafSlot slot[2][kLeafMaxG];
+    XchgWordMajor wm;
+    XchgSlot slot[2][kLeafMaxG];
+};
+
+// Word addresses in the exchange area for a leaf whose values take K words.
+template <int K> struct Xchg;
+template <> struct Xchg<1> {
+    __device__ static uint64_t *head(PanelSync *ps, int par, int k, int g) { return &ps->wm.head[par][k][g]; }
+    __device__ static uint64_t *row(PanelSync *ps, int par, int q, int g) { return &ps->wm.row[par][q][g]; }
+    __device__ static uint64_t *diag(PanelSync *ps, int par, int q) { return &ps->wm.diag[par][q]; }
+};
+template <> struct Xchg<2> {
+    __device__ static uint64_t *head(PanelSync *ps, int par, int k, int g) { return &ps->slot[par][g].head[k]; }
+    __device__ static uint64_t *row(PanelSync *ps, int par, int q, int g) { return &ps->slot[par][g].row[q]; }
+    __device__ static uint64_t *diag(PanelSync *ps, int par, int q) { return &ps->slot[par][0].diag[q]; }
 };
 
 size_t panel_sync_bytes() { return sizeof(PanelSync); }
@@ -158,9 +184,9 @@ __device__ __forceinline__ Cd wave_max(Cd c) {
 }
 
 // Leaf factorization of rows [k0, n) x columns [k0, k0+w) of the working
-// array.  Workgroup g owns relative rows [g*R, g*R+R) (R = 512 per row of a
-// thread: 1024 binary32, 512 binary64), thread t rows g*R + t (+ 512), the
-// 32 leaf entries of each in registers.
+// array.  Workgroup g owns relative rows [g*R, g*R+R) (R = 512 RT, RT rows
+// per thread), thread t rows g*R + t (+ 512), the 32 leaf entries of each in
+// registers.
 // The registers rotate: before column j, R[c] holds column j+c for
 // c < 32-j and the finished column c-(32-j) above; each column shifts them
 // left by one as it updates, so the column loop is not unrolled and every
@@ -171,7 +197,7 @@ __device__ __forceinline__ Cd wave_max(Cd c) {
 // rank-1 update.  F16: the pivot row is rounded to binary16 when it becomes
 // the pivot row, each multiplier to binary16 when formed (products of
 // binary16 numbers are exact in binary32).
-template <typename W, bool F16>
+template <typename W, bool F16, int RT>
 __global__ __launch_bounds__(kLeafNT) void k_leaf(W *__restrict__ a, int64_t n, int64_t ld,
                                                   int64_t k0, int w, int G,
                                                   int32_t *__restrict__ ipiv, int64_t *info,
@@ -179,6 +205,7 @@ __global__ __launch_bounds__(kLeafNT) void k_leaf(W *__restrict__ a, int64_t n, 
     using Wd = Words<W>;
     using Cd = Cand<W>;
     constexpr int K = Wd::K;
+    using Xc = Xchg<K>;
     constexpr int C = kLeafMaxW;
     constexpr int NWV = kLeafNT / 64;
     __shared__ Cd red[NWV];
@@ -191,8 +218,8 @@ __global__ __launch_bounds__(kLeafNT) void k_leaf(W *__restrict__ a, int64_t n, 
 
     const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
     const int64_t m = n - k0;
-    constexpr int kLeafRT = leaf_rt<W>();
-    const int64_t r0 = (int64_t)blockIdx.x * leaf_rows<W>();
+    constexpr int kLeafRT = RT;
+    const int64_t r0 = (int64_t)blockIdx.x * (kLeafNT * RT);
     // an earlier launch already timed out: every workgroup returns at once
     if (__hip_atomic_load(flags, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) & DF_TIMEOUT) return;
     if (tid == 0) s_bad = 0;
@@ -267,50 +294,49 @@ __global__ __launch_bounds__(kLeafNT) void k_leaf(W *__restrict__ a, int64_t n, 
             // wv posts and reads words [32 wv, 32 wv + 32) of every slot
             // (value c lives in words K c .. K c + K-1, low word first).
             if (wv < K) {
-                LeafSlot *my = &ps->slot[par][blockIdx.x];
+                const int g = blockIdx.x;
                 const bool own_j = blockIdx.x == 0;        // relative row j < 32 <= R
-                const int wb0 = wv * 32;
+                const int wb0 = __builtin_amdgcn_readfirstlane(wv) * 32;   // wave-uniform: scalar base addresses
                 const uint32_t *cw = crow;
                 const uint32_t *ow = orow;
                 if (lane < 32) {
-                    put_word(&my->row[wb0 + lane], cw[wb0 + lane], epoch);
-                    if (own_j) put_word(&my->diag[wb0 + lane], ow[wb0 + lane], epoch);
+                    put_word(Xc::row(ps, par, wb0 + lane, g), cw[wb0 + lane], epoch);
+                    if (own_j) put_word(Xc::diag(ps, par, wb0 + lane), ow[wb0 + lane], epoch);
                 }
                 if (wv == 0 && lane == 32) {
                     const uint64_t vb = best.vbits();
-                    put_word(&my->head[0], (uint32_t)vb, epoch);
-                    put_word(&my->head[1], (uint32_t)(vb >> 32), epoch);
-                    put_word(&my->head[2], (uint32_t)(best.valid() ? bi : 0x7fffffff), epoch);
+                    put_word(Xc::head(ps, par, 0, g), (uint32_t)vb, epoch);
+                    put_word(Xc::head(ps, par, 1, g), (uint32_t)(vb >> 32), epoch);
+                    put_word(Xc::head(ps, par, 2, g), (uint32_t)(best.valid() ? bi : 0x7fffffff), epoch);
                 }
                 // ---- every slot (lane g <-> workgroup g), one round trip ----
                 uint32_t rw[32];
 #pragma unroll
                 for (int q = 0; q < 32; ++q) rw[q] = 0;
                 uint32_t dw = 0;
-                const LeafSlot *sl = &ps->slot[par][lane < G ? lane : 0];
-                const LeafSlot *s0 = &ps->slot[par][0];
+                const int gl = lane < G ? lane : 0;
                 bool okh = lane >= G, okr = lane >= G, okd = own_j || lane >= 32;
                 uint64_t h0 = 0, h1 = 0, h2 = 0;
                 uint64_t spins = 0;
                 for (;;) {
                     if (!okh) {
-                        h0 = get_word(&sl->head[0]);
-                        h1 = get_word(&sl->head[1]);
-                        h2 = get_word(&sl->head[2]);
+                        h0 = get_word(Xc::head(ps, par, 0, gl));
+                        h1 = get_word(Xc::head(ps, par, 1, gl));
+                        h2 = get_word(Xc::head(ps, par, 2, gl));
                         okh = word_ok(h0, epoch) && word_ok(h1, epoch) && word_ok(h2, epoch);
                     }
                     if (!okr) {
                         bool ok = true;
 #pragma unroll
                         for (int q = 0; q < 32; ++q) {
-                            const uint64_t x = get_word(&sl->row[wb0 + q]);
+                            const uint64_t x = get_word(Xc::row(ps, par, wb0 + q, gl));
                             ok = ok && word_ok(x, epoch);
                             rw[q] = (uint32_t)x;
                         }
                         okr = ok;
                     }
                     if (!okd) {
-                        const uint64_t x = get_word(&s0->diag[wb0 + lane]);
+                        const uint64_t x = get_word(Xc::diag(ps, par, wb0 + lane));
                         okd = word_ok(x, epoch);
                         dw = (uint32_t)x;
                     }
@@ -552,37 +578,51 @@ bool leaf_cooperative() {
     return env == 1;
 }
 
-template <typename W, bool F16>
-hipError_t leaf_go(W *a, int64_t n, int64_t ld, int64_t k0, int w, int32_t *ipiv, int64_t *info,
-                   PanelSync *ps, uint32_t *host_base, uint32_t *flags, hipStream_t s) {
+int leaf_gmax() { return num_cus() < kLeafMaxG ? num_cus() : kLeafMaxG; }
+
+template <typename W, bool F16, int RT>
+hipError_t leaf_run(W *a, int64_t n, int64_t ld, int64_t k0, int w, int32_t *ipiv, int64_t *info,
+                    PanelSync *ps, uint32_t *host_base, uint32_t *flags, hipStream_t s) {
     const int64_t m = n - k0;
-    const int64_t G64 = (m + leaf_rows<W>() - 1) / leaf_rows<W>();
-    if (G64 > kLeafMaxG) return hipErrorInvalidValue;
+    const int64_t G64 = (m + kLeafNT * RT - 1) / (kLeafNT * RT);
+    if (G64 > leaf_gmax()) return hipErrorInvalidValue;
     const int G = (int)G64;
     uint32_t base = *host_base;
     if (G == 1) {
-        k_leaf<W, F16><<<1, kLeafNT, 0, s>>>(a, n, ld, k0, w, G, ipiv, info, ps, base, flags);
+        k_leaf<W, F16, RT><<<1, kLeafNT, 0, s>>>(a, n, ld, k0, w, G, ipiv, info, ps, base, flags);
         return hipGetLastError();
     }
     if (!leaf_cooperative()) {
-        k_leaf<W, F16><<<G, kLeafNT, 0, s>>>(a, n, ld, k0, w, G, ipiv, info, ps, base, flags);
+        k_leaf<W, F16, RT><<<G, kLeafNT, 0, s>>>(a, n, ld, k0, w, G, ipiv, info, ps, base, flags);
         hipError_t e = hipGetLastError();
         if (e == hipSuccess) *host_base = base + (uint32_t)w;
         return e;
     }
     void *args[] = {&a, (void *)&n, (void *)&ld, (void *)&k0, (void *)&w, (void *)&G,
                     &ipiv, &info, &ps, &base, &flags};
-    hipError_t e = hipLaunchCooperativeKernel((const void *)k_leaf<W, F16>, dim3(G), dim3(kLeafNT),
-                                              args, 0, s);
+    hipError_t e = hipLaunchCooperativeKernel((const void *)k_leaf<W, F16, RT>, dim3(G),
+                                              dim3(kLeafNT), args, 0, s);
     if (e == hipSuccess) *host_base = base + (uint32_t)w;
     return e;
+}
+
+// One row per thread unless the panel fits one workgroup at two (then no
+// exchange is needed) or needs more workgroups than may run at once.
+template <typename W, bool F16>
+hipError_t leaf_go(W *a, int64_t n, int64_t ld, int64_t k0, int w, int32_t *ipiv, int64_t *info,
+                   PanelSync *ps, uint32_t *host_base, uint32_t *flags, hipStream_t s) {
+    if constexpr (leaf_rt_max<W>() == 2) {
+        const int64_t m = n - k0;
+        if (m <= 2 * kLeafNT || m > (int64_t)leaf_gmax() * kLeafNT)
+            return leaf_run<W, F16, 2>(a, n, ld, k0, w, ipiv, info, ps, host_base, flags, s);
+    }
+    return leaf_run<W, F16, 1>(a, n, ld, k0, w, ipiv, info, ps, host_base, flags, s);
 }
 
 }  // namespace
 
 int leaf_max_rows(int mode) {
-    const int gmax = num_cus() < kLeafMaxG ? num_cus() : kLeafMaxG;
-    return gmax * (mode == LU_F64 ? leaf_rows<double>() : leaf_rows<float>());
+    return leaf_gmax() * kLeafNT * (mode == LU_F64 ? leaf_rt_max<double>() : leaf_rt_max<float>());
 }
 
 hipError_t launch_leaf(int mode, void *a, int64_t n, int64_t ld, int64_t k0, int w, int32_t *ipiv,
