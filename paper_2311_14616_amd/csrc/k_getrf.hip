@@ -548,6 +548,94 @@ __global__ __launch_bounds__(256) void k_trsm_col(W *__restrict__ a, int64_t ld,
         if (t < w) a[(k + t) * ld + c] = x[t];
 }
 
+// U12 <- L11^{-1} U12 for a whole panel in one launch, for a narrow column
+// range (the look-ahead panel): rows [k, k+w) (w <= kU12MaxW), columns
+// [c0, c1).  A workgroup owns kU12CW columns and keeps their w rows in LDS
+// for the whole solve.  Blocks of 32 rows, in increasing order: (a) the
+// diagonal block by substitution in registers, one wave per two columns
+// (lane = row; the final entry of row t is broadcast by readlane; F16:
+// rounded to binary16 when final, before it updates later rows); (b) every
+// row below, by one thread, subtracting the block's 32 products in
+// increasing order.  Each entry thus receives its updates in increasing k,
+// as in the column-by-column substitution, with one launch instead of a
+// triangular solve and an update per 32 rows.
+constexpr int kU12MaxW = 512;
+constexpr int kU12CW = 8;
+
+template <typename W> __device__ __forceinline__ W bcast_lane(W x, int l);
+template <> __device__ __forceinline__ float bcast_lane(float x, int l) {
+    return __int_as_float(__builtin_amdgcn_readlane(__float_as_int(x), l));
+}
+template <> __device__ __forceinline__ double bcast_lane(double x, int l) {
+    const uint64_t b = (uint64_t)__double_as_longlong(x);
+    const uint32_t lo = (uint32_t)__builtin_amdgcn_readlane((int)(uint32_t)b, l);
+    const uint32_t hi = (uint32_t)__builtin_amdgcn_readlane((int)(uint32_t)(b >> 32), l);
+    return __longlong_as_double((long long)(((uint64_t)hi << 32) | lo));
+}
+
+template <typename W, bool F16>
+__global__ __launch_bounds__(256) void k_u12(W *__restrict__ a, int64_t ld, int64_t k, int w,
+                                             int64_t c0, int64_t c1) {
+    __shared__ __align__(16) W X[kU12MaxW][kU12CW];
+    const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
+    const int64_t cb = c0 + (int64_t)blockIdx.x * kU12CW;
+    const int ncol = (int)((c1 - cb) < kU12CW ? (c1 - cb) : kU12CW);
+    for (int e = tid; e < w * kU12CW; e += 256) {
+        const int r = e / kU12CW, c = e - r * kU12CW;
+        X[r][c] = c < ncol ? a[(k + r) * ld + cb + c] : (W)0;
+    }
+    __syncthreads();
+    for (int r0 = 0; r0 < w; r0 += 32) {
+        const int hb = (w - r0) < 32 ? (w - r0) : 32;
+        {
+            // (a) rows r0 + s of column cc
+            const int s = lane & 31, cc = 2 * wv + (lane >> 5);
+            W x = s < hb ? X[r0 + s][cc] : (W)0;
+            W lr[32];
+            const W *lp = a + (k + r0 + s) * ld + k + r0;
+#pragma unroll
+            for (int t = 0; t < 32; ++t) lr[t] = (s < hb && t < s) ? lp[t] : (W)0;
+#pragma unroll
+            for (int t = 0; t < 32; ++t) {
+                if (t < hb) {
+                    if (F16 && s == t) x = (W)round_f16((float)x);
+                    const W xa = bcast_lane(x, t), xb = bcast_lane(x, 32 + t);
+                    const W xt = (lane >> 5) ? xb : xa;
+                    if (s > t) {
+                        const W prod = lr[t] * xt;
+                        x = x - prod;
+                    }
+                }
+            }
+            if (s < hb) X[r0 + s][cc] = x;
+        }
+        __syncthreads();
+        // (b) rows below the block (the block is full whenever rows follow it)
+        for (int r = r0 + 32 + tid; r < w; r += 256) {
+            W acc[kU12CW];
+#pragma unroll
+            for (int c = 0; c < kU12CW; ++c) acc[c] = X[r][c];
+            const W *lp = a + (k + r) * ld + k + r0;
+#pragma unroll 8
+            for (int t = 0; t < 32; ++t) {
+                const W l = lp[t];
+#pragma unroll
+                for (int c = 0; c < kU12CW; ++c) {
+                    const W prod = l * X[r0 + t][c];
+                    acc[c] = acc[c] - prod;
+                }
+            }
+#pragma unroll
+            for (int c = 0; c < kU12CW; ++c) X[r][c] = acc[c];
+        }
+        __syncthreads();
+    }
+    for (int e = tid; e < w * kU12CW; e += 256) {
+        const int r = e / kU12CW, c = e - r * kU12CW;
+        if (c < ncol) a[(k + r) * ld + cb + c] = X[r][c];
+    }
+}
+
 int g_num_cus = 0;
 
 int num_cus() {
@@ -675,6 +763,19 @@ hipError_t launch_trsm(int mode, void *a, int64_t ld, int64_t k, int w, int64_t 
     if (mode == LU_F64) k_trsm_col<double, false><<<nb, 256, 0, s>>>((double *)a, ld, k, w, c0, c1);
     else if (mode == LU_F32) k_trsm_col<float, false><<<nb, 256, 0, s>>>((float *)a, ld, k, w, c0, c1);
     else k_trsm_col<float, true><<<nb, 256, 0, s>>>((float *)a, ld, k, w, c0, c1);
+    return hipGetLastError();
+}
+
+int u12_max_rows() { return kU12MaxW; }
+
+hipError_t launch_u12(int mode, void *a, int64_t ld, int64_t k, int w, int64_t c0, int64_t c1,
+                      hipStream_t s) {
+    if (w <= 0 || w > kU12MaxW) return hipErrorInvalidValue;
+    if (c1 <= c0) return hipSuccess;
+    const unsigned nb = (unsigned)((c1 - c0 + kU12CW - 1) / kU12CW);
+    if (mode == LU_F64) k_u12<double, false><<<nb, 256, 0, s>>>((double *)a, ld, k, w, c0, c1);
+    else if (mode == LU_F32) k_u12<float, false><<<nb, 256, 0, s>>>((float *)a, ld, k, w, c0, c1);
+    else k_u12<float, true><<<nb, 256, 0, s>>>((float *)a, ld, k, w, c0, c1);
     return hipGetLastError();
 }
 

@@ -301,7 +301,8 @@ hipError_t apply_step(mpir_fact f, int64_t K, int w, int64_t c0, int64_t c1, hip
         ProfScope ps_(5, 0.0, s);
         e = laswp_chunks(f->mode, f->work, n, f->ld, K, w, f->ipiv, c0, c1, c1, c1, nullptr, true, s);
         if (e != hipSuccess) return e;
-        e = upper_solve(f, K, w, c0, c1, 0, s);
+        e = w <= u12_max_rows() ? launch_u12(f->mode, f->work, f->ld, K, w, c0, c1, s)
+                                : upper_solve(f, K, w, c0, c1, 0, s);
         if (e != hipSuccess) return e;
     }
     if (K + w < n) {

@@ -161,6 +161,11 @@ hipError_t launch_laswp(int mode, void *a, int64_t n, int64_t ld, int64_t k0, in
 // a3: U12 <- L11^{-1} U12 for rows [k, k+w) (w <= 32), columns [c0, c1).
 hipError_t launch_trsm(int mode, void *a, int64_t ld, int64_t k, int w, int64_t c0,
                        int64_t c1, hipStream_t s);
+// a3 for a narrow column range: U12 <- L11^{-1} U12 for rows [k, k+w),
+// w <= u12_max_rows(), columns [c0, c1), in one launch.
+int u12_max_rows();
+hipError_t launch_u12(int mode, void *a, int64_t ld, int64_t k, int w, int64_t c0, int64_t c1,
+                      hipStream_t s);
 // a4: C[r0:r0+m, c0:c0+nc] -= A[r0:, k:k+kk] * A[k:k+kk, c0:] on one
 // row-major matrix (ld).  cap > 0: at most cap workgroups per compute unit
 // (the rest of each unit stays free for work on another stream).  role: 0 =
