@@ -237,7 +237,7 @@ def main():
     ap.add_argument("--alpha", type=float, default=1.0)
     ap.add_argument("--tf", choices=["f32", "f16"], default="f32")
     ap.add_argument("--fp64-runs", type=int, default=1)
-    ap.add_argument("--cpu-sample", type=int, default=9216)
+    ap.add_argument("--cpu-sample", type=int, default=10240)
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--no-fp64", action="store_true")
     ap.add_argument("--no-batched", action="store_true")
