@@ -556,11 +556,13 @@ __global__ __launch_bounds__(256) void k_trsm_col(W *__restrict__ a, int64_t ld,
 // (lane = row; the final entry of row t is broadcast by readlane; F16:
 // rounded to binary16 when final, before it updates later rows); (b) every
 // row below, by one thread, subtracting the block's 32 products in
-// increasing order.  Each entry thus receives its updates in increasing k,
+// increasing order.  The L entries each phase needs are loaded while the
+// other phase runs.  Each entry thus receives its updates in increasing k,
 // as in the column-by-column substitution, with one launch instead of a
 // triangular solve and an update per 32 rows.
 constexpr int kU12MaxW = 512;
-constexpr int kU12CW = 8;
+constexpr int kU12CW = 8;          // columns per workgroup (two per solving wave)
+constexpr int kU12NT = 512;        // threads: one per row below a block
 
 template <typename W> __device__ __forceinline__ W bcast_lane(W x, int l);
 template <> __device__ __forceinline__ float bcast_lane(float x, int l) {
@@ -574,27 +576,42 @@ template <> __device__ __forceinline__ double bcast_lane(double x, int l) {
 }
 
 template <typename W, bool F16>
-__global__ __launch_bounds__(256) void k_u12(W *__restrict__ a, int64_t ld, int64_t k, int w,
-                                             int64_t c0, int64_t c1) {
+__global__ __launch_bounds__(kU12NT) void k_u12(W *__restrict__ a, int64_t ld, int64_t k, int w,
+                                                int64_t c0, int64_t c1) {
     __shared__ __align__(16) W X[kU12MaxW][kU12CW];
     const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
     const int64_t cb = c0 + (int64_t)blockIdx.x * kU12CW;
     const int ncol = (int)((c1 - cb) < kU12CW ? (c1 - cb) : kU12CW);
-    for (int e = tid; e < w * kU12CW; e += 256) {
+    for (int e = tid; e < w * kU12CW; e += kU12NT) {
         const int r = e / kU12CW, c = e - r * kU12CW;
         X[r][c] = c < ncol ? a[(k + r) * ld + cb + c] : (W)0;
     }
+    // waves 0-3 solve the diagonal blocks: lane = (column half, row s); the
+    // block's L row of each lane is loaded one block ahead
+    const bool solver = wv < kU12CW / 2;
+    const int s = lane & 31, cc = 2 * wv + (lane >> 5);
+    W lr[32];
+    auto load_lr = [&](int r0) {
+        const int hb = (w - r0) < 32 ? (w - r0) : 32;
+        const W *lp = a + (k + r0 + s) * ld + k + r0;
+#pragma unroll
+        for (int t = 0; t < 32; ++t) lr[t] = (solver && s < hb && t < s) ? lp[t] : (W)0;
+    };
+    load_lr(0);
     __syncthreads();
     for (int r0 = 0; r0 < w; r0 += 32) {
         const int hb = (w - r0) < 32 ? (w - r0) : 32;
-        {
-            // (a) rows r0 + s of column cc
-            const int s = lane & 31, cc = 2 * wv + (lane >> 5);
-            W x = s < hb ? X[r0 + s][cc] : (W)0;
-            W lr[32];
-            const W *lp = a + (k + r0 + s) * ld + k + r0;
+        // (b)'s L row (thread = one row below the block), in flight during (a)
+        const int r = r0 + 32 + tid;
+        W lb[32];
+        if (r < w) {
+            const W *lp = a + (k + r) * ld + k + r0;
 #pragma unroll
-            for (int t = 0; t < 32; ++t) lr[t] = (s < hb && t < s) ? lp[t] : (W)0;
+            for (int t = 0; t < 32; ++t) lb[t] = lp[t];
+        }
+        if (solver) {
+            // (a) rows r0 + s of column cc
+            W x = s < hb ? X[r0 + s][cc] : (W)0;
 #pragma unroll
             for (int t = 0; t < 32; ++t) {
                 if (t < hb) {
@@ -610,18 +627,17 @@ __global__ __launch_bounds__(256) void k_u12(W *__restrict__ a, int64_t ld, int6
             if (s < hb) X[r0 + s][cc] = x;
         }
         __syncthreads();
-        // (b) rows below the block (the block is full whenever rows follow it)
-        for (int r = r0 + 32 + tid; r < w; r += 256) {
+        if (r0 + 32 < w) load_lr(r0 + 32);
+        // (b) the rows below (the block is full whenever rows follow it)
+        if (r < w) {
             W acc[kU12CW];
 #pragma unroll
             for (int c = 0; c < kU12CW; ++c) acc[c] = X[r][c];
-            const W *lp = a + (k + r) * ld + k + r0;
-#pragma unroll 8
+#pragma unroll
             for (int t = 0; t < 32; ++t) {
-                const W l = lp[t];
 #pragma unroll
                 for (int c = 0; c < kU12CW; ++c) {
-                    const W prod = l * X[r0 + t][c];
+                    const W prod = lb[t] * X[r0 + t][c];
                     acc[c] = acc[c] - prod;
                 }
             }
@@ -630,7 +646,7 @@ __global__ __launch_bounds__(256) void k_u12(W *__restrict__ a, int64_t ld, int6
         }
         __syncthreads();
     }
-    for (int e = tid; e < w * kU12CW; e += 256) {
+    for (int e = tid; e < w * kU12CW; e += kU12NT) {
         const int r = e / kU12CW, c = e - r * kU12CW;
         if (c < ncol) a[(k + r) * ld + cb + c] = X[r][c];
     }
@@ -773,9 +789,9 @@ hipError_t launch_u12(int mode, void *a, int64_t ld, int64_t k, int w, int64_t c
     if (w <= 0 || w > kU12MaxW) return hipErrorInvalidValue;
     if (c1 <= c0) return hipSuccess;
     const unsigned nb = (unsigned)((c1 - c0 + kU12CW - 1) / kU12CW);
-    if (mode == LU_F64) k_u12<double, false><<<nb, 256, 0, s>>>((double *)a, ld, k, w, c0, c1);
-    else if (mode == LU_F32) k_u12<float, false><<<nb, 256, 0, s>>>((float *)a, ld, k, w, c0, c1);
-    else k_u12<float, true><<<nb, 256, 0, s>>>((float *)a, ld, k, w, c0, c1);
+    if (mode == LU_F64) k_u12<double, false><<<nb, kU12NT, 0, s>>>((double *)a, ld, k, w, c0, c1);
+    else if (mode == LU_F32) k_u12<float, false><<<nb, kU12NT, 0, s>>>((float *)a, ld, k, w, c0, c1);
+    else k_u12<float, true><<<nb, kU12NT, 0, s>>>((float *)a, ld, k, w, c0, c1);
     return hipGetLastError();
 }
 
