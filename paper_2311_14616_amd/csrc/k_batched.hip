@@ -47,6 +47,37 @@ __device__ __forceinline__ double pow2_ceil(double m) {
     return f == 0.5 ? ldexp(1.0, e - 1) : ldexp(1.0, e);
 }
 
+// Global-memory pointers of the device pass (the host pass sees plain
+// pointers).
+#if defined(__HIP_DEVICE_COMPILE__)
+#define GMEM __attribute__((address_space(1)))
+#else
+#define GMEM
+#endif
+
+// One 32 x 32 block of C in the matrix-core accumulator layout (lane l,
+// entry v: row r0 + 8(v/4) + 4(l/32) + v%4, column bc).  Loads are issued
+// unconditionally (out-of-range entries read an in-range word and are
+// zeroed), so the compiler keeps them in flight across the products.
+__device__ __forceinline__ void load_cblock(const GMEM float *W, int n, int r0, int bc, int lane,
+                                            bool any, float (&c)[16]) {
+#pragma unroll
+    for (int v = 0; v < 16; ++v) {
+        const int row = r0 + 8 * (v >> 2) + 4 * (lane >> 5) + (v & 3);
+        const bool ok = any && row < n && bc < n;
+        const float x = W[(int64_t)(ok ? row : 0) * n + (ok ? bc : 0)];
+        c[v] = ok ? x : 0.0f;
+    }
+}
+__device__ __forceinline__ void store_cblock(GMEM float *W, int n, int r0, int bc, int lane,
+                                             const float (&c)[16], const floatx16 &acc) {
+#pragma unroll
+    for (int v = 0; v < 16; ++v) {
+        const int row = r0 + 8 * (v >> 2) + 4 * (lane >> 5) + (v & 3);
+        if (row < n && bc < n) W[(int64_t)row * n + bc] = c[v] - acc[v];
+    }
+}
+
 // Max of a non-negative double over the workgroup (NaN wins), via bits.
 __device__ __forceinline__ double block_max(double v, uint64_t *red) {
     uint64_t b = (uint64_t)__double_as_longlong(v) & 0x7fffffffffffffffull;
@@ -99,11 +130,14 @@ __global__ __launch_bounds__(NT) void k_batched(const BatchSys *__restrict__ sys
         const BatchSys S = sys[si];
         const int n = (int)S.n;
         const int64_t lda = S.lda;
-        const TWt *A = (const TWt *)S.A;
-        const TWt *b = (const TWt *)S.b;
-        TWt *x = (TWt *)S.x;
-        float *W = S.W;
-        int32_t *perm = S.perm;
+        // every per-system pointer addresses global memory; typed so, the
+        // compiler emits global (not flat) loads and stores, whose waits do
+        // not also wait for LDS traffic
+        const GMEM TWt *A = (const GMEM TWt *)S.A;
+        const GMEM TWt *b = (const GMEM TWt *)S.b;
+        GMEM TWt *x = (GMEM TWt *)S.x;
+        GMEM float *W = (GMEM float *)S.W;
+        GMEM int32_t *perm = (GMEM int32_t *)S.perm;
         // tuned per size class: panel width (16 or 32) and update form
         const int cfg = (int)S.pad;
         const int pb = (cfg & 0xff) == 16 ? 16 : PB;
@@ -325,35 +359,25 @@ __global__ __launch_bounds__(NT) void k_batched(const BatchSys *__restrict__ sys
                         // C of the next block row is loaded while this one
                         // is multiplied and stored
                         float cv[16], cn[16];
-#pragma unroll
-                        for (int v = 0; v < 16; ++v) {
-                            const int row = r0 + 8 * (v >> 2) + 4 * (lane >> 5) + (v & 3);
-                            cv[v] = (row < n && bc < n) ? W[(int64_t)row * n + bc] : 0.0f;
-                        }
+                        load_cblock(W, n, r0, bc, lane, true, cv);
                         for (int bi = 0; bi < nbk; ++bi) {
                             const int rb = r0 + bi * 32, lr = bi * 32 + (lane & 31);
-#pragma unroll
-                            for (int v = 0; v < 16; ++v) {
-                                const int row = rb + 32 + 8 * (v >> 2) + 4 * (lane >> 5) + (v & 3);
-                                cn[v] = (bi + 1 < nbk && row < n && bc < n) ? W[(int64_t)row * n + bc] : 0.0f;
-                            }
+                            load_cblock(W, n, rb + 32, bc, lane, bi + 1 < nbk, cn);
                             floatx16 acc = floatx16{0};
+                            // entries beyond w are zero in both operands
 #pragma unroll
                             for (int s2 = 0; s2 < 2; ++s2) {
-                                if (16 * s2 < w) {
-                                    half8 av;
+                                half8 av;
 #pragma unroll
-                                    for (int q = 0; q < 8; ++q)
-                                        av[q] = (_Float16)(lr < mm ? panel[lr * PP + 16 * s2 + 8 * (lane >> 5) + q] : 0.0f);
-                                    acc = __builtin_amdgcn_mfma_f32_32x32x16_f16(av, bh[s2], acc, 0, 0, 0);
+                                for (int q = 0; q < 8; ++q) {
+                                    const float pv = panel[lr * PP + 16 * s2 + 8 * (lane >> 5) + q];
+                                    av[q] = (_Float16)(lr < mm ? pv : 0.0f);
                                 }
+                                acc = __builtin_amdgcn_mfma_f32_32x32x16_f16(av, bh[s2], acc, 0, 0, 0);
                             }
+                            store_cblock(W, n, rb, bc, lane, cv, acc);
 #pragma unroll
-                            for (int v = 0; v < 16; ++v) {
-                                const int row = rb + 8 * (v >> 2) + 4 * (lane >> 5) + (v & 3);
-                                if (row < n && bc < n) W[(int64_t)row * n + bc] = cv[v] - acc[v];
-                                cv[v] = cn[v];
-                            }
+                            for (int v = 0; v < 16; ++v) cv[v] = cn[v];
                         }
                     } else {
                         float bf[16];
@@ -363,32 +387,20 @@ __global__ __launch_bounds__(NT) void k_batched(const BatchSys *__restrict__ sys
                             bf[s1] = (bc < n && kq < w) ? W[(int64_t)(k + kq) * n + bc] : 0.0f;
                         }
                         float cv[16], cn[16];
-#pragma unroll
-                        for (int v = 0; v < 16; ++v) {
-                            const int row = r0 + 8 * (v >> 2) + 4 * (lane >> 5) + (v & 3);
-                            cv[v] = (row < n && bc < n) ? W[(int64_t)row * n + bc] : 0.0f;
-                        }
+                        load_cblock(W, n, r0, bc, lane, true, cv);
                         for (int bi = 0; bi < nbk; ++bi) {
                             const int rb = r0 + bi * 32, lr = bi * 32 + (lane & 31);
-#pragma unroll
-                            for (int v = 0; v < 16; ++v) {
-                                const int row = rb + 32 + 8 * (v >> 2) + 4 * (lane >> 5) + (v & 3);
-                                cn[v] = (bi + 1 < nbk && row < n && bc < n) ? W[(int64_t)row * n + bc] : 0.0f;
-                            }
+                            load_cblock(W, n, rb + 32, bc, lane, bi + 1 < nbk, cn);
                             floatx16 acc = floatx16{0};
+                            // entries beyond w are zero in both operands
 #pragma unroll
                             for (int s1 = 0; s1 < 16; ++s1) {
-                                if (2 * s1 < w) {
-                                    const float av = lr < mm ? panel[lr * PP + 2 * s1 + (lane >> 5)] : 0.0f;
-                                    acc = __builtin_amdgcn_mfma_f32_32x32x2f32(av, bf[s1], acc, 0, 0, 0);
-                                }
+                                const float pv = panel[lr * PP + 2 * s1 + (lane >> 5)];
+                                acc = __builtin_amdgcn_mfma_f32_32x32x2f32(lr < mm ? pv : 0.0f, bf[s1], acc, 0, 0, 0);
                             }
+                            store_cblock(W, n, rb, bc, lane, cv, acc);
 #pragma unroll
-                            for (int v = 0; v < 16; ++v) {
-                                const int row = rb + 8 * (v >> 2) + 4 * (lane >> 5) + (v & 3);
-                                if (row < n && bc < n) W[(int64_t)row * n + bc] = cv[v] - acc[v];
-                                cv[v] = cn[v];
-                            }
+                            for (int v = 0; v < 16; ++v) cv[v] = cn[v];
                         }
                     }
                 }
@@ -431,7 +443,7 @@ __global__ __launch_bounds__(NT) void k_batched(const BatchSys *__restrict__ sys
                         const int row = rb + 8 * (v >> 2) + 4 * (lane >> 5) + (v & 3);
                         const int col = cb + (lane & 31);
                         if (row < n && col < n) {
-                            float *pc = W + (int64_t)row * n + col;
+                            GMEM float *pc = W + (int64_t)row * n + col;
                             *pc = *pc - acc[v];
                         }
                     }
@@ -598,7 +610,7 @@ __global__ __launch_bounds__(NT) void k_batched(const BatchSys *__restrict__ sys
                 double rm = 0.0, xm = 0.0;
                 for (int i = tid; i < n; i += NT) {
                     double acc = 0.0;
-                    const TWt *col = A + i;
+                    const GMEM TWt *col = A + i;
                     // 16 loads in flight per thread, then the sums in order
                     int j = 0;
                     for (; j + 16 <= n; j += 16) {
