@@ -411,42 +411,46 @@ __global__ __launch_bounds__(NT) void k_batched(const BatchSys *__restrict__ sys
                 for (int blk = wv; blk < nbk * nbk; blk += NW) {
                     const int bi = blk / nbk, bj = blk - bi * nbk;
                     const int rb = r0 + bi * 32, cb = r0 + bj * 32;
-                    floatx16 acc = floatx16{0};
                     const int ar = rb + (lane & 31), bc = cb + (lane & 31);
+                    // operands and C first (unconditional loads: out-of-range
+                    // entries read an in-range word and are zeroed), then
+                    // the products
+                    float cv[16];
+                    floatx16 acc = floatx16{0};
                     if (F16) {
+                        half8 av[2], bvv[2];
 #pragma unroll
-                        for (int s1 = 0; s1 < PB; s1 += 16) {
-                            if (s1 < w) {
-                                half8 av, bvv;
+                        for (int s2 = 0; s2 < 2; ++s2)
 #pragma unroll
-                                for (int q = 0; q < 8; ++q) {
-                                    const int kq = s1 + 8 * (lane >> 5) + q;
-                                    av[q] = (_Float16)((ar < n && kq < w) ? W[(int64_t)ar * n + k + kq] : 0.0f);
-                                    bvv[q] = (_Float16)((bc < n && kq < w) ? W[(int64_t)(k + kq) * n + bc] : 0.0f);
-                                }
-                                acc = __builtin_amdgcn_mfma_f32_32x32x16_f16(av, bvv, acc, 0, 0, 0);
+                            for (int q = 0; q < 8; ++q) {
+                                const int kq = 16 * s2 + 8 * (lane >> 5) + q;
+                                const bool oka = ar < n && kq < w, okb = bc < n && kq < w;
+                                const float xa = W[(int64_t)(oka ? ar : 0) * n + k + (oka ? kq : 0)];
+                                const float xb = W[(int64_t)(k + (okb ? kq : 0)) * n + (okb ? bc : 0)];
+                                av[s2][q] = (_Float16)(oka ? xa : 0.0f);
+                                bvv[s2][q] = (_Float16)(okb ? xb : 0.0f);
                             }
-                        }
+                        load_cblock(W, n, rb, bc, lane, true, cv);
+#pragma unroll
+                        for (int s2 = 0; s2 < 2; ++s2)
+                            acc = __builtin_amdgcn_mfma_f32_32x32x16_f16(av[s2], bvv[s2], acc, 0, 0, 0);
                     } else {
+                        float av[16], bvv[16];
 #pragma unroll
-                        for (int s1 = 0; s1 < PB; s1 += 2) {
-                            if (s1 < w) {
-                                const int kq = s1 + (lane >> 5);
-                                const float av = (ar < n && kq < w) ? W[(int64_t)ar * n + k + kq] : 0.0f;
-                                const float bvv = (bc < n && kq < w) ? W[(int64_t)(k + kq) * n + bc] : 0.0f;
-                                acc = __builtin_amdgcn_mfma_f32_32x32x2f32(av, bvv, acc, 0, 0, 0);
-                            }
+                        for (int s1 = 0; s1 < 16; ++s1) {
+                            const int kq = 2 * s1 + (lane >> 5);
+                            const bool oka = ar < n && kq < w, okb = bc < n && kq < w;
+                            const float xa = W[(int64_t)(oka ? ar : 0) * n + k + (oka ? kq : 0)];
+                            const float xb = W[(int64_t)(k + (okb ? kq : 0)) * n + (okb ? bc : 0)];
+                            av[s1] = oka ? xa : 0.0f;
+                            bvv[s1] = okb ? xb : 0.0f;
                         }
-                    }
+                        load_cblock(W, n, rb, bc, lane, true, cv);
 #pragma unroll
-                    for (int v = 0; v < 16; ++v) {
-                        const int row = rb + 8 * (v >> 2) + 4 * (lane >> 5) + (v & 3);
-                        const int col = cb + (lane & 31);
-                        if (row < n && col < n) {
-                            GMEM float *pc = W + (int64_t)row * n + col;
-                            *pc = *pc - acc[v];
-                        }
+                        for (int s1 = 0; s1 < 16; ++s1)
+                            acc = __builtin_amdgcn_mfma_f32_32x32x2f32(av[s1], bvv[s1], acc, 0, 0, 0);
                     }
+                    store_cblock(W, n, rb, bc, lane, cv, acc);
                 }
             }
         }
