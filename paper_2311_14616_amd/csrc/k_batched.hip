@@ -78,6 +78,26 @@ __device__ __forceinline__ void store_cblock(GMEM float *W, int n, int r0, int b
     }
 }
 
+// dst(e) = src(e) for e = tid, tid + NT, ... < N, with U loads in flight per
+// thread (all U issued before the first is stored; src(e) must accept any
+// e < N, and is called with e0 in place of an out-of-range e).
+template <int U, typename LD, typename ST>
+__device__ __forceinline__ void staged_copy(int N, LD src, ST dst) {
+    for (int e0 = threadIdx.x; e0 < N; e0 += U * NT) {
+        decltype(src(0)) v[U];
+#pragma unroll
+        for (int u = 0; u < U; ++u) {
+            const int e = e0 + u * NT;
+            v[u] = src(e < N ? e : e0);
+        }
+#pragma unroll
+        for (int u = 0; u < U; ++u) {
+            const int e = e0 + u * NT;
+            if (e < N) dst(e, v[u]);
+        }
+    }
+}
+
 // Max of a non-negative double over the workgroup (NaN wins), via bits.
 __device__ __forceinline__ double block_max(double v, uint64_t *red) {
     uint64_t b = (uint64_t)__double_as_longlong(v) & 0x7fffffffffffffffull;
@@ -154,15 +174,27 @@ __global__ __launch_bounds__(NT) void k_batched(const BatchSys *__restrict__ sys
         for (int i0 = 0; i0 < n; i0 += TR) {
             double racc = 0.0;
             for (int j0 = 0; j0 < n; j0 += TC) {
-                for (int e = tid; e < TR * TC; e += NT) {
-                    const int r = e % TR, c = e / TR;
-                    const int i = i0 + r, j = j0 + c;
-                    tile[c * TP + r] = (i < n && j < n) ? (double)A[i + (int64_t)j * lda] : 0.0;
-                }
+                staged_copy<16>(TR * TC,
+                    [&](int e) {
+                        const int i = i0 + e % TR, j = j0 + e / TR;
+                        const bool ok = i < n && j < n;
+                        return A[(ok ? i : 0) + (int64_t)(ok ? j : 0) * lda];
+                    },
+                    [&](int e, TWt v) {
+                        const int r = e % TR, c = e / TR;
+                        tile[c * TP + r] = (i0 + r < n && j0 + c < n) ? (double)v : 0.0;
+                    });
                 __syncthreads();
                 if (tid < TR && i0 + tid < n) {
-                    const int cmax = (n - j0) < TC ? (n - j0) : TC;
-                    for (int c = 0; c < cmax; ++c) racc = racc + fabs(tile[c * TP + tid]);
+                    // columns beyond n hold zeros: adding them changes nothing
+#pragma unroll
+                    for (int c0 = 0; c0 < TC; c0 += 16) {
+                        double t[16];
+#pragma unroll
+                        for (int u = 0; u < 16; ++u) t[u] = tile[(c0 + u) * TP + tid];
+#pragma unroll
+                        for (int u = 0; u < 16; ++u) racc = racc + fabs(t[u]);
+                    }
                 }
                 int fl = 0;
                 for (int e = tid; e < TR * TC; e += NT) {
@@ -204,10 +236,9 @@ __global__ __launch_bounds__(NT) void k_batched(const BatchSys *__restrict__ sys
             const int w = (n - k) < pb ? (n - k) : pb;
             const int m = n - k;
             __syncthreads();
-            for (int e = tid; e < m * w; e += NT) {
-                const int r = e / w, c = e - r * w;
-                panel[r * PP + c] = W[(int64_t)(k + r) * n + k + c];
-            }
+            staged_copy<8>(m * w,
+                [&](int e) { const int r = e / w, c = e - r * w; return W[(int64_t)(k + r) * n + k + c]; },
+                [&](int e, float v) { const int r = e / w, c = e - r * w; panel[r * PP + c] = v; });
             __syncthreads();
             for (int j = 0; j < w; ++j) {
                 // first maximum of |a_rj|, r >= j: key = |v| bits above the
@@ -292,11 +323,13 @@ __global__ __launch_bounds__(NT) void k_batched(const BatchSys *__restrict__ sys
                 for (int q = tid; q < np; q += NT) pst[q] = perm[k + psrc[q]];
                 for (int c0 = 0; c0 < n; c0 += CH) {
                     __syncthreads();
-                    for (int e = tid; e < np * CH; e += NT) {
-                        const int q = e / CH, c = c0 + (e - q * CH);
-                        if (c < n && (c < k || c >= k + w))
-                            stage[e] = W[(int64_t)(k + psrc[q]) * n + c];
-                    }
+                    staged_copy<8>(np * CH,
+                        [&](int e) {
+                            const int q = e / CH, c = c0 + (e - q * CH);
+                            const bool ok = c < n && (c < k || c >= k + w);
+                            return W[(int64_t)(k + psrc[q]) * n + (ok ? c : 0)];
+                        },
+                        [&](int e, float v) { stage[e] = v; });
                     __syncthreads();
                     for (int e = tid; e < np * CH; e += NT) {
                         const int q = e / CH, c = c0 + (e - q * CH);
@@ -320,7 +353,14 @@ __global__ __launch_bounds__(NT) void k_batched(const BatchSys *__restrict__ sys
                 const int c = c0 + tid;
                 float *xs = panel + tid;                    // xs[t * NT]
                 if (c < n) {
-                    for (int t = 0; t < w; ++t) xs[t * NT] = W[(int64_t)(k + t) * n + c];
+                    {
+                        float xv[PB];
+#pragma unroll
+                        for (int t = 0; t < PB; ++t) xv[t] = W[(int64_t)(k + (t < w ? t : 0)) * n + c];
+#pragma unroll
+                        for (int t = 0; t < PB; ++t)
+                            if (t < w) xs[t * NT] = xv[t];
+                    }
                     for (int t = 0; t < w; ++t) {
                         float xt = xs[t * NT];
                         if (F16) { xt = round_f16(xt); xs[t * NT] = xt; }
@@ -340,10 +380,12 @@ __global__ __launch_bounds__(NT) void k_batched(const BatchSys *__restrict__ sys
                 // registers and sweeps the block rows.
                 const int r0 = k + w, mm = n - r0;
                 const int nbk = (mm + 31) / 32;
-                for (int e = tid; e < mm * PB; e += NT) {
-                    const int r = e / PB, c = e - r * PB;
-                    panel[r * PP + c] = c < w ? W[(int64_t)(r0 + r) * n + k + c] : 0.0f;
-                }
+                staged_copy<8>(mm * PB,
+                    [&](int e) {
+                        const int r = e / PB, c = e - r * PB;
+                        return W[(int64_t)(r0 + r) * n + k + (c < w ? c : 0)];
+                    },
+                    [&](int e, float v) { panel[(e / PB) * PP + e % PB] = e % PB < w ? v : 0.0f; });
                 __syncthreads();
                 for (int bj = wv; bj < nbk; bj += NW) {
                     const int cb = r0 + bj * 32, bc = cb + (lane & 31);
