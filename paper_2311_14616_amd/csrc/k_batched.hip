@@ -240,17 +240,19 @@ __global__ __launch_bounds__(NT) void k_batched(const BatchSys *__restrict__ sys
                 [&](int e) { const int r = e / w, c = e - r * w; return W[(int64_t)(k + r) * n + k + c]; },
                 [&](int e, float v) { const int r = e / w, c = e - r * w; panel[r * PP + c] = v; });
             __syncthreads();
+            // first maximum of |a_rj|, r >= j: key = |v| bits above the
+            // complemented row, maximised by DPP in each wave, then over the
+            // waves by every thread.  Each thread forms its candidates for
+            // column j+1 while it updates its rows for column j.
+            auto cand = [&](float v, int r) {
+                return ((uint64_t)__float_as_uint(fabsf(v)) << 32) | (uint64_t)(0xffffffffu - (uint32_t)r);
+            };
+            uint64_t key = 0;
+            for (int r = tid; r < m; r += NT) {
+                const uint64_t kk = cand(panel[r * PP], r);
+                key = kk > key ? kk : key;
+            }
             for (int j = 0; j < w; ++j) {
-                // first maximum of |a_rj|, r >= j: key = |v| bits above the
-                // complemented row, maximised by DPP in each wave, then over
-                // the waves by every thread
-                uint64_t key = 0;
-                for (int r = tid; r < m; r += NT)
-                    if (r >= j) {
-                        const uint64_t kk = ((uint64_t)__float_as_uint(fabsf(panel[r * PP + j])) << 32) |
-                                            (uint64_t)(0xffffffffu - (uint32_t)r);
-                        key = kk > key ? kk : key;
-                    }
                 key = wave_max_u64(key);
                 if (lane == 0) redk[wv] = key;
                 __syncthreads();
@@ -269,10 +271,10 @@ __global__ __launch_bounds__(NT) void k_batched(const BatchSys *__restrict__ sys
                 }
                 __syncthreads();
                 const float pj = panel[j * PP + j];
-                if (pj == 0.0f) {
-                    if (tid == 0 && s_info == 0) s_info = k + j + 1;
-                } else {
-                    for (int r = j + 1 + tid; r < m; r += NT) {
+                if (pj == 0.0f && tid == 0 && s_info == 0) s_info = k + j + 1;
+                key = 0;
+                for (int r = j + 1 + tid; r < m; r += NT) {
+                    if (pj != 0.0f) {
                         float l = panel[r * PP + j] / pj;
                         if (F16) l = round_f16(l);
                         panel[r * PP + j] = l;
@@ -281,9 +283,15 @@ __global__ __launch_bounds__(NT) void k_batched(const BatchSys *__restrict__ sys
                             panel[r * PP + c] = panel[r * PP + c] - prod;
                         }
                     }
+                    if (j + 1 < w) {
+                        const uint64_t kk = cand(panel[r * PP + j + 1], r);
+                        key = kk > key ? kk : key;
+                    }
                 }
-                __syncthreads();
+                // redk and the pivot row are rewritten only after the next
+                // barrier, which every thread reaches after its reads here
             }
+            __syncthreads();
             for (int e = tid; e < m * w; e += NT) {
                 const int r = e / w, c = e - r * w;
                 W[(int64_t)(k + r) * n + k + c] = panel[r * PP + c];
