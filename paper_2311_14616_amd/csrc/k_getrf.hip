@@ -309,41 +309,28 @@ __global__ __launch_bounds__(kLeafNT) void k_leaf(W *__restrict__ a, int64_t n, 
                     put_word(Xc::head(ps, par, 1, g), (uint32_t)(vb >> 32), epoch);
                     put_word(Xc::head(ps, par, 2, g), (uint32_t)(best.valid() ? bi : 0x7fffffff), epoch);
                 }
-                // ---- every slot (lane g <-> workgroup g), one round trip ----
-                uint32_t rw[32];
-#pragma unroll
-                for (int q = 0; q < 32; ++q) rw[q] = 0;
+                // ---- every header (lane g <-> workgroup g) and the old row
+                // j, polled with one round trip per poll; then the winner's
+                // row only (word wb0 + q from lane q) ----
                 uint32_t dw = 0;
                 const int gl = lane < G ? lane : 0;
-                bool okh = lane >= G, okr = lane >= G, okd = own_j || lane >= 32;
-                uint64_t h0 = 0, h1 = 0, h2 = 0;
+                bool okh = lane >= G, okd = own_j || lane >= 32;
+                uint64_t h0 = 0, h1 = 0, h2 = 0, d = 0;
                 uint64_t spins = 0;
                 for (;;) {
                     if (!okh) {
                         h0 = get_word(Xc::head(ps, par, 0, gl));
                         h1 = get_word(Xc::head(ps, par, 1, gl));
                         h2 = get_word(Xc::head(ps, par, 2, gl));
-                        okh = word_ok(h0, epoch) && word_ok(h1, epoch) && word_ok(h2, epoch);
                     }
-                    if (!okr) {
-                        bool ok = true;
-#pragma unroll
-                        for (int q = 0; q < 32; ++q) {
-                            const uint64_t x = get_word(Xc::row(ps, par, wb0 + q, gl));
-                            ok = ok && word_ok(x, epoch);
-                            rw[q] = (uint32_t)x;
-                        }
-                        okr = ok;
-                    }
-                    if (!okd) {
-                        const uint64_t x = get_word(Xc::diag(ps, par, wb0 + lane));
-                        okd = word_ok(x, epoch);
-                        dw = (uint32_t)x;
-                    }
-                    if (__all(okh && okr && okd)) break;
+                    if (!okd) d = get_word(Xc::diag(ps, par, wb0 + (lane & 31)));
+                    okh = okh || (word_ok(h0, epoch) && word_ok(h1, epoch) && word_ok(h2, epoch));
+                    okd = okd || word_ok(d, epoch);
+                    if (__all(okh && okd)) break;
                     if (++spins > kSpinLimit) { if (lane == 0) s_bad = 1; break; }
                     __builtin_amdgcn_s_sleep(1);
                 }
+                dw = (uint32_t)d;
                 Cd gbest = Cd::none();
                 if (lane < G && okh) {
                     const int hr = (int)(uint32_t)h2;
@@ -352,18 +339,24 @@ __global__ __launch_bounds__(kLeafNT) void k_leaf(W *__restrict__ a, int64_t n, 
                 }
                 const Cd wbst = wave_max(gbest);
                 const int p = wbst.row();
-                // the lane holding the winning candidate writes its words of
-                // the pivot row
-                if (lane < G && gbest.valid() && gbest.row() == p) {
-                    uint32_t *pw = prow;
-                    uint32_t *uw = pupd;
-#pragma unroll
-                    for (int q = 0; q < 32; ++q) {
-                        const int c = (wb0 + q) / K;
-                        uint32_t x = rw[q];
-                        if (F16 && c < cur) x = __float_as_uint(round_f16(__uint_as_float(x)));
-                        pw[wb0 + q] = x;
-                        uw[wb0 + q] = c < cur ? x : 0u;
+                const uint64_t wmask = __ballot(lane < G && gbest.valid() && gbest.row() == p);
+                if (wmask != 0ull) {
+                    const int gw = __builtin_amdgcn_readfirstlane(__ffsll((unsigned long long)wmask) - 1);
+                    uint64_t x = 0;
+                    bool okx = lane >= 32;
+                    for (;;) {
+                        if (!okx) x = get_word(Xc::row(ps, par, wb0 + (lane & 31), gw));
+                        okx = okx || word_ok(x, epoch);
+                        if (__all(okx)) break;
+                        if (++spins > kSpinLimit) { if (lane == 0) s_bad = 1; break; }
+                        __builtin_amdgcn_s_sleep(1);
+                    }
+                    if (lane < 32) {
+                        const int c = (wb0 + lane) / K;
+                        uint32_t xw = (uint32_t)x;
+                        if (F16 && c < cur) xw = __float_as_uint(round_f16(__uint_as_float(xw)));
+                        prow[wb0 + lane] = xw;
+                        pupd[wb0 + lane] = c < cur ? xw : 0u;
                     }
                 }
                 if (!own_j && lane < 32) orow[wb0 + lane] = dw;
