@@ -197,8 +197,13 @@ __device__ __forceinline__ Cd wave_max(Cd c) {
 // rank-1 update.  F16: the pivot row is rounded to binary16 when it becomes
 // the pivot row, each multiplier to binary16 when formed (products of
 // binary16 numbers are exact in binary32).
+// Binary32 leaves with one row per thread fit in 128 registers per lane,
+// which leaves room on a compute unit for four workgroups of the capped
+// trailing update beside the leaf's.
+template <typename W, int RT> constexpr int leaf_min_waves() { return sizeof(W) == 4 && RT == 1 ? 4 : 2; }
+
 template <typename W, bool F16, int RT>
-__global__ __launch_bounds__(kLeafNT) void k_leaf(W *__restrict__ a, int64_t n, int64_t ld,
+__global__ __launch_bounds__(kLeafNT, (leaf_min_waves<W, RT>())) void k_leaf(W *__restrict__ a, int64_t n, int64_t ld,
                                                   int64_t k0, int w, int G,
                                                   int32_t *__restrict__ ipiv, int64_t *info,
                                                   PanelSync *ps, uint32_t base, uint32_t *flags) {

@@ -337,9 +337,9 @@ int trailing_cap(int mode) {
         env = e ? std::atoi(e) : -1;
     }
     if (env >= 0) return env;
-    // measured at N = 32768: the binary32 update keeps most of its rate at
-    // 4 workgroups per unit, the binary16 / binary64 ones leave more room
-    return mode == LU_F32 ? 4 : 2;
+    // measured at N = 32768 (factorization time against the cap, with the
+    // binary32 / binary16 leaves held to 128 registers per lane)
+    return mode == LU_F32 ? 6 : mode == LU_F16 ? 3 : 2;
 }
 
 mpir_status getrf(mpir_fact f) {
