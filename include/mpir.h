@@ -127,6 +127,22 @@ mpir_status mpir_solve(mpir_fact f, const void *db, void *dx);
 mpir_status mpir_ir_solve(mpir_fact f, const void *db, void *dx,
                           const mpir_term *t, mpir_report *rep);
 
+/* GMRES-IR (sections "Krylov-IR" and "GMRES-IR"; the package's mpglu): the
+ * refinement of mpir_ir_solve, each correction equation A d = r solved by
+ * GMRES left-preconditioned with the factors, P = U^{-1} L^{-1} Pi applied
+ * in binary64 arithmetic on the TF factors (the on-the-fly solve).  GMRES
+ * starts from d = 0, runs at most `basissize` iterations (1..64, no restart;
+ * the package's default is 10), orthogonalises by classical Gram-Schmidt
+ * applied twice and stops once its estimated preconditioned residual is at
+ * most gmres_tol * ||P r||_2 (gmres_tol <= 0: 1e-12).  Requires TW = TR =
+ * F64 (MPIR_ERR_ARG otherwise).  khist (host, may be NULL): at least
+ * t->litmax entries, the GMRES iterations of each correction; rep as for
+ * mpir_ir_solve.  Krylov workspace ((basissize + 5) n binary64 numbers) is
+ * allocated in the handle on first use and kept until mpir_destroy. */
+mpir_status mpir_gmres_ir_solve(mpir_fact f, const void *db, void *dx, const mpir_term *t,
+                                int32_t basissize, double gmres_tol, mpir_report *rep,
+                                int32_t *khist);
+
 /* Batched IR for `batch` independent systems of uneven sizes
  * 1 <= n[k] <= 1024 (host array).  dA[k], db[k], dx[k]: host arrays of
  * device pointers (A column-major, lda[k] >= n[k]); same precisions for

@@ -114,6 +114,12 @@ struct mpir_fact_s {
     double t_factor_ms = 0.0;
     hipStream_t stream2 = nullptr;  // look-ahead: trailing updates
     hipEvent_t evA[2] = {nullptr, nullptr}, evB[2] = {nullptr, nullptr};
+    // GMRES-IR workspace (first use): basis (km + 1) x n, work vectors,
+    // coefficients, and the state the matrix-vector products report into
+    int km = 0;
+    double *kv = nullptr, *kw = nullptr, *kt = nullptr, *kzero = nullptr, *kd = nullptr;
+    double *kc = nullptr;
+    IrState *kst = nullptr;
 };
 
 namespace {
@@ -165,6 +171,8 @@ void free_handle(mpir_fact f) {
         if (f->evB[i]) hipEventDestroy(f->evB[i]);
     }
     if (f->stream2) hipStreamDestroy(f->stream2);
+    for (double *q : {f->kv, f->kw, f->kt, f->kzero, f->kd, f->kc}) hipFree(q);
+    hipFree(f->kst);
     delete f;
 }
 
@@ -208,6 +216,7 @@ mpir_status alloc_handle(mpir_fact f) {
 }
 
 const int kIB = 32;    // leaf width inside the panel
+const int kGmresMaxBasis = 64;   // largest GMRES basis of mpir_gmres_ir_solve
 
 // Panel width (columns per trailing update): a larger width raises the
 // arithmetic intensity of the trailing update (its C tile is read and written
@@ -636,6 +645,174 @@ mpir_status mpir_ir_solve(mpir_fact f, const void *db, void *dx, const mpir_term
         rep->relres = hs.bnorm > 0 ? rnorm / hs.bnorm : rnorm;
         const double den = f->anorm * xnorm + hs.bnorm;
         rep->bwd_err = den > 0 ? rnorm / den : 0.0;
+        rep->t_ir_ms = ms;
+    }
+    return MPIR_OK;
+}
+
+mpir_status mpir_gmres_ir_solve(mpir_fact f, const void *db, void *dx, const mpir_term *t,
+                                int32_t basissize, double gmres_tol, mpir_report *rep,
+                                int32_t *khist) {
+    if (!f || !db || !dx) return MPIR_ERR_ARG;
+    if (f->tw != MPIR_F64 || f->tr != MPIR_F64) return MPIR_ERR_ARG;
+    if (basissize < 1 || basissize > kGmresMaxBasis) return MPIR_ERR_ARG;
+    mpir_term term;
+    if (t) term = *t;
+    else mpir_term_default(&term);
+    if (term.litmax < 1 || term.litmax > MPIR_HIST_MAX - 1 || !(term.Rmax > 0.0)) return MPIR_ERR_ARG;
+    if ((term.onthefly != 0 && term.onthefly != 1) || term.reserved != 0) return MPIR_ERR_ARG;
+    const double eta = gmres_tol > 0.0 ? gmres_tol : 1e-12;
+    if (rep) {
+        std::memset(rep, 0, sizeof(*rep));
+        rep->info = f->info;
+        rep->t_factor_ms = f->t_factor_ms;
+    }
+    if (f->info) return MPIR_ERR_SINGULAR;
+    hipStream_t s = f->stream;
+    const int64_t n = f->n;
+    const int m = basissize;
+    if (f->km < m) {
+        HIPCHK(hipStreamSynchronize(s));
+        for (double **q : {&f->kv, &f->kw, &f->kt, &f->kzero, &f->kd, &f->kc}) {
+            hipFree(*q);
+            *q = nullptr;
+        }
+        hipFree(f->kst);
+        f->kst = nullptr;
+        f->km = 0;
+        if (dalloc(&f->kv, (size_t)(m + 1) * n * 8) != hipSuccess || dalloc(&f->kw, n * 8) != hipSuccess ||
+            dalloc(&f->kt, n * 8) != hipSuccess || dalloc(&f->kzero, n * 8) != hipSuccess ||
+            dalloc(&f->kd, n * 8) != hipSuccess || dalloc(&f->kc, 4 * (kGmresMaxBasis + 1) * 8) != hipSuccess ||
+            dalloc(&f->kst, sizeof(IrState)) != hipSuccess)
+            return MPIR_ERR_ALLOC;
+        HIPCHK(hipMemsetAsync(f->kzero, 0, n * 8, s));
+        HIPCHK(hipMemsetAsync(f->kst, 0, sizeof(IrState), s));
+        f->km = m;
+    }
+    double *V = f->kv, *w = f->kw, *c1 = f->kc, *c2 = f->kc + (kGmresMaxBasis + 1),
+           *nrm = f->kc + 2 * (kGmresMaxBasis + 1), *yv = f->kc + 3 * (kGmresMaxBasis + 1);
+    IrState h{};
+    h.it = -1;
+    h.anorm = f->anorm;
+    h.wilk = 0;
+    h.residterm = term.residterm ? 1 : 0;
+    h.litmax = term.litmax;
+    const double uw = std::ldexp(1.0, -52);
+    h.tol_r = term.tol_rel > 0 ? term.tol_rel : term.Cr * uw;
+    h.tol_e = term.tol_rel > 0 ? term.tol_rel : term.Ce * uw;
+    h.rmax = term.Rmax;
+    hipEvent_t e0, e1;
+    HIPCHK(hipEventCreate(&e0));
+    HIPCHK(hipEventCreate(&e1));
+    HIPCHK(hipMemcpyAsync(f->st, &h, sizeof(h), hipMemcpyHostToDevice, s));
+    HIPCHK(hipMemsetAsync(f->flags_d, 0, 4, s));
+    HIPCHK(hipEventRecord(e0, s));
+    HIPCHK(launch_ir_init(n, f->tw, f->tr, db, dx, f->r, f->st, s));
+    HIPCHK(launch_terminate(f->st, s));
+    const void *LU = factors_ptr(f);
+    const int64_t lld = f->tf == MPIR_F16 ? n : f->ld;
+    std::vector<double> H((size_t)(m + 1) * m), g(m + 1), cs(m), sn(m), y(m), hh(2 * (m + 1) + 1);
+    auto Hk = [&](int i, int k) -> double & { return H[(size_t)i * m + k]; };
+    for (int it = 0; it < term.litmax; ++it) {
+        int32_t done = 0;
+        HIPCHK(hipMemcpyAsync(&done, &f->st->done, 4, hipMemcpyDeviceToHost, s));
+        HIPCHK(hipStreamSynchronize(s));
+        if (done) break;
+        // right side P (r / sigma): the permutation, the exact power-of-two
+        // scaling, then the binary64 substitutions on the TF factors
+        HIPCHK(launch_scale_permute(n, MPIR_F64, MPIR_F64, f->r, f->perm, w, f->st, f->ts, 1, s));
+        HIPCHK(launch_trsv(f->tf, MPIR_F64, LU, n, lld, w, f->yw, f->ts, f->flags_d, f->st, 1, s));
+        HIPCHK(launch_dots(n, w, n, 1, w, nrm, s));
+        double b2 = 0.0;
+        HIPCHK(hipMemcpyAsync(&b2, nrm, 8, hipMemcpyDeviceToHost, s));
+        HIPCHK(hipStreamSynchronize(s));
+        const double beta = std::sqrt(b2);
+        int kend = 0;
+        if (beta > 0.0 && std::isfinite(beta)) {
+            HIPCHK(launch_scale(n, w, beta, V, s));
+            std::fill(g.begin(), g.end(), 0.0);
+            g[0] = beta;
+            kend = m;
+            for (int k = 0; k < m; ++k) {
+                const double *vk = V + (size_t)k * n;
+                // w = P A v_k (the residual kernel with b = 0 gives -A v_k)
+                HIPCHK(launch_residual(n, f->A, f->lda, MPIR_F64, MPIR_F64, f->kzero, vk, f->kt, f->partial,
+                                       f->nchunks, f->kst, 1, s));
+                HIPCHK(launch_gather_neg(n, f->kt, f->perm, w, f->ts, s));
+                HIPCHK(launch_trsv(f->tf, MPIR_F64, LU, n, lld, w, f->yw, f->ts, f->flags_d, f->st, 1, s));
+                // classical Gram-Schmidt, twice, then ||w||_2
+                HIPCHK(launch_dots(n, V, n, k + 1, w, c1, s));
+                HIPCHK(launch_sub_combo(n, V, n, k + 1, c1, w, s));
+                HIPCHK(launch_dots(n, V, n, k + 1, w, c2, s));
+                HIPCHK(launch_sub_combo(n, V, n, k + 1, c2, w, s));
+                HIPCHK(launch_dots(n, w, n, 1, w, nrm, s));
+                HIPCHK(hipMemcpyAsync(hh.data(), c1, (size_t)(k + 1) * 8, hipMemcpyDeviceToHost, s));
+                HIPCHK(hipMemcpyAsync(hh.data() + (m + 1), c2, (size_t)(k + 1) * 8, hipMemcpyDeviceToHost, s));
+                HIPCHK(hipMemcpyAsync(hh.data() + 2 * (m + 1), nrm, 8, hipMemcpyDeviceToHost, s));
+                HIPCHK(hipStreamSynchronize(s));
+                for (int i = 0; i <= k; ++i) Hk(i, k) = hh[i] + hh[(m + 1) + i];
+                const double hk1 = std::sqrt(hh[2 * (m + 1)]);
+                Hk(k + 1, k) = hk1;
+                if (hk1 > 0.0) HIPCHK(launch_scale(n, w, hk1, V + (size_t)(k + 1) * n, s));
+                // earlier rotations, then the one that zeroes H(k+1, k)
+                for (int i = 0; i < k; ++i) {
+                    const double tt = cs[i] * Hk(i, k) + sn[i] * Hk(i + 1, k);
+                    Hk(i + 1, k) = -sn[i] * Hk(i, k) + cs[i] * Hk(i + 1, k);
+                    Hk(i, k) = tt;
+                }
+                const double a = Hk(k, k), bb = Hk(k + 1, k);
+                if (bb == 0.0) { cs[k] = 1.0; sn[k] = 0.0; }
+                else { const double r = std::hypot(a, bb); cs[k] = a / r; sn[k] = bb / r; }
+                Hk(k, k) = cs[k] * a + sn[k] * bb;
+                Hk(k + 1, k) = 0.0;
+                g[k + 1] = -sn[k] * g[k];
+                g[k] = cs[k] * g[k];
+                if (std::fabs(g[k + 1]) <= eta * beta || hk1 == 0.0 || !std::isfinite(hk1)) {
+                    kend = k + 1;
+                    break;
+                }
+            }
+            for (int i = kend - 1; i >= 0; --i) {
+                double acc = 0.0;
+                for (int j = i + 1; j < kend; ++j) acc += Hk(i, j) * y[j];
+                y[i] = (g[i] - acc) / Hk(i, i);
+            }
+            HIPCHK(hipMemcpyAsync(yv, y.data(), (size_t)kend * 8, hipMemcpyHostToDevice, s));
+            HIPCHK(launch_combo(n, V, n, kend, yv, f->kd, s));
+        } else {
+            HIPCHK(hipMemsetAsync(f->kd, 0, n * 8, s));
+        }
+        if (khist && it < term.litmax) khist[it] = kend;
+        // x <- x + sigma d, the binary64 residual, the termination rules
+        HIPCHK(launch_update(n, f->tw, MPIR_F64, f->kd, dx, f->st, 0, s));
+        HIPCHK(launch_residual(n, f->A, f->lda, f->tw, f->tr, db, dx, f->r, f->partial, f->nchunks,
+                               f->st, 0, s));
+        HIPCHK(launch_terminate(f->st, s));
+    }
+    HIPCHK(hipEventRecord(e1, s));
+    IrState hs;
+    uint32_t flags = 0;
+    HIPCHK(hipMemcpyAsync(&hs, f->st, sizeof(hs), hipMemcpyDeviceToHost, s));
+    HIPCHK(hipMemcpyAsync(&flags, f->flags_d, 4, hipMemcpyDeviceToHost, s));
+    HIPCHK(hipStreamSynchronize(s));
+    float ms = 0.f;
+    hipEventElapsedTime(&ms, e0, e1);
+    hipEventDestroy(e0);
+    hipEventDestroy(e1);
+    if (flags & DF_TIMEOUT) return MPIR_ERR_DEVICE;
+    if (hs.it == 0 && hs.stop == MPIR_STOP_NONFINITE) return MPIR_ERR_NONFINITE;
+    if (rep) {
+        rep->n_iter = hs.it;
+        rep->stop = hs.stop;
+        rep->n_hist = hs.it + 1;
+        for (int k = 0; k <= hs.it && k < MPIR_HIST_MAX; ++k) rep->rhist[k] = hs.rhist[k];
+        for (int k = 0; k < hs.it && k < MPIR_HIST_MAX; ++k) rep->dhist[k] = hs.dhist[k];
+        rep->bnorm_inf = hs.bnorm;
+        rep->anorm_inf = f->anorm;
+        rep->xnorm_inf = hs.xnorm;
+        rep->relres = hs.bnorm > 0 ? hs.rnorm / hs.bnorm : hs.rnorm;
+        const double den = f->anorm * hs.xnorm + hs.bnorm;
+        rep->bwd_err = den > 0 ? hs.rnorm / den : 0.0;
         rep->t_ir_ms = ms;
     }
     return MPIR_OK;

@@ -219,6 +219,17 @@ hipError_t launch_trsv(int tf, int ysol, const void *LU, int64_t n, int64_t ld, 
                        TrsvSync *ts, uint32_t *flags, const IrState *st, int force,
                        hipStream_t s);
 
+// GMRES-IR vector kernels (binary64; V holds basis vectors in rows of ldv).
+hipError_t launch_gather_neg(int64_t n, const double *t, const int32_t *perm, double *w,
+                             TrsvSync *ts, hipStream_t s);
+hipError_t launch_dots(int64_t n, const double *V, int64_t ldv, int nv, const double *w,
+                       double *out, hipStream_t s);
+hipError_t launch_sub_combo(int64_t n, const double *V, int64_t ldv, int nv, const double *c,
+                            double *w, hipStream_t s);
+hipError_t launch_scale(int64_t n, const double *w, double divisor, double *out, hipStream_t s);
+hipError_t launch_combo(int64_t n, const double *V, int64_t ldv, int nv, const double *y, double *d,
+                        hipStream_t s);
+
 }  // namespace mpir
 
 // Batch creation with an explicit tuning table (NULL: the process-wide one).

@@ -28,6 +28,7 @@ PROF_GEMM, PROF_PANEL, PROF_TRSV, PROF_GEMV, PROF_DOWNCAST = 0, 1, 2, 3, 4
 
 EXPORTS = [
     "mpir_term_default", "mpir_factor", "mpir_refactor", "mpir_solve", "mpir_ir_solve",
+    "mpir_gmres_ir_solve",
     "mpir_ir_solve_batched", "mpir_destroy", "mpir_status_str", "mpir_downcast",
     "mpir_get_factors", "mpir_residual", "mpir_prof_enable", "mpir_prof_reset", "mpir_prof_get",
     "mpir_batch_create", "mpir_batch_run", "mpir_batch_destroy",
@@ -102,6 +103,8 @@ def lib():
         L.mpir_solve.argtypes = [vp, vp, vp]
         L.mpir_ir_solve.restype = C.c_int
         L.mpir_ir_solve.argtypes = [vp, vp, vp, P(Term), P(Report)]
+        L.mpir_gmres_ir_solve.restype = C.c_int
+        L.mpir_gmres_ir_solve.argtypes = [vp, vp, vp, P(Term), i32, C.c_double, P(Report), P(i32)]
         L.mpir_ir_solve_batched.restype = C.c_int
         L.mpir_ir_solve_batched.argtypes = [i32, P(i64), P(vp), P(i64), P(vp), P(vp), C.c_int,
                                             C.c_int, C.c_int, P(Term), P(Report), vp]
@@ -234,6 +237,20 @@ class Factorization:
                "mpir_ir_solve")
         return x, rep
 
+    def gmres_ir_solve(self, b, x=None, term_parms: Term | None = None, basissize: int = 10,
+                       gmres_tol: float = 0.0):
+        """GMRES-IR (the package's mpglu); returns (x, report, khist)."""
+        torch = _torch()
+        x = torch.empty_like(b) if x is None else x
+        rep = Report()
+        tp = C.byref(term_parms) if term_parms is not None else None
+        litmax = term_parms.litmax if term_parms is not None else 10
+        kh = (C.c_int32 * max(litmax, 1))()
+        _check(lib().mpir_gmres_ir_solve(self._h, _dev_ptr(b), _dev_ptr(x), tp, int(basissize),
+                                         float(gmres_tol), C.byref(rep), kh),
+               "mpir_gmres_ir_solve")
+        return x, rep, [int(kh[i]) for i in range(rep.n_iter)]
+
     def factors(self):
         """(LU row-major tensor in TF, ipiv numpy int32)."""
         torch = _torch()
@@ -263,6 +280,16 @@ def ir_solve(At, b, tf: int, tr: int | None = None, term_parms: Term | None = No
     f = Factorization(At, tf, tr, stream)
     try:
         return f.ir_solve(b, term_parms=term_parms)
+    finally:
+        f.destroy()
+
+
+def gmres_ir_solve(At, b, tf: int, term_parms: Term | None = None, basissize: int = 10,
+                   gmres_tol: float = 0.0, stream=None):
+    """GMRES-IR with TW = TR = F64; returns (x, report, khist)."""
+    f = Factorization(At, tf, F64, stream)
+    try:
+        return f.gmres_ir_solve(b, term_parms=term_parms, basissize=basissize, gmres_tol=gmres_tol)
     finally:
         f.destroy()
 
