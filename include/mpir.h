@@ -134,7 +134,7 @@ mpir_status mpir_ir_solve(mpir_fact f, const void *db, void *dx,
  * starts from d = 0, runs at most `basissize` iterations (1..64, no restart;
  * the package's default is 10), orthogonalises by classical Gram-Schmidt
  * applied twice and stops once its estimated preconditioned residual is at
- * most gmres_tol * ||P r||_2 (gmres_tol <= 0: 1e-12).  Requires TW = TR =
+ * most gmres_tol * ||P r||_2 (gmres_tol <= 0: 1e-13).  Requires TW = TR =
  * F64 (MPIR_ERR_ARG otherwise).  khist (host, may be NULL): at least
  * t->litmax entries, the GMRES iterations of each correction; rep as for
  * mpir_ir_solve.  Krylov workspace ((basissize + 5) n binary64 numbers) is

@@ -661,7 +661,7 @@ mpir_status mpir_gmres_ir_solve(mpir_fact f, const void *db, void *dx, const mpi
     else mpir_term_default(&term);
     if (term.litmax < 1 || term.litmax > MPIR_HIST_MAX - 1 || !(term.Rmax > 0.0)) return MPIR_ERR_ARG;
     if ((term.onthefly != 0 && term.onthefly != 1) || term.reserved != 0) return MPIR_ERR_ARG;
-    const double eta = gmres_tol > 0.0 ? gmres_tol : 1e-12;
+    const double eta = gmres_tol > 0.0 ? gmres_tol : 1e-13;
     if (rep) {
         std::memset(rep, 0, sizeof(*rep));
         rep->info = f->info;

@@ -55,7 +55,8 @@ def _operator(name, n, alpha):
 
 CASES = [("gmat", 512, 1.0, "f32", 10), ("gmat", 512, 799.0, "f16", 10),
          ("gmat", 1100, 10.0, "f16", 20), ("rand", 650, 0.0, "f16", 10),
-         ("gmat", 300, 1.0, "f64", 10), ("gmat", 777, 100.0, "f16", 3)]
+         ("gmat", 300, 1.0, "f64", 10), ("gmat", 777, 100.0, "f16", 3),
+         ("gmat", 4096, 1.0, "f32", 10)]
 
 
 @pytest.mark.parametrize("name,n,alpha,tf,m", CASES)

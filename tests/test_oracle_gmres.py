@@ -4,10 +4,15 @@ inner GMRES against properties that fix it independently of its own code
 built explicitly, the exact preconditioner), and the outer loop against the
 paper's claim that GMRES-IR recovers the residual where half-precision IR
 does not."""
+import json
+import os
+
 import numpy as np
 import pytest
 
 from paper_2311_14616_amd import inputs as I
+
+GOLD = json.load(open(os.path.join(os.path.dirname(__file__), "golden", "paper_examples.json")))
 
 
 @pytest.fixture(scope="module")
@@ -102,3 +107,26 @@ def test_recovers_where_half_ir_fails(G, orc):
     assert ir.stop_name != "converged"
     assert g.stop == 0 and g.relres <= 1e-14
     assert max(g.khist) >= 3
+
+
+def test_printed_statistics_session(G, orc):
+    """The printed mpglu session (tests/golden E_gmres_stats): N = 4096,
+    A = I - Gmat, FP32 factors, TW = TR = F64.  The same initial residual to
+    the printed six digits (it fixes the grid), two corrections as printed,
+    the residual after the first within a factor 2 of the printed 7.48e-14 and
+    the final one at the binary64 floor near the printed 1.44e-15 (both are
+    rounding-level quantities, so only their size is fixed), each correction
+    within one Krylov step of the printed count.  The printed session stops
+    at 1.44e-15, above eps(F64) ||b||, so the 1e-14 rule of the workloads
+    stands in for the package's stopping test here."""
+    g = GOLD["E_gmres_stats"]
+    n = g["n"]
+    at = I.gmat_operator(n, g["alpha"])
+    b = I.rhs_ones(at)
+    r = G.gmres_ir_solve(at, b, orc.F32, tol_rel=1e-14, litmax=10)
+    assert r.stop == 0
+    assert abs(r.rhist[0] - g["rhist"][0]) <= 5e-7
+    assert r.n_iter == len(g["khist"]) == 2
+    assert 0.5 <= r.rhist[1] / g["rhist"][1] <= 2.0
+    assert 0.5 <= r.rhist[2] / g["rhist"][2] <= 2.0
+    assert all(abs(k - kp) <= 1 for k, kp in zip(r.khist, g["khist"]))
