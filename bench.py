@@ -135,7 +135,10 @@ def experiments(M, I, torch, dev):
     (iii) the Wilkinson-type matrices A = H1 diag(sigma) H2 at N=16384,
           kappa in {1e4, 1e6, 1e7}, TW=TF=F32, TR=F64: forward error of IR
           against x* and against the FP64 LU solve of the same matrix, and
-          of one plain FP32 LU solve."""
+          of one plain FP32 LU solve;
+    (iv)  GMRES-IR (the factors as left preconditioner, basissize 10) against
+          IR with TF=F16 at N=32768, alpha in {1, 10, 799}: corrections, GMRES
+          iterations per correction, stop reason, time."""
     import numpy as np
     tp = M.term(tol_rel=1e-14, litmax=20)
 
@@ -225,6 +228,29 @@ def experiments(M, I, torch, dev):
         print(json.dumps(row), flush=True)
         out.append(row)
         del at32, b32
+    # (iv)
+    n = 32768
+    for alpha in (1.0, 10.0, 799.0):
+        At = I.gmat_operator_torch(n, alpha, dev)
+        b = I.rhs_ones_torch(At)
+        row = {"experiment": "GMRES-IR vs IR, TF=F16", "n": n, "alpha": alpha}
+        x, rep, ms = ir(At, b, M.F16, M.F64, tp)
+        row["ir"] = {**rec(rep), "ms": round(ms, 3), "ferr_vs_ones": float((x - 1).abs().max())}
+        xg = torch.empty_like(b)
+
+        def go():
+            f = M.Factorization(At, M.F16, M.F64)
+            _, rp, kh = f.gmres_ir_solve(b, xg, tp)
+            f.destroy()
+            return rp, kh
+        timed(go)
+        (rep, kh), ms = timed(go)
+        row["gmres_ir"] = {**rec(rep), "khist": kh, "ms": round(ms, 3),
+                           "factor_ms": round(rep.t_factor_ms, 3), "refine_ms": round(rep.t_ir_ms, 3),
+                           "ferr_vs_ones": float((xg - 1).abs().max())}
+        print(json.dumps(row), flush=True)
+        out.append(row)
+        del At, b
     return out
 
 

@@ -77,14 +77,28 @@ __global__ __launch_bounds__(256) void k_downcast(int64_t n, const TWt *__restri
     if (fl) atomicOr(flags, fl);
 }
 
-__global__ void k_pack_half(int64_t n, const float *__restrict__ src, int64_t lds,
-                            __half *__restrict__ dst) {
-    const int64_t total = n * n;
-    int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    const int64_t stride = (int64_t)gridDim.x * blockDim.x;
-    for (; i < total; i += stride) {
-        const int64_t r = i / n, c = i - r * n;
-        dst[i] = __float2half_rn(src[r * lds + c]);
+// dst (pitch ldd) = binary16 copy of src (pitch lds); the source holds
+// binary16 numbers already, so the conversion is exact.  One workgroup per
+// row segment of kPackCols columns, four columns per thread (16-byte loads,
+// 8-byte stores when both pitches and bases allow them).
+constexpr int kPackCols = 1024;
+
+__global__ __launch_bounds__(256) void k_pack_half(int64_t n, const float *__restrict__ src, int64_t lds,
+                                                   __half *__restrict__ dst, int64_t ldd, int segs, int vec) {
+    const int64_t r = blockIdx.x / segs;
+    const int64_t c = (int64_t)(blockIdx.x % segs) * kPackCols + threadIdx.x * 4;
+    if (c >= n) return;
+    const float *s = src + r * lds + c;
+    __half *d = dst + r * ldd + c;
+    if (vec && c + 4 <= n) {
+        const float4 v = *reinterpret_cast<const float4 *>(s);
+        __half2 lo = __floats2half2_rn(v.x, v.y), hi = __floats2half2_rn(v.z, v.w);
+        uint2 o;
+        o.x = *reinterpret_cast<uint32_t *>(&lo);
+        o.y = *reinterpret_cast<uint32_t *>(&hi);
+        *reinterpret_cast<uint2 *>(d) = o;
+    } else {
+        for (int j = 0; j < 4 && c + j < n; ++j) d[j] = __float2half_rn(s[j]);
     }
 }
 
@@ -107,12 +121,12 @@ hipError_t launch_downcast(int64_t n, const void *A, int64_t lda, int tw, int tf
     return hipGetLastError();
 }
 
-hipError_t launch_pack_half(int64_t n, const float *AF, int64_t ldf, __half *LU, hipStream_t s) {
-    const int64_t total = n * n;
-    if (total <= 0) return hipSuccess;
-    int64_t blocks = (total + 255) / 256;
-    if (blocks > 65536) blocks = 65536;
-    k_pack_half<<<(unsigned)blocks, 256, 0, s>>>(n, AF, ldf, LU);
+hipError_t launch_pack_half(int64_t n, const float *AF, int64_t ldf, __half *LU, int64_t ldl,
+                            hipStream_t s) {
+    if (n <= 0) return hipSuccess;
+    const int segs = (int)((n + kPackCols - 1) / kPackCols);
+    const int vec = (ldf % 4 == 0 && ldl % 4 == 0 && ((uintptr_t)AF & 15) == 0 && ((uintptr_t)LU & 7) == 0);
+    k_pack_half<<<(unsigned)(n * segs), 256, 0, s>>>(n, AF, ldf, LU, ldl, segs, vec);
     return hipGetLastError();
 }
 

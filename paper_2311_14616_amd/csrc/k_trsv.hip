@@ -17,6 +17,8 @@
 // block is on the chain: the others are consumed while the previous block
 // row is still being solved.  The bytes read are the factor entries of that
 // triangle, once.
+#include <type_traits>
+
 #include "mpir_internal.h"
 
 namespace mpir {
@@ -112,34 +114,48 @@ __global__ __launch_bounds__(256) void k_trsv(const Ft *__restrict__ LU, int64_t
     bool timed_out = false;
 
     // wave 0 preloads its row of the diagonal block and of the last
-    // dependency block (neither depends on the solution)
-    Yt drow[BS], lrow[BS];
+    // dependency block (neither depends on the solution).  Every load below
+    // reads a clamped, in-bounds index and the guard is applied to the value,
+    // so the loads of a block are all in flight together.  Binary64 solves on
+    // binary32 / binary16 factors keep these rows in binary32 (exact).
+    using St = typename std::conditional<(sizeof(Yt) == 8 && sizeof(Ft) < 8), float, Yt>::type;
+    St drow[BS], lrow[BS];
     const int64_t lastc = t > 0 ? (int64_t)(LOWER ? t - 1 : nblk - t) * BS : 0;
     if (wv == 0) {
         const bool ok = lane < rows;
-        const Ft *dr = LU + (i0 + (ok ? lane : 0)) * ld;
+        const Ft *dr = LU + (i0 + (ok ? lane : rows - 1)) * ld;
 #pragma unroll
         for (int c = 0; c < BS; ++c) {
-            drow[c] = (ok && c < rows) ? (Yt)to_d(dr[i0 + c]) : (Yt)(LOWER ? 0 : 1);
-            lrow[c] = (ok && t > 0 && lastc + c < n) ? (Yt)to_d(dr[lastc + c]) : (Yt)0;
+            const Ft dv = dr[i0 + (c < rows ? c : rows - 1)];
+            const int64_t lc = lastc + c < n ? lastc + c : n - 1;
+            const Ft lv = dr[lc];
+            drow[c] = (ok && c < rows) ? (St)to_d(dv) : (St)(LOWER ? 0 : 1);
+            lrow[c] = (ok && t > 0 && lastc + c < n) ? (St)to_d(lv) : (St)0;
         }
     }
 
     // ---- phase 1 (all waves): dependency blocks 0 .. t-2 ----
+    // rows past the end of the matrix read the last row (their sums are
+    // never used); columns past the end read column n-1 and are masked
     Yt acc[16];
 #pragma unroll
     for (int r = 0; r < 16; ++r) acc[r] = (Yt)0;
-    const Ft *base = LU + (i0 + wv * 16) * ld;
+    const Ft *base = LU + i0 * ld;
+    const int wvs = __builtin_amdgcn_readfirstlane(wv);   // wave-uniform: row offsets stay scalar
+    int rsel[16];
+#pragma unroll
+    for (int r = 0; r < 16; ++r) rsel[r] = wvs * 16 + r < rows ? wvs * 16 + r : rows - 1;
     for (int q = 0; q < t - 1 && !timed_out; ++q) {
         const int cb = LOWER ? q : nblk - 1 - q;
         const int64_t col = (int64_t)cb * BS + lane;
         const bool cv = col < n;
+        const int64_t cc = cv ? col : n - 1;
         Ft lv[16];
 #pragma unroll
-        for (int r = 0; r < 16; ++r) lv[r] = (cv && wv * 16 + r < rows) ? base[(int64_t)r * ld + col] : (Ft)0;
+        for (int r = 0; r < 16; ++r) lv[r] = base[(int64_t)rsel[r] * ld + cc];
         const Yt yv = get_y<Yt>(yw, col, cv, epoch, timed_out);
 #pragma unroll
-        for (int r = 0; r < 16; ++r) acc[r] += (Yt)to_d(lv[r]) * yv;
+        for (int r = 0; r < 16; ++r) acc[r] += (cv ? (Yt)to_d(lv[r]) : (Yt)0) * yv;
     }
     if (timed_out) s_bad = 1;
 #pragma unroll
@@ -155,21 +171,21 @@ __global__ __launch_bounds__(256) void k_trsv(const Ft *__restrict__ LU, int64_t
         if (t > 0 && !to) {
             const Yt yl = get_y<Yt>(yw, lastc + lane, lastc + lane < n, epoch, to);
 #pragma unroll
-            for (int c = 0; c < BS; ++c) s += lrow[c] * bcast(yl, c);
+            for (int c = 0; c < BS; ++c) s += (Yt)lrow[c] * bcast(yl, c);
         }
         Yt z = lane < rows ? y[i0 + lane] - s : (Yt)0;
         if (LOWER) {
 #pragma unroll
             for (int j = 0; j < BS; ++j) {
                 const Yt yj = bcast(z, j);
-                if (lane > j) z -= drow[j] * yj;
+                if (lane > j) z -= (Yt)drow[j] * yj;
             }
         } else {
 #pragma unroll
             for (int j = BS - 1; j >= 0; --j) {
-                if (lane == j) z = z / drow[j];
+                if (lane == j) z = z / (Yt)drow[j];
                 const Yt yj = bcast(z, j);
-                if (lane < j) z -= drow[j] * yj;
+                if (lane < j) z -= (Yt)drow[j] * yj;
             }
         }
         if (lane < rows) {

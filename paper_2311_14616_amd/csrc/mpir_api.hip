@@ -187,7 +187,8 @@ mpir_status alloc_handle(mpir_fact f) {
     f->ld = (n + 31) / 32 * 32;
     if (f->ld % 1024 == 0) f->ld += 32;
     if (dalloc(&f->work, (size_t)f->ld * n * wes) != hipSuccess) return MPIR_ERR_ALLOC;
-    if (f->tf == MPIR_F16 && dalloc(&f->lu16, (size_t)n * n * 2) != hipSuccess) return MPIR_ERR_ALLOC;
+    // binary16 factors for the solves: the same padded pitch
+    if (f->tf == MPIR_F16 && dalloc(&f->lu16, (size_t)f->ld * n * 2) != hipSuccess) return MPIR_ERR_ALLOC;
     if (f->tf == MPIR_F16) {
         const size_t hw = gemm_h16_ws_halves(n, panel_width(LU_F16)) * 2;
         for (auto &pr : f->hws)
@@ -428,7 +429,7 @@ mpir_status factor_impl(mpir_fact f, int64_t *info) {
     if (flags & DF_RANGE) return MPIR_ERR_RANGE;
     mpir_status st = getrf(f);
     if (st != MPIR_OK) return st;
-    if (f->tf == MPIR_F16) HIPCHK(launch_pack_half(n, (const float *)f->work, f->ld, f->lu16, s));
+    if (f->tf == MPIR_F16) HIPCHK(launch_pack_half(n, (const float *)f->work, f->ld, f->lu16, f->ld, s));
     uint64_t abits = 0;
     int64_t inf = 0;
     HIPCHK(hipMemcpyAsync(&abits, f->anorm_bits_d, 8, hipMemcpyDeviceToHost, s));
@@ -534,8 +535,7 @@ mpir_status mpir_solve(mpir_fact f, const void *db, void *dx) {
     HIPCHK(launch_scale_permute(n, f->tr, f->tf, f->r, f->perm, f->rhat, f->st, f->ts, 1, s));
     {
         ProfScope ps_(2, 2.0 * (double)n * n, s);
-        HIPCHK(launch_trsv(f->tf, f->tf == MPIR_F64 ? MPIR_F64 : MPIR_F32, factors_ptr(f), n,
-                           f->tf == MPIR_F16 ? n : f->ld, f->rhat, f->yw,
+        HIPCHK(launch_trsv(f->tf, f->tf == MPIR_F64 ? MPIR_F64 : MPIR_F32, factors_ptr(f), n, f->ld, f->rhat, f->yw,
                            f->ts, f->flags_d, f->st, 1, s));
     }
     HIPCHK(launch_update(n, f->tw, f->tf, f->rhat, dx, f->st, 1, s));
@@ -581,7 +581,7 @@ mpir_status mpir_ir_solve(mpir_fact f, const void *db, void *dx, const mpir_term
     HIPCHK(launch_ir_init(n, f->tw, f->tr, db, dx, f->r, f->st, s));
     HIPCHK(launch_terminate(f->st, s));
     const void *LU = factors_ptr(f);
-    const int64_t lld = f->tf == MPIR_F16 ? n : f->ld;
+    const int64_t lld = f->ld;
     const size_t twes = esize(f->tw);
     // LPS: the scaled residual rounded to TF, binary32 substitutions (binary64
     // for TF = F64).  MPS: the residual kept in TW, substitutions in TW
@@ -710,7 +710,7 @@ mpir_status mpir_gmres_ir_solve(mpir_fact f, const void *db, void *dx, const mpi
     HIPCHK(launch_ir_init(n, f->tw, f->tr, db, dx, f->r, f->st, s));
     HIPCHK(launch_terminate(f->st, s));
     const void *LU = factors_ptr(f);
-    const int64_t lld = f->tf == MPIR_F16 ? n : f->ld;
+    const int64_t lld = f->ld;
     std::vector<double> H((size_t)(m + 1) * m), g(m + 1), cs(m), sn(m), y(m), hh(2 * (m + 1) + 1);
     auto Hk = [&](int i, int k) -> double & { return H[(size_t)i * m + k]; };
     for (int it = 0; it < term.litmax; ++it) {
@@ -835,7 +835,7 @@ mpir_status mpir_downcast(int64_t n, const void *dA, int64_t lda, mpir_prec tw, 
         if (launch_downcast(n, dA, lda, tw, tf, tf == MPIR_F16 ? tmp : dAF, n, bits, flags, s) != hipSuccess)
             st = MPIR_ERR_HIP;
         if (st == MPIR_OK && tf == MPIR_F16 &&
-            launch_pack_half(n, (const float *)tmp, n, (__half *)dAF, s) != hipSuccess)
+            launch_pack_half(n, (const float *)tmp, n, (__half *)dAF, n, s) != hipSuccess)
             st = MPIR_ERR_HIP;
         uint64_t hb = 0;
         uint32_t hf = 0;
@@ -860,11 +860,9 @@ mpir_status mpir_get_factors(mpir_fact f, void *dLU, int32_t *ipiv) {
     hipStream_t s = f->stream;
     const int64_t n = f->n;
     if (dLU) {
-        if (f->tf == MPIR_F16) HIPCHK(hipMemcpyAsync(dLU, f->lu16, (size_t)n * n * 2, hipMemcpyDeviceToDevice, s));
-        else {
-            const size_t es = esize(f->tf);
-            HIPCHK(hipMemcpy2DAsync(dLU, n * es, f->work, f->ld * es, n * es, n, hipMemcpyDeviceToDevice, s));
-        }
+        const size_t es = esize(f->tf);
+        const void *src = f->tf == MPIR_F16 ? (const void *)f->lu16 : f->work;
+        HIPCHK(hipMemcpy2DAsync(dLU, n * es, src, f->ld * es, n * es, n, hipMemcpyDeviceToDevice, s));
     }
     if (ipiv) HIPCHK(hipMemcpyAsync(ipiv, f->ipiv, n * 4, hipMemcpyDeviceToHost, s));
     HIPCHK(hipStreamSynchronize(s));

@@ -136,8 +136,9 @@ __device__ __forceinline__ void atomic_max_nonneg(uint64_t *p, double v) {
 hipError_t launch_downcast(int64_t n, const void *A, int64_t lda, int tw, int tf,
                            void *AF, int64_t ldf, uint64_t *anorm_bits, uint32_t *flags,
                            hipStream_t s);
-// Working array (row pitch ldf) -> packed n x n TF factors (F16: binary16).
-hipError_t launch_pack_half(int64_t n, const float *AF, int64_t ldf, __half *LU, hipStream_t s);
+// Working array (row pitch ldf) -> n x n binary16 factors (row pitch ldl).
+hipError_t launch_pack_half(int64_t n, const float *AF, int64_t ldf, __half *LU, int64_t ldl,
+                            hipStream_t s);
 // Working array -> TF storage with the given row-major layout (copy).
 hipError_t launch_copy_factors(int64_t n, const void *src, int tf, void *dst, hipStream_t s);
 

@@ -1,12 +1,22 @@
 """GPU parity of GMRES-IR (sections "Krylov-IR" and "GMRES-IR") against the
 oracle in oracle/gmres_ir.py, through the C ABI.
 
-Bars: the same stop reason; outer iteration counts within +-1; the GMRES
-iteration counts of the corrections both runs take within +-1 each (the two
-sides sum their inner products in different orders, so the inner stopping
-test can fall one iteration apart); the residual rule met by both; the
-solutions within the accuracy the refinement reaches (a forward error
-bounded by kappa_inf(A) times the tolerance).
+GMRES-IR reaches the binary64 residual floor after one or two corrections,
+so the outer stop is usually decided by residuals of a few ulps of ||b||,
+which the two sides (different summation orders, factors equal only up to
+binary32 rounding) do not share.  The bars therefore compare what rounding
+does not decide:
+  - the first residual (x = 0) bit for bit;
+  - the first correction's GMRES iteration count within +-1, and every
+    common correction's count within +-1 and within the basis;
+  - the residual after the first correction within a factor 3 of the
+    oracle's when it lies above the floor (a truncated basis);
+  - outer iteration counts within +-1 and both final residuals at the
+    floor (<= 1e-13 ||b||); the same stop reason whenever the oracle's
+    residual history clears the tolerance and the stagnation ratio by a
+    margin (factor 3, ratio <= 0.3);
+  - the solutions within the accuracy the refinement reaches (a forward
+    error bounded by kappa_inf(A) times the tolerance).
 """
 import sys
 
@@ -56,7 +66,20 @@ def _operator(name, n, alpha):
 CASES = [("gmat", 512, 1.0, "f32", 10), ("gmat", 512, 799.0, "f16", 10),
          ("gmat", 1100, 10.0, "f16", 20), ("rand", 650, 0.0, "f16", 10),
          ("gmat", 300, 1.0, "f64", 10), ("gmat", 777, 100.0, "f16", 3),
-         ("gmat", 4096, 1.0, "f32", 10)]
+         ("gmat", 640, 799.0, "f16", 3), ("gmat", 1100, 10.0, "f16", 3),
+         ("rand", 1100, 0.0, "f16", 10), ("gmat", 4096, 1.0, "f32", 10)]
+
+TOL = 1e-14
+
+
+def _stop_has_margin(ref):
+    """True when the oracle's stop does not hang on rounding: every
+    intermediate residual at least 3x above the tolerance, the last at least
+    3x below, and every ratio of successive residuals at most 0.3."""
+    rel = np.asarray(ref.rhist) / ref.rhist[0]
+    ratios = rel[2:] / rel[1:-1]
+    return (ref.stop == 0 and rel[-1] <= TOL / 3 and bool(np.all(rel[1:-1] >= 3 * TOL))
+            and bool(np.all(ratios <= 0.3)))
 
 
 @pytest.mark.parametrize("name,n,alpha,tf,m", CASES)
@@ -64,24 +87,30 @@ def test_gmres_ir_parity(M, G, orc, name, n, alpha, tf, m):
     say(f"gmres-ir {name} n={n} alpha={alpha} tf={tf} basis={m}")
     at = _operator(name, n, alpha)
     b = I.rhs_ones(at)
-    tp = M.term(tol_rel=1e-14, litmax=20)
+    tp = M.term(tol_rel=TOL, litmax=20)
     x, rep, kh = M.gmres_ir_solve(dev(at), dev(b), TF[tf], term_parms=tp, basissize=m)
-    ref = G.gmres_ir_solve(at, b, TF[tf], basissize=m, tol_rel=1e-14, litmax=20)
-    say(f"  gpu n_iter={rep.n_iter} khist={kh} relres={rep.relres:.2e} | "
-        f"oracle n_iter={ref.n_iter} khist={list(ref.khist)} relres={ref.relres:.2e}")
-    assert rep.stop == ref.stop
-    assert abs(rep.n_iter - ref.n_iter) <= 1
-    assert len(kh) == rep.n_iter
+    ref = G.gmres_ir_solve(at, b, TF[tf], basissize=m, tol_rel=TOL, litmax=20)
+    rg = [rep.rhist[k] / rep.rhist[0] for k in range(rep.n_iter + 1)]
+    ro = list(np.asarray(ref.rhist) / ref.rhist[0])
+    say(f"  gpu n_iter={rep.n_iter} stop={rep.stop} khist={kh} rhist={['%.1e' % v for v in rg]} | "
+        f"oracle n_iter={ref.n_iter} stop={ref.stop} khist={[int(k) for k in ref.khist]} "
+        f"rhist={['%.1e' % v for v in ro]}")
+    # x = 0: the first residual is b itself
+    assert rep.rhist[0] == ref.rhist[0]
+    assert len(kh) == rep.n_iter and rep.n_iter >= 1
+    assert abs(kh[0] - ref.khist[0]) <= 1
     for kg, ko in zip(kh, ref.khist):
         assert abs(kg - ko) <= 1 and 1 <= kg <= m
-    if ref.stop == 0:
-        assert rep.relres <= 1e-14 and ref.relres <= 1e-14
-        assert rep.rhist[rep.n_iter] <= 1e-14 * rep.rhist[0]
+    if ro[1] >= 1e-12:
+        assert 1 / 3 <= rg[1] / ro[1] <= 3
+    assert abs(rep.n_iter - ref.n_iter) <= 1
+    assert rg[-1] <= 1e-13 and ro[-1] <= 1e-13
+    assert rep.stop in (0, 1) and ref.stop in (0, 1)
+    if _stop_has_margin(ref):
+        assert rep.stop == ref.stop == 0 and rg[-1] <= TOL
     xg = x.cpu().numpy()
     kappa = np.abs(at).sum(0).max() * np.abs(np.linalg.inv(at.T)).sum(1).max()
-    assert np.abs(xg - ref.x).max() <= 10 * kappa * 1e-14 * np.abs(ref.x).max()
-    # the GPU's first residual is the oracle's: both start from x = 0
-    assert rep.rhist[0] == ref.rhist[0]
+    assert np.abs(xg - ref.x).max() <= 10 * kappa * TOL * np.abs(ref.x).max()
 
 
 def test_gmres_ir_exact_preconditioner_one_step(M):
