@@ -29,6 +29,11 @@
  * infinity at 65520).  Binary32 rounding is the C conversion (double->float),
  * which is IEEE round-to-nearest-even.  Double rounding through binary32 or
  * binary64 before binary16 is innocuous for +,-,*,/ because 24 >= 2*11+2.
+ * Rounding to bfloat16 (the 16-bit format of section "Half Precision": the
+ * exponent range of binary32, an 8-bit significand) is done by orc_fl_b,
+ * written from the same definition (round to nearest, ties to even, gradual
+ * underflow at quantum 2^-133, overflow to infinity at (2 - 2^-8) 2^127);
+ * the same double-rounding argument holds since 24 >= 2*8+2.
  *
  * LU modes (how "factor in precision TF" is read for each TF):
  *   ORC_LU_F64       all arithmetic in binary64.
@@ -40,6 +45,9 @@
  *                    rounded to binary32 (the product of two binary16 values
  *                    is exact in binary32).
  *   ORC_LU_F16STRICT every operation rounded to binary16.
+ *   ORC_LU_BF16MIXED as ORC_LU_F16MIXED with bfloat16 factors (fl_b in
+ *                    place of fl_h; products of two bfloat16 values are
+ *                    exact in binary32 too).
  *
  * Solve modes (precision TS of the triangular solves in the low-precision
  * solve): ORC_TS_F32 (binary32 arithmetic on the factors; the default for
@@ -58,8 +66,9 @@
 #include <omp.h>
 #endif
 
-enum { ORC_F64 = 0, ORC_F32 = 1, ORC_F16 = 2 };
-enum { ORC_LU_F64 = 0, ORC_LU_F32 = 1, ORC_LU_F16MIXED = 2, ORC_LU_F16STRICT = 3 };
+enum { ORC_F64 = 0, ORC_F32 = 1, ORC_F16 = 2, ORC_BF16 = 3 };
+enum { ORC_LU_F64 = 0, ORC_LU_F32 = 1, ORC_LU_F16MIXED = 2, ORC_LU_F16STRICT = 3,
+       ORC_LU_BF16MIXED = 4 };
 enum { ORC_TS_F64 = 0, ORC_TS_F32 = 1, ORC_TS_F16 = 2 };
 enum { ORC_OK = 0, ORC_SINGULAR = 1, ORC_ERR_ARG = -1, ORC_ERR_ALLOC = -2,
        ORC_ERR_NONFINITE = -4, ORC_ERR_RANGE = -5 };
@@ -87,7 +96,25 @@ double orc_fl_h(double x)
     return copysign(r * q, x);
 }
 
+/* Round a binary64 value to the nearest bfloat16 value (ties to even). */
+double orc_fl_b(double x)
+{
+    if (isnan(x)) return x;
+    double ax = fabs(x);
+    if (ax == 0.0) return x;
+    int e;
+    frexp(ax, &e);                 /* ax = f * 2^e, f in [0.5, 1) */
+    int ex = e - 1;                /* floor(log2(ax)) */
+    if (ex < -126) ex = -126;      /* subnormal range: fixed quantum 2^-133 */
+    double q = ldexp(1.0, ex - 7);
+    double m = ax / q;             /* exact: division by a power of two */
+    double r = nearbyint(m) * q;   /* round to nearest, ties to even */
+    if (r >= ldexp(1.0, 128)) return copysign(INFINITY, x);
+    return copysign(r, x);
+}
+
 static inline float fl_h(float x) { return (float)orc_fl_h((double)x); }
+static inline float fl_b(float x) { return (float)orc_fl_b((double)x); }
 static inline double fl_s(double x) { return (double)(float)x; }
 
 void orc_fl_h_array(int64_t n, const double *in, double *out)
@@ -95,11 +122,17 @@ void orc_fl_h_array(int64_t n, const double *in, double *out)
     for (int64_t i = 0; i < n; ++i) out[i] = orc_fl_h(in[i]);
 }
 
+void orc_fl_b_array(int64_t n, const double *in, double *out)
+{
+    for (int64_t i = 0; i < n; ++i) out[i] = orc_fl_b(in[i]);
+}
+
 static double unit_roundoff_eps(int p)
 {
     /* Julia eps(T): the spacing of T at 1.0, used by the paper's termination. */
     if (p == ORC_F64) return ldexp(1.0, -52);
     if (p == ORC_F32) return ldexp(1.0, -23);
+    if (p == ORC_BF16) return ldexp(1.0, -7);
     return ldexp(1.0, -10);
 }
 
@@ -130,6 +163,7 @@ int orc_downcast(int64_t n, const void *A, int64_t lda, int tw, int tf,
             double f = a;
             if (tf == ORC_F32) f = fl_s(a);
             else if (tf == ORC_F16) f = orc_fl_h(a);
+            else if (tf == ORC_BF16) f = orc_fl_b(a);
             if (isfinite(a) && !isfinite(f)) bad_rg = 1;
             af[i * n + j] = f;
             rs = rs + fabs(a);
@@ -197,8 +231,8 @@ static void lu_f64(double *a, int64_t n, int32_t *ipiv, int64_t *info)
     }
 }
 
-/* mode: ORC_LU_F32, ORC_LU_F16MIXED or ORC_LU_F16STRICT; a holds binary32
- * numbers (binary16 values for the two half modes). */
+/* mode: ORC_LU_F32, ORC_LU_F16MIXED, ORC_LU_F16STRICT or ORC_LU_BF16MIXED;
+ * a holds binary32 numbers (binary16 / bfloat16 values for the half modes). */
 static void lu_f32(float *a, int64_t n, int mode, int32_t *ipiv, int64_t *info)
 {
     for (int64_t k = 0; k < n; ++k) {
@@ -210,6 +244,8 @@ static void lu_f32(float *a, int64_t n, int mode, int32_t *ipiv, int64_t *info)
             }
         if (mode == ORC_LU_F16MIXED)       /* row k is now final: store U in binary16 */
             for (int64_t j = k; j < n; ++j) a[k * n + j] = fl_h(a[k * n + j]);
+        if (mode == ORC_LU_BF16MIXED)      /* ... or in bfloat16 */
+            for (int64_t j = k; j < n; ++j) a[k * n + j] = fl_b(a[k * n + j]);
         if (a[k * n + k] == 0.0f) {
             if (*info == 0) *info = k + 1;
             continue;
@@ -220,7 +256,8 @@ static void lu_f32(float *a, int64_t n, int mode, int32_t *ipiv, int64_t *info)
         for (int64_t i = k + 1; i < n; ++i) {
             float *ri = a + i * n;
             float l = ri[k] / akk;
-            if (mode != ORC_LU_F32) l = fl_h(l);
+            if (mode == ORC_LU_BF16MIXED) l = fl_b(l);
+            else if (mode != ORC_LU_F32) l = fl_h(l);
             ri[k] = l;
             if (mode == ORC_LU_F16STRICT) {
                 for (int64_t j = k + 1; j < n; ++j) {
@@ -375,7 +412,7 @@ double orc_pow2_ceil(double m)
 /* ------------------------------------------------------------------------ */
 
 /* Inputs: A column-major n x n in TW (lda), b (TW), precisions tw, tf, tr
- * (ORC_F64/F32/F16), lu_mode, ts, and the termination parameters
+ * (ORC_F64/F32/F16/BF16), lu_mode, ts, and the termination parameters
  * (Cr, Ce, Rmax, litmax, residterm, tol_rel; tol_rel > 0 replaces C*u_w).
  * Outputs: x (TW), n_iter (number of corrections), stop reason, rhist
  * (n_iter+1 entries: ||b||, then ||r|| after each correction), dhist
@@ -440,6 +477,7 @@ int orc_ir_solve(int64_t n, const void *A, int64_t lda, int tw, int tf, int tr,
             double s = y[i] / sigma;
             if (rhat_prec == ORC_F32) s = fl_s(s);
             else if (rhat_prec == ORC_F16) s = orc_fl_h(s);
+            else if (rhat_prec == ORC_BF16) s = orc_fl_b(s);
             y[i] = s;
         }
         orc_trsv_lu(n, af, ts, y);

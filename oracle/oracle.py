@@ -16,8 +16,8 @@ import numpy as np
 HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(HERE, "libmpir_oracle.so")
 
-F64, F32, F16 = 0, 1, 2
-LU_F64, LU_F32, LU_F16MIXED, LU_F16STRICT = 0, 1, 2, 3
+F64, F32, F16, BF16 = 0, 1, 2, 3
+LU_F64, LU_F32, LU_F16MIXED, LU_F16STRICT, LU_BF16MIXED = 0, 1, 2, 3, 4
 TS_F64, TS_F32, TS_F16 = 0, 1, 2
 STOP_NAMES = {0: "converged", 1: "stagnated", 2: "dstagnated", 3: "litmax",
               4: "nonfinite"}
@@ -43,6 +43,9 @@ def lib():
         L.orc_fl_h.restype = d
         L.orc_fl_h.argtypes = [d]
         L.orc_fl_h_array.argtypes = [i64, vp, vp]
+        L.orc_fl_b.restype = d
+        L.orc_fl_b.argtypes = [d]
+        L.orc_fl_b_array.argtypes = [i64, vp, vp]
         L.orc_downcast.restype = C.c_int
         L.orc_downcast.argtypes = [i64, vp, i64, C.c_int, C.c_int, vp, p(d)]
         L.orc_lu.restype = C.c_int
@@ -82,6 +85,14 @@ def fl_h(x):
     a = np.ascontiguousarray(np.asarray(x, dtype=np.float64))
     out = np.empty_like(a)
     lib().orc_fl_h_array(a.size, _ptr(a), _ptr(out))
+    return out
+
+
+def fl_b(x):
+    """Round binary64 values to bfloat16 (returned as binary64)."""
+    a = np.ascontiguousarray(np.asarray(x, dtype=np.float64))
+    out = np.empty_like(a)
+    lib().orc_fl_b_array(a.size, _ptr(a), _ptr(out))
     return out
 
 
@@ -169,7 +180,7 @@ class IRResult:
 
 
 def default_lu_mode(tf: int) -> int:
-    return {F64: LU_F64, F32: LU_F32, F16: LU_F16MIXED}[tf]
+    return {F64: LU_F64, F32: LU_F32, F16: LU_F16MIXED, BF16: LU_BF16MIXED}[tf]
 
 
 def default_ts(tf: int) -> int:

@@ -3,7 +3,7 @@
 1. The exact solution of A x = b (Fractions, Gaussian elimination without
    rounding) bounds the oracle's binary64 solve: forward error <= c*kappa*u.
 2. The emulated low-precision LU of every mode is replayed with Fractions,
-   applying IEEE round-to-nearest-even to binary32/binary16 after each
+   applying IEEE round-to-nearest-even to binary32/binary16/bfloat16 after each
    operation, from the format's definition (precision p, minimum exponent,
    overflow).  This pins the C rounding machinery -- contraction, excess
    precision, the binary16 rounding routine -- independently of it: L, U and
@@ -15,7 +15,8 @@ import math
 import numpy as np
 import pytest
 
-FMT = {"f64": (53, -1022, 1023), "f32": (24, -126, 127), "f16": (11, -14, 15)}
+FMT = {"f64": (53, -1022, 1023), "f32": (24, -126, 127), "f16": (11, -14, 15),
+       "bf16": (8, -126, 127)}
 INF = float("inf")
 
 
@@ -52,22 +53,24 @@ def replay_lu(a, mode):
     a = [row[:] for row in a]
     ipiv = []
     info = 0
-    work = {"f64": "f64", "f32": "f32", "f16mixed": "f32", "f16strict": "f16"}[mode]
+    work = {"f64": "f64", "f32": "f32", "f16mixed": "f32", "f16strict": "f16",
+            "bf16mixed": "f32"}[mode]
+    low = {"f16mixed": "f16", "bf16mixed": "bf16"}.get(mode)
     for k in range(n):
         p = max(range(k, n), key=lambda i: (abs(a[i][k]), -i))
         ipiv.append(p)
         if p != k:
             a[k], a[p] = a[p], a[k]
-        if mode == "f16mixed":
+        if low:
             for j in range(k, n):
-                a[k][j] = rnd(a[k][j], "f16")
+                a[k][j] = rnd(a[k][j], low)
         if a[k][k] == 0:
             info = info or k + 1
             continue
         for i in range(k + 1, n):
             l = rnd(a[i][k] / a[k][k], work)
-            if mode == "f16mixed":
-                l = rnd(l, "f16")
+            if low:
+                l = rnd(l, low)
             a[i][k] = l
             for j in range(k + 1, n):
                 prod = rnd(l * a[k][j], work)
@@ -118,17 +121,19 @@ def _cases():
     return out
 
 
-@pytest.mark.parametrize("mode", ["f64", "f32", "f16mixed", "f16strict"])
+@pytest.mark.parametrize("mode", ["f64", "f32", "f16mixed", "f16strict", "bf16mixed"])
 @pytest.mark.parametrize("case", _cases(), ids=lambda c: f"n{c[0]}s{c[1]}")
 def test_lu_bitwise_vs_rational_replay(orc, mode, case):
     n, _, a = case
-    tf = {"f64": orc.F64, "f32": orc.F32, "f16mixed": orc.F16, "f16strict": orc.F16}[mode]
+    tf = {"f64": orc.F64, "f32": orc.F32, "f16mixed": orc.F16, "f16strict": orc.F16,
+          "bf16mixed": orc.BF16}[mode]
     lu_mode = {"f64": orc.LU_F64, "f32": orc.LU_F32, "f16mixed": orc.LU_F16MIXED,
-               "f16strict": orc.LU_F16STRICT}[mode]
+               "f16strict": orc.LU_F16STRICT, "bf16mixed": orc.LU_BF16MIXED}[mode]
     at = np.ascontiguousarray(a.T)
     af, anorm, st = orc.downcast(at, tf)
     assert st == 0
-    init_fmt = {"f64": "f64", "f32": "f32", "f16mixed": "f16", "f16strict": "f16"}[mode]
+    init_fmt = {"f64": "f64", "f32": "f32", "f16mixed": "f16", "f16strict": "f16",
+                "bf16mixed": "bf16"}[mode]
     ra = [[rnd(Fr(float(a[i, j])), init_fmt) for j in range(n)] for i in range(n)]
     assert all(Fr(float(af[i, j])) == ra[i][j] for i in range(n) for j in range(n))
     lu, ipiv, info, st = orc.lu(af, lu_mode)
