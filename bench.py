@@ -131,7 +131,7 @@ def experiments(M, I, torch, dev):
     (i)   TF=F32 IR at N=8192 against the FP64 LU solve;
     (ii)  TF=F16 IR at N in {8192, 32768}, alpha in {1, 10, 100}: iteration
           counts, stop reason and the level where it stalls, beside the
-          onthefly (mixed-precision) solve and TF=F32;
+          onthefly (mixed-precision) solve, TF=BF16 and TF=F32;
     (iii) the Wilkinson-type matrices A = H1 diag(sigma) H2 at N=16384,
           kappa in {1e4, 1e6, 1e7}, TW=TF=F32, TR=F64: forward error of IR
           against x* and against the FP64 LU solve of the same matrix, and
@@ -150,6 +150,7 @@ def experiments(M, I, torch, dev):
         return r, (time.perf_counter() - t0) * 1e3
 
     tp_mps = M.term(tol_rel=1e-14, litmax=20, onthefly=True)
+    tp30 = M.term(tol_rel=1e-14, litmax=30)
 
     def ir(At, b, tf, tr=M.F64, term=tp):
         x = torch.empty_like(b)
@@ -196,7 +197,8 @@ def experiments(M, I, torch, dev):
             At = I.gmat_operator_torch(n, alpha, dev)
             b = I.rhs_ones_torch(At)
             row = {"experiment": "half-precision factorization", "n": n, "alpha": alpha}
-            for name, tf, tpar in (("f16", M.F16, tp), ("f16_onthefly", M.F16, tp_mps), ("f32", M.F32, tp)):
+            for name, tf, tpar in (("f16", M.F16, tp), ("f16_onthefly", M.F16, tp_mps),
+                                   ("bf16", M.BF16, tp30), ("f32", M.F32, tp)):
                 x, rep, ms = ir(At, b, tf, M.F64, tpar)
                 r = rec(rep)
                 r["ms"] = round(ms, 3)
@@ -369,26 +371,28 @@ def main():
         },
     }
     if args.tf == "f32":
-        # the same solve with the half-precision factorization (binary16 L
-        # and U, binary32 trailing matrix, FP32 MFMA accumulation)
-        log("[bench] TF=FP16 solve of the same system")
+        # the same solve with the 16-bit factorizations (binary16 or bfloat16
+        # L and U, binary32 trailing matrix, 16-bit MFMA with binary32
+        # accumulation)
         xh = torch.empty_like(b)
+        for key, tfh in (("f16_factorization", M.F16), ("bf16_factorization", M.BF16)):
+            log(f"[bench] {key}: solve of the same system")
 
-        def step_h():
-            f = M.Factorization(At, M.F16, M.F64, stream)
-            _, rh = f.ir_solve(b, xh, tp)
-            f.destroy()
-            return rh
-        step_h()
-        torch.cuda.synchronize()
-        t0 = time.perf_counter()
-        rh = step_h()
-        torch.cuda.synchronize()
-        hms = (time.perf_counter() - t0) * 1e3
-        out["f16_factorization"] = {"ms": round(hms, 3), "n_iter": rh.n_iter, "stop": rh.stop_name,
-                                    "bwd_err": rh.bwd_err, "relres": rh.relres,
-                                    "t_factor_ms": rh.t_factor_ms, "t_ir_ms": rh.t_ir_ms}
-        log(f"[bench] TF=FP16: {hms:.2f} ms, n_iter={rh.n_iter}, bwd={rh.bwd_err:.2e}")
+            def step_h():
+                f = M.Factorization(At, tfh, M.F64, stream)
+                _, rh = f.ir_solve(b, xh, M.term(tol_rel=1e-14, litmax=30))
+                f.destroy()
+                return rh
+            step_h()
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            rh = step_h()
+            torch.cuda.synchronize()
+            hms = (time.perf_counter() - t0) * 1e3
+            out[key] = {"ms": round(hms, 3), "n_iter": rh.n_iter, "stop": rh.stop_name,
+                        "bwd_err": rh.bwd_err, "relres": rh.relres,
+                        "t_factor_ms": rh.t_factor_ms, "t_ir_ms": rh.t_ir_ms}
+            log(f"[bench] {key}: {hms:.2f} ms, n_iter={rh.n_iter}, bwd={rh.bwd_err:.2e}")
     if not args.no_fp64:
         log("[bench] FP64 LU comparator")
         xs = torch.empty_like(b)
@@ -409,8 +413,9 @@ def main():
         bn = float(b.abs().max())
         out["fp64_lu_ms"] = round(fp64_ms, 3)
         out["speedup_vs_fp64_lu"] = round(fp64_ms / ms_step, 3)
-        if "f16_factorization" in out:
-            out["f16_factorization"]["speedup_vs_fp64_lu"] = round(fp64_ms / out["f16_factorization"]["ms"], 3)
+        for key in ("f16_factorization", "bf16_factorization"):
+            if key in out:
+                out[key]["speedup_vs_fp64_lu"] = round(fp64_ms / out[key]["ms"], 3)
         out["fp64_lu_relres"] = rn64 / bn
         log(f"[bench] FP64 LU solve {fp64_ms:.2f} ms  relres={rn64 / bn:.2e}")
     if not args.no_batched:

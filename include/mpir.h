@@ -13,9 +13,11 @@
  *  - Matrices and vectors passed as `d*` are DEVICE pointers owned by the
  *    caller.  A is column-major (LAPACK / Julia layout) with leading
  *    dimension lda >= n.  Host pointers are named without the `d` prefix.
- *  - Precisions: TW in {F64, F32}; TF in {F32, F16} below TW, or TF == TW;
- *    TR in {TW, F64} (section "Evaluating the residual in extended
- *    precision").  BF16 is reserved and rejected.
+ *  - Precisions: TW in {F64, F32}; TF in {F32, F16, BF16} below TW, or
+ *    TF == TW; TR in {TW, F64} (section "Evaluating the residual in extended
+ *    precision").  BF16 is the 16-bit format of section "Half Precision"
+ *    (binary32 exponent range, 8-bit significand); the batched entry points
+ *    take TF in {F32, F16} only.
  *  - Every call is ordered on the HIP stream given to mpir_factor (a
  *    hipStream_t passed as void*, NULL = the default stream) and returns
  *    only when its results are in place (it synchronises that stream).
@@ -104,7 +106,7 @@ void mpir_term_default(mpir_term *t);
  *  - F16 factorization: binary16 L and U, binary32 trailing matrix (each U
  *    row rounded to binary16 when it becomes final, each multiplier rounded
  *    to binary16 when formed; MFMA products of binary16 operands accumulate
- *    in binary32).
+ *    in binary32).  BF16: the same with bfloat16 L and U.
  *  - *out receives the handle also on MPIR_ERR_SINGULAR (*info = first zero
  *    pivot, 1-based, LAPACK semantics: the factorization is completed);
  *    on any other error *out is NULL. */

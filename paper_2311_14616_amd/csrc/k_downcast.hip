@@ -2,7 +2,8 @@
 // fused with ||A||_inf and the finiteness / range checks.
 //
 // Layout: A is column-major in TW (lda); A_F is the row-major working array
-// of the factorization (binary32 for TF in {F32, F16}, binary64 for F64).
+// of the factorization (binary32 for TF in {F32, F16, BF16}, binary64 for
+// F64).
 // One workgroup owns a strip of 64 rows and walks the column tiles from left
 // to right, so each row sum of |a_ij| is accumulated in increasing j (the
 // same order as a plain loop, hence bit-identical to it).  Reads are
@@ -61,6 +62,7 @@ __global__ __launch_bounds__(256) void k_downcast(int64_t n, const TWt *__restri
                     Wt w;
                     if (TF == MPIR_F64) w = (Wt)v;
                     else if (TF == MPIR_F32) w = (Wt)(float)v;
+                    else if (TF == MPIR_BF16) w = (Wt)d2bf_as_float(v);
                     else w = (Wt)d2h_as_float(v);
                     if (!isfinite(v)) fl |= DF_NONFINITE;
                     else if (isinf((double)w)) fl |= DF_RANGE;
@@ -77,28 +79,36 @@ __global__ __launch_bounds__(256) void k_downcast(int64_t n, const TWt *__restri
     if (fl) atomicOr(flags, fl);
 }
 
-// dst (pitch ldd) = binary16 copy of src (pitch lds); the source holds
-// binary16 numbers already, so the conversion is exact.  One workgroup per
-// row segment of kPackCols columns, four columns per thread (16-byte loads,
-// 8-byte stores when both pitches and bases allow them).
+// dst (pitch ldd) = 16-bit copy of src (pitch lds): binary16 (BF = false)
+// or bfloat16 (BF = true, the upper half of the binary32 pattern); the
+// source holds such numbers already, so the conversion is exact.  One
+// workgroup per row segment of kPackCols columns, four columns per thread
+// (16-byte loads, 8-byte stores when both pitches and bases allow them).
 constexpr int kPackCols = 1024;
 
+template <bool BF>
+__device__ __forceinline__ uint32_t pack2(float x, float y) {
+    if (BF) return (__float_as_uint(x) >> 16) | (__float_as_uint(y) & 0xffff0000u);
+    __half2 h = __floats2half2_rn(x, y);
+    return *reinterpret_cast<uint32_t *>(&h);
+}
+
+template <bool BF>
 __global__ __launch_bounds__(256) void k_pack_half(int64_t n, const float *__restrict__ src, int64_t lds,
-                                                   __half *__restrict__ dst, int64_t ldd, int segs, int vec) {
+                                                   uint16_t *__restrict__ dst, int64_t ldd, int segs, int vec) {
     const int64_t r = blockIdx.x / segs;
     const int64_t c = (int64_t)(blockIdx.x % segs) * kPackCols + threadIdx.x * 4;
     if (c >= n) return;
     const float *s = src + r * lds + c;
-    __half *d = dst + r * ldd + c;
+    uint16_t *d = dst + r * ldd + c;
     if (vec && c + 4 <= n) {
         const float4 v = *reinterpret_cast<const float4 *>(s);
-        __half2 lo = __floats2half2_rn(v.x, v.y), hi = __floats2half2_rn(v.z, v.w);
         uint2 o;
-        o.x = *reinterpret_cast<uint32_t *>(&lo);
-        o.y = *reinterpret_cast<uint32_t *>(&hi);
+        o.x = pack2<BF>(v.x, v.y);
+        o.y = pack2<BF>(v.z, v.w);
         *reinterpret_cast<uint2 *>(d) = o;
     } else {
-        for (int j = 0; j < 4 && c + j < n; ++j) d[j] = __float2half_rn(s[j]);
+        for (int j = 0; j < 4 && c + j < n; ++j) d[j] = (uint16_t)(pack2<BF>(s[j], 0.0f) & 0xffffu);
     }
 }
 
@@ -112,21 +122,26 @@ hipError_t launch_downcast(int64_t n, const void *A, int64_t lda, int tw, int tf
         const double *a = (const double *)A;
         if (tf == MPIR_F64) k_downcast<double, double, MPIR_F64><<<grid, block, 0, s>>>(n, a, lda, (double *)AF, ldf, anorm_bits, flags);
         else if (tf == MPIR_F32) k_downcast<double, float, MPIR_F32><<<grid, block, 0, s>>>(n, a, lda, (float *)AF, ldf, anorm_bits, flags);
+        else if (tf == MPIR_BF16) k_downcast<double, float, MPIR_BF16><<<grid, block, 0, s>>>(n, a, lda, (float *)AF, ldf, anorm_bits, flags);
         else k_downcast<double, float, MPIR_F16><<<grid, block, 0, s>>>(n, a, lda, (float *)AF, ldf, anorm_bits, flags);
     } else {
         const float *a = (const float *)A;
         if (tf == MPIR_F32) k_downcast<float, float, MPIR_F32><<<grid, block, 0, s>>>(n, a, lda, (float *)AF, ldf, anorm_bits, flags);
+        else if (tf == MPIR_BF16) k_downcast<float, float, MPIR_BF16><<<grid, block, 0, s>>>(n, a, lda, (float *)AF, ldf, anorm_bits, flags);
         else k_downcast<float, float, MPIR_F16><<<grid, block, 0, s>>>(n, a, lda, (float *)AF, ldf, anorm_bits, flags);
     }
     return hipGetLastError();
 }
 
-hipError_t launch_pack_half(int64_t n, const float *AF, int64_t ldf, __half *LU, int64_t ldl,
+hipError_t launch_pack_half(int tf, int64_t n, const float *AF, int64_t ldf, void *LU, int64_t ldl,
                             hipStream_t s) {
     if (n <= 0) return hipSuccess;
     const int segs = (int)((n + kPackCols - 1) / kPackCols);
     const int vec = (ldf % 4 == 0 && ldl % 4 == 0 && ((uintptr_t)AF & 15) == 0 && ((uintptr_t)LU & 7) == 0);
-    k_pack_half<<<(unsigned)(n * segs), 256, 0, s>>>(n, AF, ldf, LU, ldl, segs, vec);
+    if (tf == MPIR_BF16)
+        k_pack_half<true><<<(unsigned)(n * segs), 256, 0, s>>>(n, AF, ldf, (uint16_t *)LU, ldl, segs, vec);
+    else
+        k_pack_half<false><<<(unsigned)(n * segs), 256, 0, s>>>(n, AF, ldf, (uint16_t *)LU, ldl, segs, vec);
     return hipGetLastError();
 }
 

@@ -8,6 +8,9 @@
 //              working array); they are staged to LDS as binary16 and
 //              multiplied with v_mfma_f32_32x32x16_f16 into binary32
 //              accumulators; A22 stays binary32.
+//   TF = BF16: as F16 with bfloat16 operands and v_mfma_f32_32x32x16_bf16
+//              in the trailing update; inside the panel the binary32 path
+//              (products of two bfloat16 numbers are exact in binary32).
 //   TF = F64 : binary64, v_mfma_f64_16x16x4_f64 (the FP64 comparator).
 //
 // Tiling: a workgroup of four wave64s computes a BM x BN tile of C (binary32:
@@ -30,6 +33,22 @@ typedef float floatx16 __attribute__((ext_vector_type(16)));
 typedef float floatx4 __attribute__((ext_vector_type(4)));
 typedef _Float16 half8 __attribute__((ext_vector_type(8)));
 typedef _Float16 half4 __attribute__((ext_vector_type(4)));
+typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
+
+// 8-element operand vector of a 16-bit type and its 32x32x16 MFMA.
+template <typename T16> struct Vec16;
+template <> struct Vec16<_Float16> {
+    using V8 = half8;
+    __device__ static floatx16 mfma(V8 a, V8 b, floatx16 c) {
+        return __builtin_amdgcn_mfma_f32_32x32x16_f16(a, b, c, 0, 0, 0);
+    }
+};
+template <> struct Vec16<__bf16> {
+    using V8 = bf16x8;
+    __device__ static floatx16 mfma(V8 a, V8 b, floatx16 c) {
+        return __builtin_amdgcn_mfma_f32_32x32x16_bf16(a, b, c, 0, 0, 0);
+    }
+};
 typedef double doublex4 __attribute__((ext_vector_type(4)));
 
 // XCD-aware tile order: the dispatcher hands workgroup ids round-robin to
@@ -220,33 +239,38 @@ __global__ __launch_bounds__(256) void k_gemm_32(float *__restrict__ a, int64_t 
             }
 }
 
-// --------------------------------------- binary16 operands packed per step
-// For TF = F16, L21 and U12 hold binary16 numbers in the binary32 working
-// array.  They are packed once per update into binary16 copies with k
+// --------------------------------------- 16-bit operands packed per step
+// For TF = F16 (BF16), L21 and U12 hold binary16 (bfloat16) numbers in the
+// binary32 working array.  They are packed once per update into 16-bit
+// copies (the conversion is exact) with k
 // contiguous (A as m x kp, B transposed as n x kp; kp = kk rounded up to 32,
 // rows padded to 128, the padding zero), so the update reads half the bytes
 // with 16-byte loads that land directly in the MFMA operand layout.
 constexpr int kHT = 128;     // tile edge of the packed-operand update
 constexpr int kHK = 32;      // k per LDS stage
 
+template <typename T16>
 __global__ __launch_bounds__(256) void k_pack_rows_h(const float *__restrict__ a, int64_t ld,
                                                      int64_t r0, int64_t m, int64_t mp, int64_t k,
-                                                     int64_t kk, int64_t kp, _Float16 *__restrict__ out) {
+                                                     int64_t kk, int64_t kp, T16 *__restrict__ out) {
     // out[i][t] = a[r0 + i][k + t] (i < m, t < kk), zero padding
+    using V8 = typename Vec16<T16>::V8;
     const int64_t tot = mp * (kp / 8);
     for (int64_t e = (int64_t)blockIdx.x * 256 + threadIdx.x; e < tot; e += (int64_t)gridDim.x * 256) {
         const int64_t i = e / (kp / 8), t0 = (e - i * (kp / 8)) * 8;
-        half8 h;
+        V8 h;
 #pragma unroll
         for (int q = 0; q < 8; ++q)
-            h[q] = (_Float16)((i < m && t0 + q < kk) ? a[(r0 + i) * ld + k + t0 + q] : 0.0f);
-        *reinterpret_cast<half8 *>(out + i * kp + t0) = h;
+            h[q] = (T16)((i < m && t0 + q < kk) ? a[(r0 + i) * ld + k + t0 + q] : 0.0f);
+        *reinterpret_cast<V8 *>(out + i * kp + t0) = h;
     }
 }
 
+template <typename T16>
 __global__ __launch_bounds__(256) void k_pack_cols_h(const float *__restrict__ a, int64_t ld,
                                                      int64_t k, int64_t kk, int64_t kp, int64_t c0,
-                                                     int64_t nc, int64_t np_, _Float16 *__restrict__ out) {
+                                                     int64_t nc, int64_t np_, T16 *__restrict__ out) {
+    using V8 = typename Vec16<T16>::V8;
     // out[j][t] = a[k + t][c0 + j] (j < nc, t < kk), zero padding; 64 x 64
     // tiles transposed through LDS
     __shared__ float tl[64][65];
@@ -262,27 +286,28 @@ __global__ __launch_bounds__(256) void k_pack_cols_h(const float *__restrict__ a
         const int jj = e / 8, tq = (e % 8) * 8;
         const int64_t j = j0 + jj, t = t0 + tq;
         if (j < np_ && t < kp) {
-            half8 h;
+            V8 h;
 #pragma unroll
-            for (int q = 0; q < 8; ++q) h[q] = (_Float16)tl[tq + q][jj];
-            *reinterpret_cast<half8 *>(out + j * kp + t) = h;
+            for (int q = 0; q < 8; ++q) h[q] = (T16)tl[tq + q][jj];
+            *reinterpret_cast<V8 *>(out + j * kp + t) = h;
         }
     }
 }
 
 // C[r0 + i][c0 + j] -= sum_t Ah[i][t] Bt[j][t]: 128 x 128 tiles, four waves
-// in a 2 x 2 grid of 64 x 64 (2 x 2 blocks of v_mfma_f32_32x32x16_f16),
+// in a 2 x 2 grid of 64 x 64 (2 x 2 blocks of the 32x32x16 MFMA of T16),
 // double-buffered LDS stages of BK k; binary32 accumulators.
-template <int ROLE, int BK, int MINB>
+template <typename T16, int ROLE, int BK, int MINB>
 __global__ __launch_bounds__(256, MINB) void k_gemm_h16(float *__restrict__ a, int64_t ld, int64_t r0,
                                                         int64_t m, int64_t c0, int64_t nc,
-                                                        const _Float16 *__restrict__ Ah,
-                                                        const _Float16 *__restrict__ Bt, int64_t kp,
+                                                        const T16 *__restrict__ Ah,
+                                                        const T16 *__restrict__ Bt, int64_t kp,
                                                         int tiles_n, int nblk) {
-    constexpr int P = BK + 8;                         // LDS pitch (halves)
-    constexpr int NV = BK / 16;                       // 8-half vectors per thread and operand
-    __shared__ __align__(16) _Float16 As[2][kHT * P];
-    __shared__ __align__(16) _Float16 Bs[2][kHT * P];
+    using V8 = typename Vec16<T16>::V8;
+    constexpr int P = BK + 8;                         // LDS pitch (16-bit elements)
+    constexpr int NV = BK / 16;                       // 8-element vectors per thread and operand
+    __shared__ __align__(16) T16 As[2][kHT * P];
+    __shared__ __align__(16) T16 Bs[2][kHT * P];
     const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
     const int bid = xcd_remap(blockIdx.x, nblk);
     int trow, tcol;
@@ -291,21 +316,21 @@ __global__ __launch_bounds__(256, MINB) void k_gemm_h16(float *__restrict__ a, i
     const int wm = (wv >> 1) * 64, wn = (wv & 1) * 64;
     // loads: thread -> row tid / 2, BK/2 consecutive k at (tid % 2) * BK/2
     const int lr = tid >> 1, lk = (tid & 1) * (BK / 2);
-    const _Float16 *ap = Ah + (tm + lr) * kp + lk;
-    const _Float16 *bp = Bt + (tn + lr) * kp + lk;
-    half8 ra[NV], rb[NV];
+    const T16 *ap = Ah + (tm + lr) * kp + lk;
+    const T16 *bp = Bt + (tn + lr) * kp + lk;
+    V8 ra[NV], rb[NV];
     auto load = [&](int64_t kc) {
 #pragma unroll
         for (int q = 0; q < NV; ++q) {
-            ra[q] = *reinterpret_cast<const half8 *>(ap + kc + 8 * q);
-            rb[q] = *reinterpret_cast<const half8 *>(bp + kc + 8 * q);
+            ra[q] = *reinterpret_cast<const V8 *>(ap + kc + 8 * q);
+            rb[q] = *reinterpret_cast<const V8 *>(bp + kc + 8 * q);
         }
     };
     auto store = [&](int buf) {
 #pragma unroll
         for (int q = 0; q < NV; ++q) {
-            *reinterpret_cast<half8 *>(&As[buf][lr * P + lk + 8 * q]) = ra[q];
-            *reinterpret_cast<half8 *>(&Bs[buf][lr * P + lk + 8 * q]) = rb[q];
+            *reinterpret_cast<V8 *>(&As[buf][lr * P + lk + 8 * q]) = ra[q];
+            *reinterpret_cast<V8 *>(&Bs[buf][lr * P + lk + 8 * q]) = rb[q];
         }
     };
     floatx16 acc[2][2];
@@ -323,18 +348,18 @@ __global__ __launch_bounds__(256, MINB) void k_gemm_h16(float *__restrict__ a, i
 #pragma unroll
         for (int s2 = 0; s2 < BK; s2 += 16) {
             const int kb = s2 + 8 * (lane >> 5);
-            half8 af[2], bf[2];
+            V8 af[2], bf[2];
 #pragma unroll
             for (int i = 0; i < 2; ++i)
-                af[i] = *reinterpret_cast<const half8 *>(&As[buf][(wm + i * 32 + (lane & 31)) * P + kb]);
+                af[i] = *reinterpret_cast<const V8 *>(&As[buf][(wm + i * 32 + (lane & 31)) * P + kb]);
 #pragma unroll
             for (int j = 0; j < 2; ++j)
-                bf[j] = *reinterpret_cast<const half8 *>(&Bs[buf][(wn + j * 32 + (lane & 31)) * P + kb]);
+                bf[j] = *reinterpret_cast<const V8 *>(&Bs[buf][(wn + j * 32 + (lane & 31)) * P + kb]);
 #pragma unroll
             for (int i = 0; i < 2; ++i)
 #pragma unroll
                 for (int j = 0; j < 2; ++j)
-                    acc[i][j] = __builtin_amdgcn_mfma_f32_32x32x16_f16(af[i], bf[j], acc[i][j], 0, 0, 0);
+                    acc[i][j] = Vec16<T16>::mfma(af[i], bf[j], acc[i][j]);
         }
         if (more) store(buf ^ 1);
         __syncthreads();
@@ -526,7 +551,7 @@ hipError_t gemm_go(int mode, void *a, int64_t ld, int64_t r0, int64_t m, int64_t
         return hipGetLastError();
     }
     const bool vec = (ld % 4 == 0) && (k % 4 == 0) && (c0 % 4 == 0) && (base % 16 == 0);
-    if (mode == LU_F32) go32<false, ROLE>(vec, (float *)a, ld, r0, m, c0, nc, k, kk, cap, s);
+    if (mode == LU_F32 || mode == LU_BF16) go32<false, ROLE>(vec, (float *)a, ld, r0, m, c0, nc, k, kk, cap, s);
     else go32<true, ROLE>(vec, (float *)a, ld, r0, m, c0, nc, k, kk, cap, s);
     return hipGetLastError();
 }
@@ -538,28 +563,35 @@ size_t gemm_h16_ws_halves(int64_t rows, int64_t kk) {
     return (size_t)(rp * kp);
 }
 
-hipError_t launch_gemm_update_h16(float *a, int64_t ld, int64_t r0, int64_t m, int64_t c0, int64_t nc,
-                                  int64_t k, int64_t kk, __half *wa, __half *wb, int cap,
-                                  hipStream_t s) {
-    if (m <= 0 || nc <= 0 || kk <= 0) return hipSuccess;
+template <typename T16>
+hipError_t gemm_h16_go(float *a, int64_t ld, int64_t r0, int64_t m, int64_t c0, int64_t nc,
+                       int64_t k, int64_t kk, void *wa, void *wb, int cap, hipStream_t s) {
     const int64_t mp = (m + kHT - 1) / kHT * kHT, np_ = (nc + kHT - 1) / kHT * kHT;
     const int64_t kp = (kk + kHK - 1) / kHK * kHK;
     const int64_t tiles_m = mp / kHT, tiles_n = np_ / kHT, nblk = tiles_m * tiles_n;
     if (nblk > 0x7fffffffll) return hipErrorInvalidValue;
-    _Float16 *Ah = reinterpret_cast<_Float16 *>(wa), *Bt = reinterpret_cast<_Float16 *>(wb);
+    T16 *Ah = reinterpret_cast<T16 *>(wa), *Bt = reinterpret_cast<T16 *>(wb);
     {
         const int64_t work = mp * (kp / 8);
         const unsigned g = (unsigned)((work + 255) / 256 < 8192 ? (work + 255) / 256 : 8192);
-        k_pack_rows_h<<<g, 256, 0, s>>>(a, ld, r0, m, mp, k, kk, kp, Ah);
+        k_pack_rows_h<T16><<<g, 256, 0, s>>>(a, ld, r0, m, mp, k, kk, kp, Ah);
         dim3 gb((unsigned)(np_ / 64), (unsigned)((kp + 63) / 64));
-        k_pack_cols_h<<<gb, 256, 0, s>>>(a, ld, k, kk, kp, c0, nc, np_, Bt);
+        k_pack_cols_h<T16><<<gb, 256, 0, s>>>(a, ld, k, kk, kp, c0, nc, np_, Bt);
     }
-    auto kv = k_gemm_h16<0, kHK, 2>;
+    auto kv = k_gemm_h16<T16, 0, kHK, 2>;
     static int pad[9] = {-1, -1, -1, -1, -1, -1, -1, -1, -1};
     const int ci = cap < 0 ? 0 : cap > 8 ? 8 : cap;
     if (pad[ci] < 0) pad[ci] = cap_pad((const void *)kv, ci);
     kv<<<(unsigned)nblk, 256, pad[ci], s>>>(a, ld, r0, m, c0, nc, Ah, Bt, kp, (int)tiles_n, (int)nblk);
     return hipGetLastError();
+}
+
+hipError_t launch_gemm_update_h16(int mode, float *a, int64_t ld, int64_t r0, int64_t m, int64_t c0,
+                                  int64_t nc, int64_t k, int64_t kk, void *wa, void *wb, int cap,
+                                  hipStream_t s) {
+    if (m <= 0 || nc <= 0 || kk <= 0) return hipSuccess;
+    if (mode == LU_BF16) return gemm_h16_go<__bf16>(a, ld, r0, m, c0, nc, k, kk, wa, wb, cap, s);
+    return gemm_h16_go<_Float16>(a, ld, r0, m, c0, nc, k, kk, wa, wb, cap, s);
 }
 
 hipError_t launch_gemm_update(int mode, void *a, int64_t ld, int64_t r0, int64_t m, int64_t c0,

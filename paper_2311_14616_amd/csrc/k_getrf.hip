@@ -4,7 +4,7 @@
 // row interchanges, and the small unit-lower triangular solve that forms U12.
 // The trailing-matrix update is in k_gemm.hip.
 //
-// Working array: row-major, leading dimension ld, binary32 (TF = F32, F16)
+// Working array: row-major, leading dimension ld, binary32 (TF = F32, F16, BF16)
 // or binary64 (TF = F64).  Row interchanges of a row-major matrix move
 // contiguous memory, which is why this layout was chosen.
 #include <climits>
@@ -194,7 +194,7 @@ __device__ __forceinline__ Cd wave_max(Cd c) {
 // wave, then over the waves; the best row of each workgroup is posted with
 // the old row j in one slot of epoch-tagged words; every workgroup reads
 // every slot in one round trip and picks the same winner; swap; scale;
-// rank-1 update.  F16: the pivot row is rounded to binary16 when it becomes
+// rank-1 update.  F16 / BF16: the pivot row is rounded to TF when it becomes
 // the pivot row, each multiplier to binary16 when formed (products of
 // binary16 numbers are exact in binary32).
 // Binary32 leaves with one row per thread fit in 128 registers per lane,
@@ -202,7 +202,7 @@ __device__ __forceinline__ Cd wave_max(Cd c) {
 // trailing update beside the leaf's.
 template <typename W, int RT> constexpr int leaf_min_waves() { return sizeof(W) == 4 && RT == 1 ? 4 : 2; }
 
-template <typename W, bool F16, int RT>
+template <typename W, int RD, int RT>
 __global__ __launch_bounds__(kLeafNT, (leaf_min_waves<W, RT>())) void k_leaf(W *__restrict__ a, int64_t n, int64_t ld,
                                                   int64_t k0, int w, int G,
                                                   int32_t *__restrict__ ipiv, int64_t *info,
@@ -216,7 +216,7 @@ __global__ __launch_bounds__(kLeafNT, (leaf_min_waves<W, RT>())) void k_leaf(W *
     __shared__ Cd red[NWV];
     // rows in LDS as 32-bit words (value c in words K c .. K c + K-1)
     __shared__ __align__(16) uint32_t crow[C * K];   // this workgroup's candidate row (rotated)
-    __shared__ __align__(16) uint32_t prow[C * K];   // pivot row (rotated; F16: current part rounded)
+    __shared__ __align__(16) uint32_t prow[C * K];   // pivot row (rotated; F16/BF16: current part rounded)
     __shared__ __align__(16) uint32_t pupd[C * K];   // pivot row with the finished part zeroed
     __shared__ __align__(16) uint32_t orow[C * K];   // old row j
     __shared__ int s_p, s_bad;
@@ -270,7 +270,7 @@ __global__ __launch_bounds__(kLeafNT, (leaf_min_waves<W, RT>())) void k_leaf(W *
                 if (mine[q] && rr[q] == bi) {
 #pragma unroll
                     for (int c = 0; c < C; ++c) {
-                        const W x = (F16 && c < cur) ? (W)round_f16((float)v[q][c]) : v[q][c];
+                        const W x = (RD && c < cur) ? (W)round_lo<RD>((float)v[q][c]) : v[q][c];
                         Wd::put(prow, c, x);
                         Wd::put(pupd, c, c < cur ? x : (W)0);
                     }
@@ -359,7 +359,7 @@ __global__ __launch_bounds__(kLeafNT, (leaf_min_waves<W, RT>())) void k_leaf(W *
                     if (lane < 32) {
                         const int c = (wb0 + lane) / K;
                         uint32_t xw = (uint32_t)x;
-                        if (F16 && c < cur) xw = __float_as_uint(round_f16(__uint_as_float(xw)));
+                        if (RD && c < cur) xw = __float_as_uint(round_lo<RD>(__uint_as_float(xw)));
                         prow[wb0 + lane] = xw;
                         pupd[wb0 + lane] = c < cur ? xw : 0u;
                     }
@@ -397,7 +397,7 @@ __global__ __launch_bounds__(kLeafNT, (leaf_min_waves<W, RT>())) void k_leaf(W *
         for (int q = 0; q < kLeafRT; ++q) {
             if (rr[q] > j && piv != (W)0) {
                 W l = v[q][0] / piv;
-                if (F16) l = (W)round_f16((float)l);
+                if (RD) l = (W)round_lo<RD>((float)l);
 #pragma unroll
                 for (int c = 0; c < C - 1; ++c) {
                     const W prod = l * Wd::get(pupd, c + 1);
@@ -514,8 +514,8 @@ __global__ __launch_bounds__(256) void k_laswp(W *__restrict__ a, int64_t ld, in
 // U12 <- L11^{-1} U12 for rows [k, k+w), w <= 32, columns [c0, c1): one
 // thread per column, L11 in LDS, the w entries of the column in registers,
 // no barrier inside the substitution.  Right-looking: row t is final at step
-// t (F16: rounded to binary16 then) and updates the rows below it.
-template <typename W, bool F16>
+// t (F16 / BF16: rounded to TF then) and updates the rows below it.
+template <typename W, int RD>
 __global__ __launch_bounds__(256) void k_trsm_col(W *__restrict__ a, int64_t ld, int64_t k, int w,
                                                   int64_t c0, int64_t c1) {
     __shared__ W L[32][33];
@@ -533,7 +533,7 @@ __global__ __launch_bounds__(256) void k_trsm_col(W *__restrict__ a, int64_t ld,
 #pragma unroll
     for (int t = 0; t < 32; ++t) {
         if (t < w) {
-            if (F16) x[t] = (W)round_f16((float)x[t]);
+            if (RD) x[t] = (W)round_lo<RD>((float)x[t]);
 #pragma unroll
             for (int s2 = t + 1; s2 < 32; ++s2) {
                 const W prod = L[s2][t] * x[t];
@@ -551,8 +551,8 @@ __global__ __launch_bounds__(256) void k_trsm_col(W *__restrict__ a, int64_t ld,
 // [c0, c1).  A workgroup owns kU12CW columns and keeps their w rows in LDS
 // for the whole solve.  Blocks of 32 rows, in increasing order: (a) the
 // diagonal block by substitution in registers, one wave per two columns
-// (lane = row; the final entry of row t is broadcast by readlane; F16:
-// rounded to binary16 when final, before it updates later rows); (b) every
+// (lane = row; the final entry of row t is broadcast by readlane; F16 /
+// BF16: rounded to TF when final, before it updates later rows); (b) every
 // row below, by one thread, subtracting the block's 32 products in
 // increasing order.  The L entries each phase needs are loaded while the
 // other phase runs.  Each entry thus receives its updates in increasing k,
@@ -573,7 +573,7 @@ template <> __device__ __forceinline__ double bcast_lane(double x, int l) {
     return __longlong_as_double((long long)(((uint64_t)hi << 32) | lo));
 }
 
-template <typename W, bool F16>
+template <typename W, int RD>
 __global__ __launch_bounds__(kU12NT) void k_u12(W *__restrict__ a, int64_t ld, int64_t k, int w,
                                                 int64_t c0, int64_t c1) {
     __shared__ __align__(16) W X[kU12MaxW][kU12CW];
@@ -613,7 +613,7 @@ __global__ __launch_bounds__(kU12NT) void k_u12(W *__restrict__ a, int64_t ld, i
 #pragma unroll
             for (int t = 0; t < 32; ++t) {
                 if (t < hb) {
-                    if (F16 && s == t) x = (W)round_f16((float)x);
+                    if (RD && s == t) x = (W)round_lo<RD>((float)x);
                     const W xa = bcast_lane(x, t), xb = bcast_lane(x, 32 + t);
                     const W xt = (lane >> 5) ? xb : xa;
                     if (s > t) {
@@ -682,7 +682,7 @@ bool leaf_cooperative() {
 
 int leaf_gmax() { return num_cus() < kLeafMaxG ? num_cus() : kLeafMaxG; }
 
-template <typename W, bool F16, int RT>
+template <typename W, int RD, int RT>
 hipError_t leaf_run(W *a, int64_t n, int64_t ld, int64_t k0, int w, int32_t *ipiv, int64_t *info,
                     PanelSync *ps, uint32_t *host_base, uint32_t *flags, hipStream_t s) {
     const int64_t m = n - k0;
@@ -691,18 +691,18 @@ hipError_t leaf_run(W *a, int64_t n, int64_t ld, int64_t k0, int w, int32_t *ipi
     const int G = (int)G64;
     uint32_t base = *host_base;
     if (G == 1) {
-        k_leaf<W, F16, RT><<<1, kLeafNT, 0, s>>>(a, n, ld, k0, w, G, ipiv, info, ps, base, flags);
+        k_leaf<W, RD, RT><<<1, kLeafNT, 0, s>>>(a, n, ld, k0, w, G, ipiv, info, ps, base, flags);
         return hipGetLastError();
     }
     if (!leaf_cooperative()) {
-        k_leaf<W, F16, RT><<<G, kLeafNT, 0, s>>>(a, n, ld, k0, w, G, ipiv, info, ps, base, flags);
+        k_leaf<W, RD, RT><<<G, kLeafNT, 0, s>>>(a, n, ld, k0, w, G, ipiv, info, ps, base, flags);
         hipError_t e = hipGetLastError();
         if (e == hipSuccess) *host_base = base + (uint32_t)w;
         return e;
     }
     void *args[] = {&a, (void *)&n, (void *)&ld, (void *)&k0, (void *)&w, (void *)&G,
                     &ipiv, &info, &ps, &base, &flags};
-    hipError_t e = hipLaunchCooperativeKernel((const void *)k_leaf<W, F16, RT>, dim3(G),
+    hipError_t e = hipLaunchCooperativeKernel((const void *)k_leaf<W, RD, RT>, dim3(G),
                                               dim3(kLeafNT), args, 0, s);
     if (e == hipSuccess) *host_base = base + (uint32_t)w;
     return e;
@@ -710,15 +710,15 @@ hipError_t leaf_run(W *a, int64_t n, int64_t ld, int64_t k0, int w, int32_t *ipi
 
 // One row per thread unless the panel fits one workgroup at two (then no
 // exchange is needed) or needs more workgroups than may run at once.
-template <typename W, bool F16>
+template <typename W, int RD>
 hipError_t leaf_go(W *a, int64_t n, int64_t ld, int64_t k0, int w, int32_t *ipiv, int64_t *info,
                    PanelSync *ps, uint32_t *host_base, uint32_t *flags, hipStream_t s) {
     if constexpr (leaf_rt_max<W>() == 2) {
         const int64_t m = n - k0;
         if (m <= 2 * kLeafNT || m > (int64_t)leaf_gmax() * kLeafNT)
-            return leaf_run<W, F16, 2>(a, n, ld, k0, w, ipiv, info, ps, host_base, flags, s);
+            return leaf_run<W, RD, 2>(a, n, ld, k0, w, ipiv, info, ps, host_base, flags, s);
     }
-    return leaf_run<W, F16, 1>(a, n, ld, k0, w, ipiv, info, ps, host_base, flags, s);
+    return leaf_run<W, RD, 1>(a, n, ld, k0, w, ipiv, info, ps, host_base, flags, s);
 }
 
 }  // namespace
@@ -732,10 +732,12 @@ hipError_t launch_leaf(int mode, void *a, int64_t n, int64_t ld, int64_t k0, int
                        hipStream_t s) {
     if (w <= 0 || w > kLeafMaxW || k0 >= n) return hipErrorInvalidValue;
     if (mode == LU_F64)
-        return leaf_go<double, false>((double *)a, n, ld, k0, w, ipiv, info, ps, host_base, flags, s);
+        return leaf_go<double, 0>((double *)a, n, ld, k0, w, ipiv, info, ps, host_base, flags, s);
     if (mode == LU_F32)
-        return leaf_go<float, false>((float *)a, n, ld, k0, w, ipiv, info, ps, host_base, flags, s);
-    return leaf_go<float, true>((float *)a, n, ld, k0, w, ipiv, info, ps, host_base, flags, s);
+        return leaf_go<float, 0>((float *)a, n, ld, k0, w, ipiv, info, ps, host_base, flags, s);
+    if (mode == LU_BF16)
+        return leaf_go<float, 2>((float *)a, n, ld, k0, w, ipiv, info, ps, host_base, flags, s);
+    return leaf_go<float, 1>((float *)a, n, ld, k0, w, ipiv, info, ps, host_base, flags, s);
 }
 
 hipError_t launch_laswp(int mode, void *a, int64_t n, int64_t ld, int64_t k0, int cnt,
@@ -774,9 +776,10 @@ hipError_t launch_trsm(int mode, void *a, int64_t ld, int64_t k, int w, int64_t 
                        hipStream_t s) {
     if (w <= 0 || w > 32 || c1 <= c0) return w <= 0 || w > 32 ? hipErrorInvalidValue : hipSuccess;
     const unsigned nb = (unsigned)((c1 - c0 + 255) / 256);
-    if (mode == LU_F64) k_trsm_col<double, false><<<nb, 256, 0, s>>>((double *)a, ld, k, w, c0, c1);
-    else if (mode == LU_F32) k_trsm_col<float, false><<<nb, 256, 0, s>>>((float *)a, ld, k, w, c0, c1);
-    else k_trsm_col<float, true><<<nb, 256, 0, s>>>((float *)a, ld, k, w, c0, c1);
+    if (mode == LU_F64) k_trsm_col<double, 0><<<nb, 256, 0, s>>>((double *)a, ld, k, w, c0, c1);
+    else if (mode == LU_F32) k_trsm_col<float, 0><<<nb, 256, 0, s>>>((float *)a, ld, k, w, c0, c1);
+    else if (mode == LU_BF16) k_trsm_col<float, 2><<<nb, 256, 0, s>>>((float *)a, ld, k, w, c0, c1);
+    else k_trsm_col<float, 1><<<nb, 256, 0, s>>>((float *)a, ld, k, w, c0, c1);
     return hipGetLastError();
 }
 
@@ -787,9 +790,10 @@ hipError_t launch_u12(int mode, void *a, int64_t ld, int64_t k, int w, int64_t c
     if (w <= 0 || w > kU12MaxW) return hipErrorInvalidValue;
     if (c1 <= c0) return hipSuccess;
     const unsigned nb = (unsigned)((c1 - c0 + kU12CW - 1) / kU12CW);
-    if (mode == LU_F64) k_u12<double, false><<<nb, kU12NT, 0, s>>>((double *)a, ld, k, w, c0, c1);
-    else if (mode == LU_F32) k_u12<float, false><<<nb, kU12NT, 0, s>>>((float *)a, ld, k, w, c0, c1);
-    else k_u12<float, true><<<nb, kU12NT, 0, s>>>((float *)a, ld, k, w, c0, c1);
+    if (mode == LU_F64) k_u12<double, 0><<<nb, kU12NT, 0, s>>>((double *)a, ld, k, w, c0, c1);
+    else if (mode == LU_F32) k_u12<float, 0><<<nb, kU12NT, 0, s>>>((float *)a, ld, k, w, c0, c1);
+    else if (mode == LU_BF16) k_u12<float, 2><<<nb, kU12NT, 0, s>>>((float *)a, ld, k, w, c0, c1);
+    else k_u12<float, 1><<<nb, kU12NT, 0, s>>>((float *)a, ld, k, w, c0, c1);
     return hipGetLastError();
 }
 

@@ -1,6 +1,7 @@
 // Triangular solves with the packed LU factors, d_F = U^{-1} L^{-1} rhat
 // (the "d = U^{-1} L^{-1} r" step of Algorithm IR, done in the solve
-// precision TS: binary32 arithmetic on binary32 or binary16 factors, or
+// precision TS: binary32 arithmetic on binary32, binary16 or bfloat16
+// factors, or
 // binary64 for the FP64 comparator).
 //
 // One launch per triangle.  The factor is cut into 64-row block rows; each
@@ -117,7 +118,7 @@ __global__ __launch_bounds__(256) void k_trsv(const Ft *__restrict__ LU, int64_t
     // dependency block (neither depends on the solution).  Every load below
     // reads a clamped, in-bounds index and the guard is applied to the value,
     // so the loads of a block are all in flight together.  Binary64 solves on
-    // binary32 / binary16 factors keep these rows in binary32 (exact).
+    // binary32 / 16-bit factors keep these rows in binary32 (exact).
     using St = typename std::conditional<(sizeof(Yt) == 8 && sizeof(Ft) < 8), float, Yt>::type;
     St drow[BS], lrow[BS];
     const int64_t lastc = t > 0 ? (int64_t)(LOWER ? t - 1 : nblk - t) * BS : 0;
@@ -218,11 +219,13 @@ hipError_t launch_trsv(int tf, int ysol, const void *LU, int64_t n, int64_t ld, 
     if (n <= 0) return hipSuccess;
     if (tf == MPIR_F64) return go<double, double>((const double *)LU, n, ld, (double *)y, yw, ts, flags, st, force, s);
     if (ysol == MPIR_F64) {
-        // binary64 substitutions on binary32 / binary16 factors (MPS)
+        // binary64 substitutions on binary32 / 16-bit factors (MPS)
         if (tf == MPIR_F32) return go<float, double>((const float *)LU, n, ld, (double *)y, yw, ts, flags, st, force, s);
+        if (tf == MPIR_BF16) return go<bf16_t, double>((const bf16_t *)LU, n, ld, (double *)y, yw, ts, flags, st, force, s);
         return go<__half, double>((const __half *)LU, n, ld, (double *)y, yw, ts, flags, st, force, s);
     }
     if (tf == MPIR_F32) return go<float, float>((const float *)LU, n, ld, (float *)y, yw, ts, flags, st, force, s);
+    if (tf == MPIR_BF16) return go<bf16_t, float>((const bf16_t *)LU, n, ld, (float *)y, yw, ts, flags, st, force, s);
     return go<__half, float>((const __half *)LU, n, ld, (float *)y, yw, ts, flags, st, force, s);
 }
 

@@ -153,6 +153,7 @@ __global__ __launch_bounds__(256) void k_scale_permute(int64_t n, const TRt *__r
     Yt o;
     if (TF == MPIR_F64) o = (Yt)v;
     else if (TF == MPIR_F32) o = (Yt)(float)v;
+    else if (TF == MPIR_BF16) o = (Yt)d2bf_as_float(v);
     else o = (Yt)d2h_as_float(v);
     rhat[i] = o;
 }
@@ -280,9 +281,11 @@ hipError_t launch_scale_permute(int64_t n, int tr, int tf, const void *r, const 
         k_scale_permute<double, double, MPIR_F64><<<g, bl, 0, s>>>(n, (const double *)r, perm, (double *)rhat, st, ts, force);
     } else if (tr == MPIR_F64) {
         if (tf == MPIR_F32) k_scale_permute<double, float, MPIR_F32><<<g, bl, 0, s>>>(n, (const double *)r, perm, (float *)rhat, st, ts, force);
+        else if (tf == MPIR_BF16) k_scale_permute<double, float, MPIR_BF16><<<g, bl, 0, s>>>(n, (const double *)r, perm, (float *)rhat, st, ts, force);
         else k_scale_permute<double, float, MPIR_F16><<<g, bl, 0, s>>>(n, (const double *)r, perm, (float *)rhat, st, ts, force);
     } else {
         if (tf == MPIR_F32) k_scale_permute<float, float, MPIR_F32><<<g, bl, 0, s>>>(n, (const float *)r, perm, (float *)rhat, st, ts, force);
+        else if (tf == MPIR_BF16) k_scale_permute<float, float, MPIR_BF16><<<g, bl, 0, s>>>(n, (const float *)r, perm, (float *)rhat, st, ts, force);
         else k_scale_permute<float, float, MPIR_F16><<<g, bl, 0, s>>>(n, (const float *)r, perm, (float *)rhat, st, ts, force);
     }
     return hipGetLastError();

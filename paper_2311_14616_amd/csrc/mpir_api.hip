@@ -126,16 +126,21 @@ namespace {
 
 size_t esize(int p) { return p == MPIR_F64 ? 8 : (p == MPIR_F32 ? 4 : 2); }
 
+// 16-bit factorization precisions (factors packed for the solves).
+bool is16(int tf) { return tf == MPIR_F16 || tf == MPIR_BF16; }
+
 bool valid_triple(int tw, int tf, int tr) {
     if (tw != MPIR_F64 && tw != MPIR_F32) return false;
-    if (tf != MPIR_F64 && tf != MPIR_F32 && tf != MPIR_F16) return false;
+    if (tf != MPIR_F64 && tf != MPIR_F32 && tf != MPIR_F16 && tf != MPIR_BF16) return false;
     if (tr != MPIR_F64 && tr != MPIR_F32) return false;
     if (tw == MPIR_F32 && tf == MPIR_F64) return false;   // TF must not exceed TW
     if (tr == MPIR_F32 && tw == MPIR_F64) return false;   // TR >= TW
     return true;
 }
 
-int lu_mode_of(int tf) { return tf == MPIR_F64 ? LU_F64 : (tf == MPIR_F32 ? LU_F32 : LU_F16); }
+int lu_mode_of(int tf) {
+    return tf == MPIR_F64 ? LU_F64 : tf == MPIR_F32 ? LU_F32 : tf == MPIR_BF16 ? LU_BF16 : LU_F16;
+}
 
 #define HIPCHK(x)                                  \
     do {                                           \
@@ -188,9 +193,9 @@ mpir_status alloc_handle(mpir_fact f) {
     if (f->ld % 1024 == 0) f->ld += 32;
     if (dalloc(&f->work, (size_t)f->ld * n * wes) != hipSuccess) return MPIR_ERR_ALLOC;
     // binary16 factors for the solves: the same padded pitch
-    if (f->tf == MPIR_F16 && dalloc(&f->lu16, (size_t)f->ld * n * 2) != hipSuccess) return MPIR_ERR_ALLOC;
-    if (f->tf == MPIR_F16) {
-        const size_t hw = gemm_h16_ws_halves(n, panel_width(LU_F16)) * 2;
+    if (is16(f->tf) && dalloc(&f->lu16, (size_t)f->ld * n * 2) != hipSuccess) return MPIR_ERR_ALLOC;
+    if (is16(f->tf)) {
+        const size_t hw = gemm_h16_ws_halves(n, panel_width(f->mode)) * 2;
         for (auto &pr : f->hws)
             for (auto &q : pr)
                 if (dalloc(&q, hw) != hipSuccess) return MPIR_ERR_ALLOC;
@@ -297,9 +302,9 @@ hipError_t factor_panel(mpir_fact f, int64_t K, int w, hipStream_t s) {
 // [k, k+kk); F16: binary16 operands packed first (workspace slot ws).
 hipError_t trailing_update(mpir_fact f, int64_t r0, int64_t m, int64_t c0, int64_t nc, int64_t k,
                            int64_t kk, int cap, int ws, hipStream_t s) {
-    if (f->mode == LU_F16)
-        return launch_gemm_update_h16((float *)f->work, f->ld, r0, m, c0, nc, k, kk, f->hws[ws][0],
-                                      f->hws[ws][1], cap, s);
+    if (f->mode == LU_F16 || f->mode == LU_BF16)
+        return launch_gemm_update_h16(f->mode, (float *)f->work, f->ld, r0, m, c0, nc, k, kk,
+                                      f->hws[ws][0], f->hws[ws][1], cap, s);
     return launch_gemm_update(f->mode, f->work, f->ld, r0, m, c0, nc, k, kk, cap, 0, s);
 }
 
@@ -349,7 +354,7 @@ int trailing_cap(int mode) {
     if (env >= 0) return env;
     // measured at N = 32768 (factorization time against the cap, with the
     // binary32 / binary16 leaves held to 128 registers per lane)
-    return mode == LU_F32 ? 6 : mode == LU_F16 ? 3 : 2;
+    return mode == LU_F32 ? 6 : (mode == LU_F16 || mode == LU_BF16) ? 3 : 2;
 }
 
 mpir_status getrf(mpir_fact f) {
@@ -429,7 +434,7 @@ mpir_status factor_impl(mpir_fact f, int64_t *info) {
     if (flags & DF_RANGE) return MPIR_ERR_RANGE;
     mpir_status st = getrf(f);
     if (st != MPIR_OK) return st;
-    if (f->tf == MPIR_F16) HIPCHK(launch_pack_half(n, (const float *)f->work, f->ld, f->lu16, f->ld, s));
+    if (is16(f->tf)) HIPCHK(launch_pack_half(f->tf, n, (const float *)f->work, f->ld, f->lu16, f->ld, s));
     uint64_t abits = 0;
     int64_t inf = 0;
     HIPCHK(hipMemcpyAsync(&abits, f->anorm_bits_d, 8, hipMemcpyDeviceToHost, s));
@@ -449,7 +454,7 @@ mpir_status factor_impl(mpir_fact f, int64_t *info) {
     return inf ? MPIR_ERR_SINGULAR : MPIR_OK;
 }
 
-const void *factors_ptr(mpir_fact f) { return f->tf == MPIR_F16 ? (const void *)f->lu16 : f->work; }
+const void *factors_ptr(mpir_fact f) { return is16(f->tf) ? (const void *)f->lu16 : f->work; }
 
 }  // namespace
 
@@ -828,14 +833,14 @@ mpir_status mpir_downcast(int64_t n, const void *dA, int64_t lda, mpir_prec tw, 
     void *tmp = nullptr;
     mpir_status st = MPIR_OK;
     if (dalloc(&bits, 16) != hipSuccess || dalloc(&flags, 8) != hipSuccess) st = MPIR_ERR_ALLOC;
-    if (st == MPIR_OK && tf == MPIR_F16 && dalloc(&tmp, (size_t)n * n * 4) != hipSuccess) st = MPIR_ERR_ALLOC;
+    if (st == MPIR_OK && is16(tf) && dalloc(&tmp, (size_t)n * n * 4) != hipSuccess) st = MPIR_ERR_ALLOC;
     if (st == MPIR_OK) {
         hipMemsetAsync(bits, 0, 8, s);
         hipMemsetAsync(flags, 0, 4, s);
-        if (launch_downcast(n, dA, lda, tw, tf, tf == MPIR_F16 ? tmp : dAF, n, bits, flags, s) != hipSuccess)
+        if (launch_downcast(n, dA, lda, tw, tf, is16(tf) ? tmp : dAF, n, bits, flags, s) != hipSuccess)
             st = MPIR_ERR_HIP;
-        if (st == MPIR_OK && tf == MPIR_F16 &&
-            launch_pack_half(n, (const float *)tmp, n, (__half *)dAF, n, s) != hipSuccess)
+        if (st == MPIR_OK && is16(tf) &&
+            launch_pack_half(tf, n, (const float *)tmp, n, dAF, n, s) != hipSuccess)
             st = MPIR_ERR_HIP;
         uint64_t hb = 0;
         uint32_t hf = 0;
@@ -861,7 +866,7 @@ mpir_status mpir_get_factors(mpir_fact f, void *dLU, int32_t *ipiv) {
     const int64_t n = f->n;
     if (dLU) {
         const size_t es = esize(f->tf);
-        const void *src = f->tf == MPIR_F16 ? (const void *)f->lu16 : f->work;
+        const void *src = is16(f->tf) ? (const void *)f->lu16 : f->work;
         HIPCHK(hipMemcpy2DAsync(dLU, n * es, src, f->ld * es, n * es, n, hipMemcpyDeviceToDevice, s));
     }
     if (ipiv) HIPCHK(hipMemcpyAsync(ipiv, f->ipiv, n * 4, hipMemcpyDeviceToHost, s));

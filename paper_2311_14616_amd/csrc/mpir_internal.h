@@ -17,8 +17,14 @@ namespace mpir {
 //   LU_F16   : binary16 L and U, binary32 trailing matrix, FP16 MFMA with
 //              binary32 accumulation; a U row is rounded to binary16 when it
 //              becomes final, a multiplier when it is formed.
+//   LU_BF16  : the same with bfloat16 L and U (binary32 exponent range, an
+//              8-bit significand); BF16 MFMA for the trailing update, FP32
+//              MFMA (exact products of bfloat16 numbers) inside the panel.
 // ---------------------------------------------------------------------------
-enum LuMode { LU_F64 = 0, LU_F32 = 1, LU_F16 = 2 };
+enum LuMode { LU_F64 = 0, LU_F32 = 1, LU_F16 = 2, LU_BF16 = 3 };
+
+// Rounding applied to the factors: 0 none, 1 binary16, 2 bfloat16.
+constexpr int rd_of_mode(int mode) { return mode == LU_F16 ? 1 : mode == LU_BF16 ? 2 : 0; }
 
 // Device status word bits (sticky, OR-ed by kernels).
 enum DevFlag : uint32_t {
@@ -90,10 +96,37 @@ __device__ __forceinline__ float d2h_as_float(double x) {
     return round_f16(d2f_round_odd(x));
 }
 
+// binary32 -> bfloat16 (round to nearest, ties to even, on the bit pattern:
+// adding 0x7fff plus the lowest kept bit carries into the kept bits exactly
+// when the dropped half is above the midpoint, or at it with the kept part
+// odd; a carry out of the significand raises the exponent, up to infinity).
+__device__ __forceinline__ float round_bf16(float x) {
+    uint32_t u = __float_as_uint(x);
+    if ((u & 0x7fffffffu) > 0x7f800000u) return x;             // NaN
+    u += 0x7fffu + ((u >> 16) & 1u);
+    return __uint_as_float(u & 0xffff0000u);
+}
+
+// binary64 -> bfloat16 rounded once (round to odd to binary32 first:
+// 24 >= 8 + 2).
+__device__ __forceinline__ float d2bf_as_float(double x) {
+    return round_bf16(d2f_round_odd(x));
+}
+
+template <int RD> __device__ __forceinline__ float round_lo(float x) {
+    return RD == 1 ? round_f16(x) : RD == 2 ? round_bf16(x) : x;
+}
+
+// bfloat16 storage (the upper half of a binary32 pattern).
+struct bf16_t { uint16_t u; };
+__device__ __forceinline__ float bf16_to_f(bf16_t v) { return __uint_as_float((uint32_t)v.u << 16); }
+
 template <typename T> __device__ __forceinline__ double to_d(T v) { return (double)v; }
 template <> __device__ __forceinline__ double to_d<__half>(__half v) { return (double)__half2float(v); }
+template <> __device__ __forceinline__ double to_d<bf16_t>(bf16_t v) { return (double)bf16_to_f(v); }
 template <typename T> __device__ __forceinline__ float to_f(T v) { return (float)v; }
 template <> __device__ __forceinline__ float to_f<__half>(__half v) { return __half2float(v); }
+template <> __device__ __forceinline__ float to_f<bf16_t>(bf16_t v) { return bf16_to_f(v); }
 
 // Atomic max of a non-negative double through its bit pattern (IEEE order of
 // non-negative doubles equals the unsigned order of their bits; NaN maps to a
@@ -136,8 +169,9 @@ __device__ __forceinline__ void atomic_max_nonneg(uint64_t *p, double v) {
 hipError_t launch_downcast(int64_t n, const void *A, int64_t lda, int tw, int tf,
                            void *AF, int64_t ldf, uint64_t *anorm_bits, uint32_t *flags,
                            hipStream_t s);
-// Working array (row pitch ldf) -> n x n binary16 factors (row pitch ldl).
-hipError_t launch_pack_half(int64_t n, const float *AF, int64_t ldf, __half *LU, int64_t ldl,
+// Working array (row pitch ldf) -> n x n 16-bit factors (row pitch ldl):
+// binary16 for tf = MPIR_F16, bfloat16 for MPIR_BF16.
+hipError_t launch_pack_half(int tf, int64_t n, const float *AF, int64_t ldf, void *LU, int64_t ldl,
                             hipStream_t s);
 // Working array -> TF storage with the given row-major layout (copy).
 hipError_t launch_copy_factors(int64_t n, const void *src, int tf, void *dst, hipStream_t s);
@@ -175,12 +209,13 @@ hipError_t launch_u12(int mode, void *a, int64_t ld, int64_t k, int w, int64_t c
 hipError_t launch_gemm_update(int mode, void *a, int64_t ld, int64_t r0, int64_t m,
                               int64_t c0, int64_t nc, int64_t k, int64_t kk, int cap,
                               int role, hipStream_t s);
-// a4, TF = F16: the same trailing update with L21 and U12 first packed into
-// binary16 (k contiguous) in the workspaces wa (>= gemm_h16_ws_halves(m, kk)
-// halves) and wb (>= gemm_h16_ws_halves(nc, kk)).
+// a4, TF = F16 or BF16 (mode): the same trailing update with L21 and U12
+// first packed into 16-bit copies (k contiguous) in the workspaces wa
+// (>= gemm_h16_ws_halves(m, kk) elements) and wb (>= gemm_h16_ws_halves(nc,
+// kk) elements).
 size_t gemm_h16_ws_halves(int64_t rows, int64_t kk);
-hipError_t launch_gemm_update_h16(float *a, int64_t ld, int64_t r0, int64_t m, int64_t c0,
-                                  int64_t nc, int64_t k, int64_t kk, __half *wa, __half *wb,
+hipError_t launch_gemm_update_h16(int mode, float *a, int64_t ld, int64_t r0, int64_t m, int64_t c0,
+                                  int64_t nc, int64_t k, int64_t kk, void *wa, void *wb,
                                   int cap, hipStream_t s);
 
 // a5: residual r = b - A x in TR, partial sums over column chunks then a

@@ -160,12 +160,14 @@ def _prec_of_dtype(dt) -> int:
         return F32
     if dt == torch.float16:
         return F16
+    if dt == torch.bfloat16:
+        return BF16
     raise TypeError(f"unsupported dtype {dt}")
 
 
 def _dtype_of_prec(p: int):
     torch = _torch()
-    return {F64: torch.float64, F32: torch.float32, F16: torch.float16}[p]
+    return {F64: torch.float64, F32: torch.float32, F16: torch.float16, BF16: torch.bfloat16}[p]
 
 
 def _stream_ptr(stream):

@@ -59,7 +59,8 @@ def test_argument_validation_needs_no_device(M):
     assert L.mpir_factor(8, dummy, 4, M.F64, M.F32, M.F64, None, C.byref(h), C.byref(info)) == M.ERR_ARG
     assert L.mpir_factor(8, None, 8, M.F64, M.F32, M.F64, None, C.byref(h), C.byref(info)) == M.ERR_ARG
     assert L.mpir_factor(8, dummy, 8, M.F32, M.F64, M.F64, None, C.byref(h), C.byref(info)) == M.ERR_ARG
-    assert L.mpir_factor(8, dummy, 8, M.F64, M.BF16, M.F64, None, C.byref(h), C.byref(info)) == M.ERR_ARG
+    assert L.mpir_factor(8, dummy, 8, M.F64, 7, M.F64, None, C.byref(h), C.byref(info)) == M.ERR_ARG
+    assert L.mpir_factor(8, dummy, 8, M.BF16, M.BF16, M.F64, None, C.byref(h), C.byref(info)) == M.ERR_ARG
     assert L.mpir_factor(8, dummy, 8, M.F64, M.F32, M.F32, None, C.byref(h), C.byref(info)) == M.ERR_ARG
     assert h.value in (None, 0) and info.value == 0
     assert L.mpir_solve(None, dummy, dummy) == M.ERR_ARG
