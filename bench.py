@@ -138,7 +138,10 @@ def experiments(M, I, torch, dev):
           of one plain FP32 LU solve;
     (iv)  GMRES-IR (the factors as left preconditioner, basissize 10) against
           IR with TF=F16 at N=32768, alpha in {1, 10, 799}: corrections, GMRES
-          iterations per correction, stop reason, time."""
+          iterations per correction, stop reason, time;
+    (v)   several right-hand sides with one factorization (TF=F32, N=32768,
+          nrhs in {4, 16}): refinement time of one mpir_ir_solve_multi call
+          against nrhs single-column refinements."""
     import numpy as np
     tp = M.term(tol_rel=1e-14, litmax=20)
 
@@ -253,6 +256,30 @@ def experiments(M, I, torch, dev):
         print(json.dumps(row), flush=True)
         out.append(row)
         del At, b
+    # (v)
+    n = 32768
+    At = I.gmat_operator_torch(n, 1.0, dev)
+    b = I.rhs_ones_torch(At)
+    f = M.Factorization(At, M.F32, M.F64)
+    for nrhs in (4, 16):
+        scales = [2.0 ** (k % 7 - 3) * (-1) ** k for k in range(nrhs)]
+        B = torch.stack([s * b for s in scales]).contiguous()
+        X, reps = f.ir_solve_multi(B, term_parms=tp)            # warm-up
+        (X, reps), ms_multi = timed(lambda: f.ir_solve_multi(B, term_parms=tp))
+        ms_single = 0.0
+        for c in range(nrhs):
+            _, ms = timed(lambda: f.ir_solve(B[c].contiguous(), term_parms=tp))
+            ms_single += ms
+        row = {"experiment": "several right-hand sides, TF=F32", "n": n, "nrhs": nrhs,
+               "multi_ms": round(ms_multi, 3), "single_ms_sum": round(ms_single, 3),
+               "speedup": round(ms_single / ms_multi, 3),
+               "n_iter": [r.n_iter for r in reps], "all_converged": all(r.stop == 0 for r in reps),
+               "bwd_err_max": max(r.bwd_err for r in reps)}
+        print(json.dumps(row), flush=True)
+        out.append(row)
+        del B, X
+    f.destroy()
+    del At, b
     return out
 
 

@@ -129,6 +129,23 @@ mpir_status mpir_solve(mpir_fact f, const void *db, void *dx);
 mpir_status mpir_ir_solve(mpir_fact f, const void *db, void *dx,
                           const mpir_term *t, mpir_report *rep);
 
+/* Several right-hand sides with one factorization (sections "Memory
+ * Allocations: I", on reusing a factorization, and "Double-Single IR", on
+ * solving for many right-hand sides with one factorization): column c of the
+ * n x nrhs column-major matrices dB (ldb >= n) and dX (ldx >= n, TW) is
+ * refined exactly as mpir_ir_solve refines it alone -- the same operations
+ * in the same order, so each column's result and report equal that call's
+ * -- but each residual pass reads A once for up to four columns and each
+ * pair of triangular solves reads the factors once for up to four columns
+ * (two with binary64 solves).  Every column keeps its own termination
+ * state; columns that have stopped are not updated.  reps (host, may be
+ * NULL): nrhs reports.  Returns MPIR_ERR_NONFINITE if some column of dB is
+ * not finite (that column's report says so, the others are solved).
+ * Workspace for nrhs columns is allocated in the handle on first use and
+ * kept until mpir_destroy. */
+mpir_status mpir_ir_solve_multi(mpir_fact f, int32_t nrhs, const void *dB, int64_t ldb, void *dX,
+                                int64_t ldx, const mpir_term *t, mpir_report *reps);
+
 /* GMRES-IR (sections "Krylov-IR" and "GMRES-IR"; the package's mpglu): the
  * refinement of mpir_ir_solve, each correction equation A d = r solved by
  * GMRES left-preconditioned with the factors, P = U^{-1} L^{-1} Pi applied

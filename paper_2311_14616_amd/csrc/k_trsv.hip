@@ -64,42 +64,62 @@ template <> struct YWords<double> {
     }
 };
 
-// Entry `col` of the solution once published with `epoch` (every lane of
-// the wave polls its own word; the wave leaves when all have arrived).
-template <typename Yt>
-__device__ __forceinline__ Yt get_y(const uint64_t *yw, int64_t col, bool valid, uint32_t epoch,
-                                    bool &timed_out) {
+// Entry `col` of NR solution columns (column c at yw + c * ystride words)
+// once published with `epoch`: every lane of the wave polls its own words,
+// the wave leaves when all have arrived.
+template <typename Yt, int NR>
+__device__ __forceinline__ void get_ys(const uint64_t *yw, int64_t ystride, int64_t col, bool valid,
+                                       uint32_t epoch, bool &timed_out, Yt (&out)[NR]) {
     constexpr int K = YWords<Yt>::K;
-    uint32_t p[K];
+    uint32_t p[NR][K];
+    bool ok[NR];
 #pragma unroll
-    for (int q = 0; q < K; ++q) p[q] = 0;
-    bool ok = !valid;
+    for (int c = 0; c < NR; ++c) {
+        ok[c] = !valid;
+#pragma unroll
+        for (int q = 0; q < K; ++q) p[c][q] = 0;
+    }
     uint64_t spins = 0;
     for (;;) {
-        if (!ok) {
-            ok = true;
+        bool all = true;
 #pragma unroll
-            for (int q = 0; q < K; ++q) {
-                const uint64_t w = __hip_atomic_load(&yw[col * K + q], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-                ok = ok && (uint32_t)(w >> 32) == epoch;
-                p[q] = (uint32_t)w;
+        for (int c = 0; c < NR; ++c) {
+            if (!ok[c]) {
+                bool o = true;
+#pragma unroll
+                for (int q = 0; q < K; ++q) {
+                    const uint64_t w = __hip_atomic_load(&yw[c * ystride + col * K + q], __ATOMIC_RELAXED,
+                                                         __HIP_MEMORY_SCOPE_AGENT);
+                    o = o && (uint32_t)(w >> 32) == epoch;
+                    p[c][q] = (uint32_t)w;
+                }
+                ok[c] = o;
             }
+            all = all && ok[c];
         }
-        if (__all(ok)) break;
+        if (__all(all)) break;
         if (++spins > kSpinLimit) { timed_out = true; break; }
         __builtin_amdgcn_s_sleep(1);
     }
-    return valid ? YWords<Yt>::from(p) : (Yt)0;
+#pragma unroll
+    for (int c = 0; c < NR; ++c) out[c] = valid ? YWords<Yt>::from(p[c]) : (Yt)0;
 }
 
-template <typename Ft, typename Yt, bool LOWER>
+// NR right-hand sides at once (columns y + c * ldy, solution words at
+// yw + c * n * K): the factor is read once for all of them; phase 1 keeps NR
+// sums per row, and in phase 2 wave c solves the diagonal block of column c.
+// Each column receives exactly the operations of the one-column solve, in
+// the same order.
+template <typename Ft, typename Yt, bool LOWER, int NR>
 __global__ __launch_bounds__(256) void k_trsv(const Ft *__restrict__ LU, int64_t n, int64_t ld,
-                                              Yt *__restrict__ y, uint64_t *__restrict__ yw,
+                                              Yt *__restrict__ y, int64_t ldy, uint64_t *__restrict__ yw,
                                               TrsvSync *ts, uint32_t *flags, const IrState *st,
                                               int force) {
+    static_assert(NR >= 1 && NR <= 4, "one wave per right-hand side in phase 2");
     if (!force && st->done) return;
     constexpr int K = YWords<Yt>::K;
-    __shared__ Yt red[BS][BS + 1];
+    const int64_t ystride = n * K;
+    __shared__ Yt red[NR][BS][BS + 1];
     __shared__ int s_t;
     __shared__ int s_bad;
     const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
@@ -114,7 +134,7 @@ __global__ __launch_bounds__(256) void k_trsv(const Ft *__restrict__ LU, int64_t
     const int rows = (int)((n - i0) < BS ? (n - i0) : BS);
     bool timed_out = false;
 
-    // wave 0 preloads its row of the diagonal block and of the last
+    // waves 0 .. NR-1 preload their row of the diagonal block and of the last
     // dependency block (neither depends on the solution).  Every load below
     // reads a clamped, in-bounds index and the guard is applied to the value,
     // so the loads of a block are all in flight together.  Binary64 solves on
@@ -122,7 +142,7 @@ __global__ __launch_bounds__(256) void k_trsv(const Ft *__restrict__ LU, int64_t
     using St = typename std::conditional<(sizeof(Yt) == 8 && sizeof(Ft) < 8), float, Yt>::type;
     St drow[BS], lrow[BS];
     const int64_t lastc = t > 0 ? (int64_t)(LOWER ? t - 1 : nblk - t) * BS : 0;
-    if (wv == 0) {
+    if (wv < NR) {
         const bool ok = lane < rows;
         const Ft *dr = LU + (i0 + (ok ? lane : rows - 1)) * ld;
 #pragma unroll
@@ -138,9 +158,11 @@ __global__ __launch_bounds__(256) void k_trsv(const Ft *__restrict__ LU, int64_t
     // ---- phase 1 (all waves): dependency blocks 0 .. t-2 ----
     // rows past the end of the matrix read the last row (their sums are
     // never used); columns past the end read column n-1 and are masked
-    Yt acc[16];
+    Yt acc[NR][16];
 #pragma unroll
-    for (int r = 0; r < 16; ++r) acc[r] = (Yt)0;
+    for (int c = 0; c < NR; ++c)
+#pragma unroll
+        for (int r = 0; r < 16; ++r) acc[c][r] = (Yt)0;
     const Ft *base = LU + i0 * ld;
     const int wvs = __builtin_amdgcn_readfirstlane(wv);   // wave-uniform: row offsets stay scalar
     int rsel[16];
@@ -154,46 +176,57 @@ __global__ __launch_bounds__(256) void k_trsv(const Ft *__restrict__ LU, int64_t
         Ft lv[16];
 #pragma unroll
         for (int r = 0; r < 16; ++r) lv[r] = base[(int64_t)rsel[r] * ld + cc];
-        const Yt yv = get_y<Yt>(yw, col, cv, epoch, timed_out);
+        Yt yv[NR];
+        get_ys<Yt, NR>(yw, ystride, col, cv, epoch, timed_out, yv);
 #pragma unroll
-        for (int r = 0; r < 16; ++r) acc[r] += (cv ? (Yt)to_d(lv[r]) : (Yt)0) * yv;
+        for (int r = 0; r < 16; ++r) {
+            const Yt lvr = cv ? (Yt)to_d(lv[r]) : (Yt)0;
+#pragma unroll
+            for (int c = 0; c < NR; ++c) acc[c][r] = fmadd(lvr, yv[c], acc[c][r]);
+        }
     }
     if (timed_out) s_bad = 1;
 #pragma unroll
-    for (int r = 0; r < 16; ++r) red[wv * 16 + r][lane] = acc[r];
+    for (int c = 0; c < NR; ++c)
+#pragma unroll
+        for (int r = 0; r < 16; ++r) red[c][wv * 16 + r][lane] = acc[c][r];
     __syncthreads();
 
-    // ---- phase 2 (wave 0): last dependency block, then the diagonal block ----
-    if (wv == 0) {
+    // ---- phase 2 (wave c, c < NR): last dependency block, then the
+    // diagonal block of column c ----
+    if (wv < NR) {
+        const int c = wvs;
         Yt s = (Yt)0;
         if (lane < rows)
-            for (int c = 0; c < BS; ++c) s += red[lane][c];
+            for (int k = 0; k < BS; ++k) s += red[c][lane][k];
         bool to = s_bad != 0;
         if (t > 0 && !to) {
-            const Yt yl = get_y<Yt>(yw, lastc + lane, lastc + lane < n, epoch, to);
+            Yt yl[1];
+            get_ys<Yt, 1>(yw + c * ystride, ystride, lastc + lane, lastc + lane < n, epoch, to, yl);
 #pragma unroll
-            for (int c = 0; c < BS; ++c) s += (Yt)lrow[c] * bcast(yl, c);
+            for (int k = 0; k < BS; ++k) s = fmadd((Yt)lrow[k], bcast(yl[0], k), s);
         }
-        Yt z = lane < rows ? y[i0 + lane] - s : (Yt)0;
+        Yt *yc = y + c * ldy;
+        Yt z = lane < rows ? yc[i0 + lane] - s : (Yt)0;
         if (LOWER) {
 #pragma unroll
             for (int j = 0; j < BS; ++j) {
                 const Yt yj = bcast(z, j);
-                if (lane > j) z -= (Yt)drow[j] * yj;
+                if (lane > j) z = fmadd(-(Yt)drow[j], yj, z);
             }
         } else {
 #pragma unroll
             for (int j = BS - 1; j >= 0; --j) {
                 if (lane == j) z = z / (Yt)drow[j];
                 const Yt yj = bcast(z, j);
-                if (lane < j) z -= (Yt)drow[j] * yj;
+                if (lane < j) z = fmadd(-(Yt)drow[j], yj, z);
             }
         }
         if (lane < rows) {
-            y[i0 + lane] = z;
+            yc[i0 + lane] = z;
 #pragma unroll
             for (int q = 0; q < K; ++q)
-                __hip_atomic_store(&yw[(i0 + lane) * K + q],
+                __hip_atomic_store(&yw[c * ystride + (i0 + lane) * K + q],
                                    ((uint64_t)epoch << 32) | YWords<Yt>::part(z, q),
                                    __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
         }
@@ -203,30 +236,51 @@ __global__ __launch_bounds__(256) void k_trsv(const Ft *__restrict__ LU, int64_t
     if (tid == 0 && s_bad) atomicOr(flags, (uint32_t)DF_TIMEOUT);
 }
 
-template <typename Ft, typename Yt>
-hipError_t go(const Ft *LU, int64_t n, int64_t ld, Yt *y, uint64_t *yw, TrsvSync *ts, uint32_t *flags,
-              const IrState *st, int force, hipStream_t s) {
+template <typename Ft, typename Yt, int NR>
+hipError_t go(const Ft *LU, int64_t n, int64_t ld, Yt *y, int64_t ldy, uint64_t *yw, TrsvSync *ts,
+              uint32_t *flags, const IrState *st, int force, hipStream_t s) {
     const unsigned nblk = (unsigned)((n + BS - 1) / BS);
-    k_trsv<Ft, Yt, true><<<nblk, 256, 0, s>>>(LU, n, ld, y, yw, ts, flags, st, force);
-    k_trsv<Ft, Yt, false><<<nblk, 256, 0, s>>>(LU, n, ld, y, yw, ts, flags, st, force);
+    k_trsv<Ft, Yt, true, NR><<<nblk, 256, 0, s>>>(LU, n, ld, y, ldy, yw, ts, flags, st, force);
+    k_trsv<Ft, Yt, false, NR><<<nblk, 256, 0, s>>>(LU, n, ld, y, ldy, yw, ts, flags, st, force);
     return hipGetLastError();
+}
+
+template <typename Ft, typename Yt>
+hipError_t go_nr(int nr, const Ft *LU, int64_t n, int64_t ld, Yt *y, int64_t ldy, uint64_t *yw,
+                 TrsvSync *ts, uint32_t *flags, const IrState *st, int force, hipStream_t s) {
+    if (nr == 1) return go<Ft, Yt, 1>(LU, n, ld, y, ldy, yw, ts, flags, st, force, s);
+    if (nr == 2) return go<Ft, Yt, 2>(LU, n, ld, y, ldy, yw, ts, flags, st, force, s);
+    if constexpr (sizeof(Yt) == 4) {
+        if (nr == 4) return go<Ft, Yt, 4>(LU, n, ld, y, ldy, yw, ts, flags, st, force, s);
+    }
+    return hipErrorInvalidValue;
 }
 
 }  // namespace
 
 hipError_t launch_trsv(int tf, int ysol, const void *LU, int64_t n, int64_t ld, void *y, uint64_t *yw,
                        TrsvSync *ts, uint32_t *flags, const IrState *st, int force, hipStream_t s) {
+    return launch_trsv_multi(tf, ysol, 1, LU, n, ld, y, n, yw, ts, flags, st, force, s);
+}
+
+int trsv_max_rhs(int ysol) { return ysol == MPIR_F64 ? 2 : 4; }
+
+hipError_t launch_trsv_multi(int tf, int ysol, int nr, const void *LU, int64_t n, int64_t ld, void *y,
+                             int64_t ldy, uint64_t *yw, TrsvSync *ts, uint32_t *flags, const IrState *st,
+                             int force, hipStream_t s) {
     if (n <= 0) return hipSuccess;
-    if (tf == MPIR_F64) return go<double, double>((const double *)LU, n, ld, (double *)y, yw, ts, flags, st, force, s);
+    if (nr < 1 || nr > trsv_max_rhs(ysol == MPIR_F64 || tf == MPIR_F64 ? MPIR_F64 : MPIR_F32) || ldy < n)
+        return hipErrorInvalidValue;
+    if (tf == MPIR_F64) return go_nr<double, double>(nr, (const double *)LU, n, ld, (double *)y, ldy, yw, ts, flags, st, force, s);
     if (ysol == MPIR_F64) {
         // binary64 substitutions on binary32 / 16-bit factors (MPS)
-        if (tf == MPIR_F32) return go<float, double>((const float *)LU, n, ld, (double *)y, yw, ts, flags, st, force, s);
-        if (tf == MPIR_BF16) return go<bf16_t, double>((const bf16_t *)LU, n, ld, (double *)y, yw, ts, flags, st, force, s);
-        return go<__half, double>((const __half *)LU, n, ld, (double *)y, yw, ts, flags, st, force, s);
+        if (tf == MPIR_F32) return go_nr<float, double>(nr, (const float *)LU, n, ld, (double *)y, ldy, yw, ts, flags, st, force, s);
+        if (tf == MPIR_BF16) return go_nr<bf16_t, double>(nr, (const bf16_t *)LU, n, ld, (double *)y, ldy, yw, ts, flags, st, force, s);
+        return go_nr<__half, double>(nr, (const __half *)LU, n, ld, (double *)y, ldy, yw, ts, flags, st, force, s);
     }
-    if (tf == MPIR_F32) return go<float, float>((const float *)LU, n, ld, (float *)y, yw, ts, flags, st, force, s);
-    if (tf == MPIR_BF16) return go<bf16_t, float>((const bf16_t *)LU, n, ld, (float *)y, yw, ts, flags, st, force, s);
-    return go<__half, float>((const __half *)LU, n, ld, (float *)y, yw, ts, flags, st, force, s);
+    if (tf == MPIR_F32) return go_nr<float, float>(nr, (const float *)LU, n, ld, (float *)y, ldy, yw, ts, flags, st, force, s);
+    if (tf == MPIR_BF16) return go_nr<bf16_t, float>(nr, (const bf16_t *)LU, n, ld, (float *)y, ldy, yw, ts, flags, st, force, s);
+    return go_nr<__half, float>(nr, (const __half *)LU, n, ld, (float *)y, ldy, yw, ts, flags, st, force, s);
 }
 
 }  // namespace mpir

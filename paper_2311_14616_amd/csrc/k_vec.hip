@@ -82,7 +82,7 @@ __global__ __launch_bounds__(256) void k_resid_partial(int64_t n, const TWt *__r
             for (int q = 0; q < 16; ++q) {
                 const TRt xq = (TRt)x[j + q];
 #pragma unroll
-                for (int r = 0; r < RPT; ++r) acc[r] += (TRt)v[q][r] * xq;
+                for (int r = 0; r < RPT; ++r) acc[r] = fmadd((TRt)v[q][r], xq, acc[r]);
             }
         }
     }
@@ -90,11 +90,73 @@ __global__ __launch_bounds__(256) void k_resid_partial(int64_t n, const TWt *__r
         const TRt xq = (TRt)x[j];
 #pragma unroll
         for (int r = 0; r < RPT; ++r)
-            if (i + r < n) acc[r] += (TRt)col[(j - j0) * lda + r] * xq;
+            if (i + r < n) acc[r] = fmadd((TRt)col[(j - j0) * lda + r], xq, acc[r]);
     }
 #pragma unroll
     for (int r = 0; r < RPT; ++r)
         if (i + r < n) partial[(int64_t)blockIdx.y * n + i + r] = (double)acc[r];
+}
+
+// ---- residual, pass 1 for NR right-hand sides (columns x + q * ldx):
+// A is read once; column q's partial sums go to partial + q * nch * n and
+// receive exactly the operations of the one-column pass, in its order.
+template <typename TWt, typename TRt, int RPT, int NR>
+__global__ __launch_bounds__(256) void k_resid_partial_multi(int64_t n, const TWt *__restrict__ A,
+                                                             int64_t lda, const TWt *__restrict__ x,
+                                                             int64_t ldx, double *__restrict__ partial,
+                                                             int nch) {
+    const int64_t i = ((int64_t)blockIdx.x * kRowsPerBlock + threadIdx.x) * RPT;
+    const int64_t j0 = (int64_t)blockIdx.y * kChunkCols;
+    const int64_t j1 = (j0 + kChunkCols) < n ? (j0 + kChunkCols) : n;
+    if (i >= n) return;
+    TRt acc[NR][RPT];
+#pragma unroll
+    for (int c = 0; c < NR; ++c)
+#pragma unroll
+        for (int r = 0; r < RPT; ++r) acc[c][r] = 0;
+    const TWt *col = A + i + j0 * lda;
+    const bool full = i + RPT <= n;
+    int64_t j = j0;
+    if (full) {
+        for (; j + 16 <= j1; j += 16) {
+            TWt v[16][RPT];
+#pragma unroll
+            for (int q = 0; q < 16; ++q) {
+                const TWt *p = col + (j - j0 + q) * lda;
+                if constexpr (RPT == 2 && sizeof(TWt) == 8) {
+                    const double2 t = *reinterpret_cast<const double2 *>(p);
+                    v[q][0] = t.x; v[q][1] = t.y;
+                } else if constexpr (RPT == 2 && sizeof(TWt) == 4) {
+                    const float2 t = *reinterpret_cast<const float2 *>(p);
+                    v[q][0] = t.x; v[q][1] = t.y;
+                } else {
+#pragma unroll
+                    for (int r = 0; r < RPT; ++r) v[q][r] = p[r];
+                }
+            }
+#pragma unroll
+            for (int q = 0; q < 16; ++q)
+#pragma unroll
+                for (int c = 0; c < NR; ++c) {
+                    const TRt xq = (TRt)x[c * ldx + j + q];
+#pragma unroll
+                    for (int r = 0; r < RPT; ++r) acc[c][r] = fmadd((TRt)v[q][r], xq, acc[c][r]);
+                }
+        }
+    }
+    for (; j < j1; ++j)
+#pragma unroll
+        for (int c = 0; c < NR; ++c) {
+            const TRt xq = (TRt)x[c * ldx + j];
+#pragma unroll
+            for (int r = 0; r < RPT; ++r)
+                if (i + r < n) acc[c][r] = fmadd((TRt)col[(j - j0) * lda + r], xq, acc[c][r]);
+        }
+#pragma unroll
+    for (int c = 0; c < NR; ++c)
+#pragma unroll
+        for (int r = 0; r < RPT; ++r)
+            if (i + r < n) partial[((int64_t)c * nch + blockIdx.y) * n + i + r] = (double)acc[c][r];
 }
 
 // ---- residual, pass 2: r_i = b_i - sum_c partial[c][i] (c increasing) ----
@@ -261,6 +323,54 @@ hipError_t launch_residual(int64_t n, const void *A, int64_t lda, int tw, int tr
         if (vec) k_resid_partial<float, float, 2><<<g1, b1, 0, s>>>(n, (const float *)A, lda, (const float *)x, partial, st, force);
         else k_resid_partial<float, float, 1><<<g1, b1, 0, s>>>(n, (const float *)A, lda, (const float *)x, partial, st, force);
         k_resid_reduce<float, float><<<g2, b2, 0, s>>>(n, (const float *)b, (const float *)x, partial, nch, (float *)r, st, force);
+    }
+    return hipGetLastError();
+}
+
+template <typename TWt, typename TRt, int NR>
+void resid_multi_go(bool vec, int64_t n, const TWt *A, int64_t lda, const TWt *x, int64_t ldx,
+                    double *partial, int nch, hipStream_t s) {
+    const int rpt = vec ? 2 : 1;
+    dim3 g1((unsigned)((n + (int64_t)kRowsPerBlock * rpt - 1) / ((int64_t)kRowsPerBlock * rpt)), (unsigned)nch);
+    if (vec) k_resid_partial_multi<TWt, TRt, 2, NR><<<g1, kRowsPerBlock, 0, s>>>(n, A, lda, x, ldx, partial, nch);
+    else k_resid_partial_multi<TWt, TRt, 1, NR><<<g1, kRowsPerBlock, 0, s>>>(n, A, lda, x, ldx, partial, nch);
+}
+
+template <typename TWt, typename TRt>
+void resid_multi_nr(int nr, bool vec, int64_t n, const TWt *A, int64_t lda, const TWt *x, int64_t ldx,
+                    double *partial, int nch, hipStream_t s) {
+    if (nr == 1) resid_multi_go<TWt, TRt, 1>(vec, n, A, lda, x, ldx, partial, nch, s);
+    else if (nr == 2) resid_multi_go<TWt, TRt, 2>(vec, n, A, lda, x, ldx, partial, nch, s);
+    else if (nr == 3) resid_multi_go<TWt, TRt, 3>(vec, n, A, lda, x, ldx, partial, nch, s);
+    else resid_multi_go<TWt, TRt, 4>(vec, n, A, lda, x, ldx, partial, nch, s);
+}
+
+hipError_t launch_residual_multi(int64_t n, const void *A, int64_t lda, int tw, int tr, int nr,
+                                 const void *b, int64_t ldb, const void *x, int64_t ldx, void *r,
+                                 double *partial, int nch, IrState *st, int force, hipStream_t s) {
+    if (n <= 0) return hipSuccess;
+    if (nr < 1 || nr > 4) return hipErrorInvalidValue;
+    const size_t es = tw == MPIR_F64 ? 8 : 4;
+    const size_t rs = tr == MPIR_F64 ? 8 : 4;
+    const bool vec = ((uintptr_t)A % (2 * es) == 0) && (lda % 2 == 0);
+    dim3 g2(blocks_for(n, 256)), b2(256);
+    if (tw == MPIR_F64)
+        resid_multi_nr<double, double>(nr, vec, n, (const double *)A, lda, (const double *)x, ldx, partial, nch, s);
+    else if (tr == MPIR_F64)
+        resid_multi_nr<float, double>(nr, vec, n, (const float *)A, lda, (const float *)x, ldx, partial, nch, s);
+    else
+        resid_multi_nr<float, float>(nr, vec, n, (const float *)A, lda, (const float *)x, ldx, partial, nch, s);
+    for (int c = 0; c < nr; ++c) {
+        const char *bc = (const char *)b + c * ldb * es;
+        const char *xc = (const char *)x + c * ldx * es;
+        char *rc = (char *)r + c * n * rs;
+        const double *pc = partial + (int64_t)c * nch * n;
+        if (tw == MPIR_F64)
+            k_resid_reduce<double, double><<<g2, b2, 0, s>>>(n, (const double *)bc, (const double *)xc, pc, nch, (double *)rc, st + c, force);
+        else if (tr == MPIR_F64)
+            k_resid_reduce<float, double><<<g2, b2, 0, s>>>(n, (const float *)bc, (const float *)xc, pc, nch, (double *)rc, st + c, force);
+        else
+            k_resid_reduce<float, float><<<g2, b2, 0, s>>>(n, (const float *)bc, (const float *)xc, pc, nch, (float *)rc, st + c, force);
     }
     return hipGetLastError();
 }

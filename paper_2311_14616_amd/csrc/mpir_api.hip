@@ -120,6 +120,13 @@ struct mpir_fact_s {
     double *kv = nullptr, *kw = nullptr, *kt = nullptr, *kzero = nullptr, *kd = nullptr;
     double *kc = nullptr;
     IrState *kst = nullptr;
+    // several right-hand sides (first use): per-column states, residuals,
+    // scaled residuals / solutions and solution words, residual partial sums
+    int mcap = 0;
+    IrState *mst = nullptr;
+    void *mr = nullptr, *mrhat = nullptr;
+    double *mpart = nullptr;
+    uint64_t *myw = nullptr;
 };
 
 namespace {
@@ -178,6 +185,11 @@ void free_handle(mpir_fact f) {
     if (f->stream2) hipStreamDestroy(f->stream2);
     for (double *q : {f->kv, f->kw, f->kt, f->kzero, f->kd, f->kc}) hipFree(q);
     hipFree(f->kst);
+    hipFree(f->mst);
+    hipFree(f->mr);
+    hipFree(f->mrhat);
+    hipFree(f->mpart);
+    hipFree(f->myw);
     delete f;
 }
 
@@ -821,6 +833,159 @@ mpir_status mpir_gmres_ir_solve(mpir_fact f, const void *db, void *dx, const mpi
         rep->t_ir_ms = ms;
     }
     return MPIR_OK;
+}
+
+mpir_status mpir_ir_solve_multi(mpir_fact f, int32_t nrhs, const void *dB, int64_t ldb, void *dX,
+                                int64_t ldx, const mpir_term *t, mpir_report *reps) {
+    if (!f || !dB || !dX || nrhs < 1 || ldb < f->n || ldx < f->n) return MPIR_ERR_ARG;
+    mpir_term term;
+    if (t) term = *t;
+    else mpir_term_default(&term);
+    if (term.litmax < 1 || term.litmax > MPIR_HIST_MAX - 1 || !(term.Rmax > 0.0)) return MPIR_ERR_ARG;
+    if ((term.onthefly != 0 && term.onthefly != 1) || term.reserved != 0) return MPIR_ERR_ARG;
+    if (reps) {
+        for (int c = 0; c < nrhs; ++c) {
+            std::memset(&reps[c], 0, sizeof(reps[c]));
+            reps[c].info = f->info;
+            reps[c].t_factor_ms = f->t_factor_ms;
+        }
+    }
+    if (f->info) return MPIR_ERR_SINGULAR;
+    hipStream_t s = f->stream;
+    const int64_t n = f->n;
+    const size_t es = esize(f->tw), rs = esize(f->tr);
+    if (f->mcap < nrhs) {
+        HIPCHK(hipStreamSynchronize(s));
+        hipFree(f->mst);
+        hipFree(f->mr);
+        hipFree(f->mrhat);
+        hipFree(f->mpart);
+        hipFree(f->myw);
+        f->mst = nullptr; f->mr = nullptr; f->mrhat = nullptr; f->mpart = nullptr; f->myw = nullptr;
+        f->mcap = 0;
+        if (dalloc(&f->mst, (size_t)nrhs * sizeof(IrState)) != hipSuccess ||
+            dalloc(&f->mr, (size_t)nrhs * n * 8) != hipSuccess ||
+            dalloc(&f->mrhat, (size_t)nrhs * n * 8) != hipSuccess ||
+            dalloc(&f->mpart, (size_t)4 * f->nchunks * n * 8) != hipSuccess ||
+            dalloc(&f->myw, (size_t)nrhs * n * 2 * 8) != hipSuccess)
+            return MPIR_ERR_ALLOC;
+        HIPCHK(hipMemsetAsync(f->mrhat, 0, (size_t)nrhs * n * 8, s));
+        HIPCHK(hipMemsetAsync(f->myw, 0, (size_t)nrhs * n * 2 * 8, s));
+        f->mcap = nrhs;
+    }
+    const double uw = f->tw == MPIR_F64 ? std::ldexp(1.0, -52) : std::ldexp(1.0, -23);
+    IrState h{};
+    h.it = -1;
+    h.anorm = f->anorm;
+    h.wilk = (f->tr == MPIR_F64 && f->tw != MPIR_F64) ? 1 : 0;
+    h.residterm = term.residterm ? 1 : 0;
+    h.litmax = term.litmax;
+    h.tol_r = term.tol_rel > 0 ? term.tol_rel : term.Cr * uw;
+    h.tol_e = term.tol_rel > 0 ? term.tol_rel : term.Ce * uw;
+    h.rmax = term.Rmax;
+    std::vector<IrState> hv((size_t)nrhs, h);
+    hipEvent_t e0, e1;
+    HIPCHK(hipEventCreate(&e0));
+    HIPCHK(hipEventCreate(&e1));
+    HIPCHK(hipMemcpyAsync(f->mst, hv.data(), (size_t)nrhs * sizeof(IrState), hipMemcpyHostToDevice, s));
+    HIPCHK(hipMemsetAsync(f->flags_d, 0, 4, s));
+    HIPCHK(hipEventRecord(e0, s));
+    const char *B = (const char *)dB;
+    char *X = (char *)dX;
+    char *R = (char *)f->mr, *RH = (char *)f->mrhat;
+    IrState *S = f->mst;
+    for (int c = 0; c < nrhs; ++c) {
+        HIPCHK(launch_ir_init(n, f->tw, f->tr, B + c * ldb * es, X + c * ldx * es, R + c * n * rs, S + c, s));
+        HIPCHK(launch_terminate(S + c, s));
+    }
+    const void *LU = factors_ptr(f);
+    // the precisions of mpir_ir_solve: LPS (rhat in TF, binary32 solves;
+    // binary64 for TF = F64) or the on-the-fly solve in TW
+    const bool mps = term.onthefly && f->tf != f->tw;
+    const int rprec = mps ? f->tw : f->tf;
+    const int yprec = mps ? f->tw : (f->tf == MPIR_F64 ? MPIR_F64 : MPIR_F32);
+    const size_t ys = yprec == MPIR_F64 ? 8 : 4;
+    const int tnr = trsv_max_rhs(yprec);
+    std::vector<int32_t> done((size_t)nrhs, 0);
+    auto any_active = [&](int c0, int c1) {
+        for (int c = c0; c < c1; ++c)
+            if (!done[c]) return true;
+        return false;
+    };
+    for (int it = 0; it < term.litmax; ++it) {
+        HIPCHK(hipMemcpy2DAsync(done.data(), 4, &S->done, sizeof(IrState), 4, (size_t)nrhs,
+                                hipMemcpyDeviceToHost, s));
+        HIPCHK(hipStreamSynchronize(s));
+        if (!any_active(0, nrhs)) break;
+        for (int c0 = 0, c1 = 0; c0 < nrhs; c0 = c1) {
+            // chunks of 4, 2 or 1 columns (the solve's instantiations)
+            int nr = nrhs - c0 < tnr ? nrhs - c0 : tnr;
+            if (nr == 3) nr = 2;
+            c1 = c0 + nr;
+            if (!any_active(c0, c1)) continue;
+            for (int c = c0; c < c1; ++c)
+                HIPCHK(launch_scale_permute(n, f->tr, rprec, R + c * n * rs, f->perm, RH + c * n * ys, S + c,
+                                            f->ts, 0, s));
+            HIPCHK(launch_trsv_multi(f->tf, yprec, c1 - c0, LU, n, f->ld, RH + c0 * n * ys, n,
+                                     f->myw, f->ts, f->flags_d, S + c0, 1, s));
+            for (int c = c0; c < c1; ++c)
+                HIPCHK(launch_update(n, f->tw, rprec, RH + c * n * ys, X + c * ldx * es, S + c, 0, s));
+        }
+        for (int c0 = 0; c0 < nrhs; c0 += 4) {
+            const int c1 = c0 + 4 < nrhs ? c0 + 4 : nrhs;
+            if (!any_active(c0, c1)) continue;
+            HIPCHK(launch_residual_multi(n, f->A, f->lda, f->tw, f->tr, c1 - c0, B + c0 * ldb * es, ldb,
+                                         X + c0 * ldx * es, ldx, R + c0 * n * rs, f->mpart, f->nchunks,
+                                         S + c0, 0, s));
+        }
+        for (int c = 0; c < nrhs; ++c)
+            if (!done[c]) HIPCHK(launch_terminate(S + c, s));
+    }
+    HIPCHK(hipEventRecord(e1, s));
+    uint32_t flags = 0;
+    HIPCHK(hipMemcpyAsync(hv.data(), S, (size_t)nrhs * sizeof(IrState), hipMemcpyDeviceToHost, s));
+    HIPCHK(hipMemcpyAsync(&flags, f->flags_d, 4, hipMemcpyDeviceToHost, s));
+    HIPCHK(hipStreamSynchronize(s));
+    float ms = 0.f;
+    hipEventElapsedTime(&ms, e0, e1);
+    hipEventDestroy(e0);
+    hipEventDestroy(e1);
+    if (flags & DF_TIMEOUT) return MPIR_ERR_DEVICE;
+    bool nonfinite_input = false;
+    for (int c = 0; c < nrhs; ++c) {
+        const IrState &hs = hv[c];
+        if (hs.it == 0 && hs.stop == MPIR_STOP_NONFINITE) nonfinite_input = true;
+        double rnorm = hs.rnorm, xnorm = hs.xnorm;
+        if (f->tr != MPIR_F64 && hs.it > 0) {
+            // report the binary64 residual of the returned x
+            IrState h2{};
+            h2.it = 0;
+            HIPCHK(hipMemcpyAsync(f->st, &h2, sizeof(h2), hipMemcpyHostToDevice, s));
+            HIPCHK(launch_residual(n, f->A, f->lda, f->tw, MPIR_F64, B + c * ldb * es, X + c * ldx * es, f->r,
+                                   f->partial, f->nchunks, f->st, 1, s));
+            uint64_t bits[3];
+            HIPCHK(hipMemcpyAsync(bits, &f->st->rnorm_bits, 24, hipMemcpyDeviceToHost, s));
+            HIPCHK(hipStreamSynchronize(s));
+            std::memcpy(&rnorm, &bits[0], 8);
+            std::memcpy(&xnorm, &bits[2], 8);
+        }
+        if (reps) {
+            mpir_report *rep = &reps[c];
+            rep->n_iter = hs.it;
+            rep->stop = hs.stop;
+            rep->n_hist = hs.it + 1;
+            for (int k = 0; k <= hs.it && k < MPIR_HIST_MAX; ++k) rep->rhist[k] = hs.rhist[k];
+            for (int k = 0; k < hs.it && k < MPIR_HIST_MAX; ++k) rep->dhist[k] = hs.dhist[k];
+            rep->bnorm_inf = hs.bnorm;
+            rep->anorm_inf = f->anorm;
+            rep->xnorm_inf = xnorm;
+            rep->relres = hs.bnorm > 0 ? rnorm / hs.bnorm : rnorm;
+            const double den = f->anorm * xnorm + hs.bnorm;
+            rep->bwd_err = den > 0 ? rnorm / den : 0.0;
+            rep->t_ir_ms = ms;
+        }
+    }
+    return nonfinite_input ? MPIR_ERR_NONFINITE : MPIR_OK;
 }
 
 mpir_status mpir_downcast(int64_t n, const void *dA, int64_t lda, mpir_prec tw, mpir_prec tf,

@@ -121,6 +121,12 @@ template <int RD> __device__ __forceinline__ float round_lo(float x) {
 struct bf16_t { uint16_t u; };
 __device__ __forceinline__ float bf16_to_f(bf16_t v) { return __uint_as_float((uint32_t)v.u << 16); }
 
+// Fused multiply-add a*b + c, rounded once.  Written out where the same sum
+// is computed by several kernels (or instantiations) that must agree bit for
+// bit: left to the compiler, contraction depends on the surrounding code.
+__device__ __forceinline__ float fmadd(float a, float b, float c) { return __builtin_fmaf(a, b, c); }
+__device__ __forceinline__ double fmadd(double a, double b, double c) { return __builtin_fma(a, b, c); }
+
 template <typename T> __device__ __forceinline__ double to_d(T v) { return (double)v; }
 template <> __device__ __forceinline__ double to_d<__half>(__half v) { return (double)__half2float(v); }
 template <> __device__ __forceinline__ double to_d<bf16_t>(bf16_t v) { return (double)bf16_to_f(v); }
@@ -224,6 +230,11 @@ hipError_t launch_residual(int64_t n, const void *A, int64_t lda, int tw, int tr
                            const void *b, const void *x, void *r, double *partial,
                            int nchunks, IrState *st, int force, hipStream_t s);
 int residual_chunks(int64_t n);
+// The residual of nr <= 4 right-hand sides (columns b + c * ldb, x + c * ldx,
+// r + c * n; states st + c) with one pass over A; partial: nr * nch * n.
+hipError_t launch_residual_multi(int64_t n, const void *A, int64_t lda, int tw, int tr, int nr,
+                                 const void *b, int64_t ldb, const void *x, int64_t ldx, void *r,
+                                 double *partial, int nch, IrState *st, int force, hipStream_t s);
 
 // IR vector steps.
 hipError_t launch_ir_init(int64_t n, int tw, int tr, const void *b, void *x, void *r,
@@ -254,6 +265,12 @@ hipError_t launch_batched(int tw, int tf, const BatchSys *sys, const int32_t *or
 hipError_t launch_trsv(int tf, int ysol, const void *LU, int64_t n, int64_t ld, void *y, uint64_t *yw,
                        TrsvSync *ts, uint32_t *flags, const IrState *st, int force,
                        hipStream_t s);
+// The same for nr right-hand sides at once (columns y + c * ldy, c < nr <=
+// trsv_max_rhs(TS); solution words yw + c * n * 2): the factors are read once.
+int trsv_max_rhs(int ysol);
+hipError_t launch_trsv_multi(int tf, int ysol, int nr, const void *LU, int64_t n, int64_t ld, void *y,
+                             int64_t ldy, uint64_t *yw, TrsvSync *ts, uint32_t *flags, const IrState *st,
+                             int force, hipStream_t s);
 
 // GMRES-IR vector kernels (binary64; V holds basis vectors in rows of ldv).
 hipError_t launch_gather_neg(int64_t n, const double *t, const int32_t *perm, double *w,

@@ -28,7 +28,7 @@ PROF_GEMM, PROF_PANEL, PROF_TRSV, PROF_GEMV, PROF_DOWNCAST = 0, 1, 2, 3, 4
 
 EXPORTS = [
     "mpir_term_default", "mpir_factor", "mpir_refactor", "mpir_solve", "mpir_ir_solve",
-    "mpir_gmres_ir_solve",
+    "mpir_gmres_ir_solve", "mpir_ir_solve_multi",
     "mpir_ir_solve_batched", "mpir_destroy", "mpir_status_str", "mpir_downcast",
     "mpir_get_factors", "mpir_residual", "mpir_prof_enable", "mpir_prof_reset", "mpir_prof_get",
     "mpir_batch_create", "mpir_batch_run", "mpir_batch_destroy",
@@ -103,6 +103,8 @@ def lib():
         L.mpir_solve.argtypes = [vp, vp, vp]
         L.mpir_ir_solve.restype = C.c_int
         L.mpir_ir_solve.argtypes = [vp, vp, vp, P(Term), P(Report)]
+        L.mpir_ir_solve_multi.restype = C.c_int
+        L.mpir_ir_solve_multi.argtypes = [vp, i32, vp, i64, vp, i64, P(Term), P(Report)]
         L.mpir_gmres_ir_solve.restype = C.c_int
         L.mpir_gmres_ir_solve.argtypes = [vp, vp, vp, P(Term), i32, C.c_double, P(Report), P(i32)]
         L.mpir_ir_solve_batched.restype = C.c_int
@@ -238,6 +240,20 @@ class Factorization:
         _check(lib().mpir_ir_solve(self._h, _dev_ptr(b), _dev_ptr(x), tp, C.byref(rep)),
                "mpir_ir_solve")
         return x, rep
+
+    def ir_solve_multi(self, B, X=None, term_parms: Term | None = None, allow=(OK,)):
+        """Several right-hand sides: B is (nrhs, n), row c = right-hand side c
+        (column-major n x nrhs with ldb = B.stride(0)); returns (X, reports)."""
+        torch = _torch()
+        nrhs, n = B.shape
+        if n != self.n or B.stride(1) != 1:
+            raise ValueError("B must be (nrhs, n) with unit stride along n")
+        X = torch.empty_like(B) if X is None else X
+        reps = (Report * nrhs)()
+        tp = C.byref(term_parms) if term_parms is not None else None
+        _check(lib().mpir_ir_solve_multi(self._h, nrhs, _dev_ptr(B), B.stride(0), _dev_ptr(X), X.stride(0),
+                                         tp, reps), "mpir_ir_solve_multi", allow)
+        return X, list(reps)
 
     def gmres_ir_solve(self, b, x=None, term_parms: Term | None = None, basissize: int = 10,
                        gmres_tol: float = 0.0):
