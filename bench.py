@@ -136,9 +136,10 @@ def experiments(M, I, torch, dev):
           kappa in {1e4, 1e6, 1e7}, TW=TF=F32, TR=F64: forward error of IR
           against x* and against the FP64 LU solve of the same matrix, and
           of one plain FP32 LU solve;
-    (iv)  GMRES-IR (the factors as left preconditioner, basissize 10) against
-          IR with TF=F16 at N=32768, alpha in {1, 10, 799}: corrections, GMRES
-          iterations per correction, stop reason, time;
+    (iv)  GMRES-IR (the factors as left preconditioner, basissize 10) and
+          BiCGSTAB-IR (at most 10 iterations) against IR with TF=F16 at
+          N=32768, alpha in {1, 10, 799}: corrections, Krylov iterations per
+          correction, stop reason, time;
     (v)   several right-hand sides with one factorization (TF=F32, N=32768,
           nrhs in {4, 16}): refinement time of one mpir_ir_solve_multi call
           against nrhs single-column refinements."""
@@ -238,7 +239,7 @@ def experiments(M, I, torch, dev):
     for alpha in (1.0, 10.0, 799.0):
         At = I.gmat_operator_torch(n, alpha, dev)
         b = I.rhs_ones_torch(At)
-        row = {"experiment": "GMRES-IR vs IR, TF=F16", "n": n, "alpha": alpha}
+        row = {"experiment": "GMRES-IR and BiCGSTAB-IR vs IR, TF=F16", "n": n, "alpha": alpha}
         x, rep, ms = ir(At, b, M.F16, M.F64, tp)
         row["ir"] = {**rec(rep), "ms": round(ms, 3), "ferr_vs_ones": float((x - 1).abs().max())}
         xg = torch.empty_like(b)
@@ -253,6 +254,17 @@ def experiments(M, I, torch, dev):
         row["gmres_ir"] = {**rec(rep), "khist": kh, "ms": round(ms, 3),
                            "factor_ms": round(rep.t_factor_ms, 3), "refine_ms": round(rep.t_ir_ms, 3),
                            "ferr_vs_ones": float((xg - 1).abs().max())}
+
+        def go_b():
+            f = M.Factorization(At, M.F16, M.F64)
+            _, rp, kh = f.bicgstab_ir_solve(b, xg, tp)
+            f.destroy()
+            return rp, kh
+        timed(go_b)
+        (rep, kh), ms = timed(go_b)
+        row["bicgstab_ir"] = {**rec(rep), "khist": kh, "ms": round(ms, 3),
+                              "factor_ms": round(rep.t_factor_ms, 3), "refine_ms": round(rep.t_ir_ms, 3),
+                              "ferr_vs_ones": float((xg - 1).abs().max())}
         print(json.dumps(row), flush=True)
         out.append(row)
         del At, b

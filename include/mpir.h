@@ -162,6 +162,23 @@ mpir_status mpir_gmres_ir_solve(mpir_fact f, const void *db, void *dx, const mpi
                                 int32_t basissize, double gmres_tol, mpir_report *rep,
                                 int32_t *khist);
 
+/* BiCGSTAB-IR (section "Krylov-IR"; the package's mpblu): the refinement
+ * of mpir_ir_solve, each correction equation A d = r solved by BiCGSTAB
+ * preconditioned on the left with the factors, P = U^{-1} L^{-1} Pi applied
+ * in binary64 arithmetic on the TF factors (as for mpir_gmres_ir_solve).
+ * BiCGSTAB starts from d = 0 with the shadow vector P r, runs at most
+ * `maxit` iterations (1..1000; two preconditioned products each) and stops
+ * once the norm of its half-step or full-step residual is at most
+ * inner_tol * ||P r||_2 (inner_tol <= 0: 1e-13), or on a zero denominator
+ * (keeping the last iterate).  Requires TW = TR = F64 (MPIR_ERR_ARG
+ * otherwise).  khist (host, may be NULL): at least t->litmax entries, the
+ * BiCGSTAB iterations of each correction; rep as for mpir_ir_solve.  Nine
+ * binary64 n-vectors of workspace are allocated in the handle on first use
+ * and kept until mpir_destroy. */
+mpir_status mpir_bicgstab_ir_solve(mpir_fact f, const void *db, void *dx, const mpir_term *t,
+                                   int32_t maxit, double inner_tol, mpir_report *rep,
+                                   int32_t *khist);
+
 /* Batched IR for `batch` independent systems of uneven sizes
  * 1 <= n[k] <= 1024 (host array).  dA[k], db[k], dx[k]: host arrays of
  * device pointers (A column-major, lda[k] >= n[k]); same precisions for

@@ -11,6 +11,9 @@
 //   k_sub_combo   w_i -= sum_j c_j V_j[i], j increasing
 //   k_scale       out_i = w_i / s
 //   k_combo       d_i = sum_j y_j V_j[i], j increasing
+//   k_lin3        out_i = (x_i + a y_i) + b z_i (BiCGSTAB's vector updates;
+//                 out may alias any input: each thread reads its entries
+//                 before writing)
 #include "mpir_internal.h"
 
 namespace mpir {
@@ -67,6 +70,15 @@ __global__ __launch_bounds__(kKT) void k_combo(int64_t n, const double *__restri
     d[i] = x;
 }
 
+__global__ __launch_bounds__(kKT) void k_lin3(int64_t n, const double *x, double a, const double *y,
+                                              double b, const double *z, double *out) {
+    const int64_t i = (int64_t)blockIdx.x * kKT + threadIdx.x;
+    if (i >= n) return;
+    double v = x[i] + a * y[i];
+    if (z) v = v + b * z[i];
+    out[i] = v;
+}
+
 unsigned blocks(int64_t n) { return (unsigned)((n + kKT - 1) / kKT); }
 
 }  // namespace
@@ -98,6 +110,12 @@ hipError_t launch_scale(int64_t n, const double *w, double sc, double *out, hipS
 hipError_t launch_combo(int64_t n, const double *V, int64_t ldv, int nv, const double *y, double *d,
                         hipStream_t s) {
     k_combo<<<blocks(n), kKT, 0, s>>>(n, V, ldv, nv, y, d);
+    return hipGetLastError();
+}
+
+hipError_t launch_lin3(int64_t n, const double *x, double a, const double *y, double b, const double *z,
+                       double *out, hipStream_t s) {
+    k_lin3<<<blocks(n), kKT, 0, s>>>(n, x, a, y, b, z, out);
     return hipGetLastError();
 }
 

@@ -127,6 +127,10 @@ struct mpir_fact_s {
     void *mr = nullptr, *mrhat = nullptr;
     double *mpart = nullptr;
     uint64_t *myw = nullptr;
+    // BiCGSTAB-IR (first use): nine n-vectors and eight scalars, and the
+    // state the matrix-vector products report into
+    double *bq = nullptr;
+    IrState *bst = nullptr;
 };
 
 namespace {
@@ -190,6 +194,8 @@ void free_handle(mpir_fact f) {
     hipFree(f->mrhat);
     hipFree(f->mpart);
     hipFree(f->myw);
+    hipFree(f->bq);
+    hipFree(f->bst);
     delete f;
 }
 
@@ -802,6 +808,160 @@ mpir_status mpir_gmres_ir_solve(mpir_fact f, const void *db, void *dx, const mpi
         if (khist && it < term.litmax) khist[it] = kend;
         // x <- x + sigma d, the binary64 residual, the termination rules
         HIPCHK(launch_update(n, f->tw, MPIR_F64, f->kd, dx, f->st, 0, s));
+        HIPCHK(launch_residual(n, f->A, f->lda, f->tw, f->tr, db, dx, f->r, f->partial, f->nchunks,
+                               f->st, 0, s));
+        HIPCHK(launch_terminate(f->st, s));
+    }
+    HIPCHK(hipEventRecord(e1, s));
+    IrState hs;
+    uint32_t flags = 0;
+    HIPCHK(hipMemcpyAsync(&hs, f->st, sizeof(hs), hipMemcpyDeviceToHost, s));
+    HIPCHK(hipMemcpyAsync(&flags, f->flags_d, 4, hipMemcpyDeviceToHost, s));
+    HIPCHK(hipStreamSynchronize(s));
+    float ms = 0.f;
+    hipEventElapsedTime(&ms, e0, e1);
+    hipEventDestroy(e0);
+    hipEventDestroy(e1);
+    if (flags & DF_TIMEOUT) return MPIR_ERR_DEVICE;
+    if (hs.it == 0 && hs.stop == MPIR_STOP_NONFINITE) return MPIR_ERR_NONFINITE;
+    if (rep) {
+        rep->n_iter = hs.it;
+        rep->stop = hs.stop;
+        rep->n_hist = hs.it + 1;
+        for (int k = 0; k <= hs.it && k < MPIR_HIST_MAX; ++k) rep->rhist[k] = hs.rhist[k];
+        for (int k = 0; k < hs.it && k < MPIR_HIST_MAX; ++k) rep->dhist[k] = hs.dhist[k];
+        rep->bnorm_inf = hs.bnorm;
+        rep->anorm_inf = f->anorm;
+        rep->xnorm_inf = hs.xnorm;
+        rep->relres = hs.bnorm > 0 ? hs.rnorm / hs.bnorm : hs.rnorm;
+        const double den = f->anorm * hs.xnorm + hs.bnorm;
+        rep->bwd_err = den > 0 ? hs.rnorm / den : 0.0;
+        rep->t_ir_ms = ms;
+    }
+    return MPIR_OK;
+}
+
+mpir_status mpir_bicgstab_ir_solve(mpir_fact f, const void *db, void *dx, const mpir_term *t,
+                                   int32_t maxit, double inner_tol, mpir_report *rep, int32_t *khist) {
+    if (!f || !db || !dx) return MPIR_ERR_ARG;
+    if (f->tw != MPIR_F64 || f->tr != MPIR_F64) return MPIR_ERR_ARG;
+    if (maxit < 1 || maxit > 1000) return MPIR_ERR_ARG;
+    mpir_term term;
+    if (t) term = *t;
+    else mpir_term_default(&term);
+    if (term.litmax < 1 || term.litmax > MPIR_HIST_MAX - 1 || !(term.Rmax > 0.0)) return MPIR_ERR_ARG;
+    if ((term.onthefly != 0 && term.onthefly != 1) || term.reserved != 0) return MPIR_ERR_ARG;
+    const double eta = inner_tol > 0.0 ? inner_tol : 1e-13;
+    if (rep) {
+        std::memset(rep, 0, sizeof(*rep));
+        rep->info = f->info;
+        rep->t_factor_ms = f->t_factor_ms;
+    }
+    if (f->info) return MPIR_ERR_SINGULAR;
+    hipStream_t s = f->stream;
+    const int64_t n = f->n;
+    if (!f->bq) {
+        if (dalloc(&f->bq, (size_t)(9 * n + 8) * 8) != hipSuccess || dalloc(&f->bst, sizeof(IrState)) != hipSuccess)
+            return MPIR_ERR_ALLOC;
+        HIPCHK(hipMemsetAsync(f->bq, 0, (size_t)(9 * n + 8) * 8, s));
+        HIPCHK(hipMemsetAsync(f->bst, 0, sizeof(IrState), s));
+    }
+    double *vr = f->bq, *vrs = vr + n, *vp = vr + 2 * n, *vv = vr + 3 * n, *vs = vr + 4 * n, *vt = vr + 5 * n,
+           *vd = vr + 6 * n, *vtmp = vr + 7 * n, *vzero = vr + 8 * n, *sc = vr + 9 * n;
+    IrState h{};
+    h.it = -1;
+    h.anorm = f->anorm;
+    h.wilk = 0;
+    h.residterm = term.residterm ? 1 : 0;
+    h.litmax = term.litmax;
+    const double uw = std::ldexp(1.0, -52);
+    h.tol_r = term.tol_rel > 0 ? term.tol_rel : term.Cr * uw;
+    h.tol_e = term.tol_rel > 0 ? term.tol_rel : term.Ce * uw;
+    h.rmax = term.Rmax;
+    hipEvent_t e0, e1;
+    HIPCHK(hipEventCreate(&e0));
+    HIPCHK(hipEventCreate(&e1));
+    HIPCHK(hipMemcpyAsync(f->st, &h, sizeof(h), hipMemcpyHostToDevice, s));
+    HIPCHK(hipMemsetAsync(f->flags_d, 0, 4, s));
+    HIPCHK(hipEventRecord(e0, s));
+    HIPCHK(launch_ir_init(n, f->tw, f->tr, db, dx, f->r, f->st, s));
+    HIPCHK(launch_terminate(f->st, s));
+    const void *LU = factors_ptr(f);
+    // w = P A v: the residual kernel with b = 0 gives -A v, then the
+    // permutation (negated) and the binary64 substitutions on the TF factors
+    auto op = [&](const double *in, double *out) -> hipError_t {
+        hipError_t e = launch_residual(n, f->A, f->lda, MPIR_F64, MPIR_F64, vzero, in, vtmp, f->partial,
+                                       f->nchunks, f->bst, 1, s);
+        if (e == hipSuccess) e = launch_gather_neg(n, vtmp, f->perm, out, f->ts, s);
+        if (e == hipSuccess) e = launch_trsv(f->tf, MPIR_F64, LU, n, f->ld, out, f->yw, f->ts, f->flags_d, f->st, 1, s);
+        return e;
+    };
+    double hv = 0.0;
+    auto dot = [&](const double *a, const double *b, double *out) -> hipError_t {
+        hipError_t e = launch_dots(n, a, n, 1, b, sc, s);
+        if (e == hipSuccess) e = hipMemcpyAsync(&hv, sc, 8, hipMemcpyDeviceToHost, s);
+        if (e == hipSuccess) e = hipStreamSynchronize(s);
+        *out = hv;
+        return e;
+    };
+    for (int it = 0; it < term.litmax; ++it) {
+        int32_t done = 0;
+        HIPCHK(hipMemcpyAsync(&done, &f->st->done, 4, hipMemcpyDeviceToHost, s));
+        HIPCHK(hipStreamSynchronize(s));
+        if (done) break;
+        // right side P (r / sigma)
+        HIPCHK(launch_scale_permute(n, MPIR_F64, MPIR_F64, f->r, f->perm, vr, f->st, f->ts, 1, s));
+        HIPCHK(launch_trsv(f->tf, MPIR_F64, LU, n, f->ld, vr, f->yw, f->ts, f->flags_d, f->st, 1, s));
+        HIPCHK(hipMemsetAsync(vd, 0, n * 8, s));
+        double b2 = 0.0;
+        HIPCHK(dot(vr, vr, &b2));
+        const double beta0 = std::sqrt(b2);
+        int kend = 0;
+        if (beta0 > 0.0 && std::isfinite(beta0)) {
+            HIPCHK(launch_lin3(n, vr, 0.0, vr, 0.0, nullptr, vrs, s));     // shadow = P r / sigma
+            HIPCHK(hipMemsetAsync(vp, 0, n * 8, s));
+            HIPCHK(hipMemsetAsync(vv, 0, n * 8, s));
+            double rho_old = 1.0, alpha = 1.0, omega = 1.0;
+            const double tol_in = eta * beta0;
+            for (int k = 1; k <= maxit; ++k) {
+                double rho = 0.0;
+                HIPCHK(dot(vrs, vr, &rho));
+                if (rho == 0.0) { kend = k - 1; break; }
+                const double beta = (rho / rho_old) * (alpha / omega);
+                HIPCHK(launch_lin3(n, vr, beta, vp, -beta * omega, vv, vp, s));   // p = r + beta (p - omega v)
+                HIPCHK(op(vp, vv));
+                double den = 0.0;
+                HIPCHK(dot(vrs, vv, &den));
+                if (den == 0.0) { kend = k - 1; break; }
+                alpha = rho / den;
+                HIPCHK(launch_lin3(n, vr, -alpha, vv, 0.0, nullptr, vs, s));      // s = r - alpha v
+                double s2 = 0.0;
+                HIPCHK(dot(vs, vs, &s2));
+                kend = k;
+                if (std::sqrt(s2) <= tol_in) {
+                    HIPCHK(launch_lin3(n, vd, alpha, vp, 0.0, nullptr, vd, s));
+                    break;
+                }
+                HIPCHK(op(vs, vt));
+                double tt = 0.0, tsd = 0.0;
+                HIPCHK(dot(vt, vt, &tt));
+                if (tt == 0.0) {
+                    HIPCHK(launch_lin3(n, vd, alpha, vp, 0.0, nullptr, vd, s));
+                    break;
+                }
+                HIPCHK(dot(vt, vs, &tsd));
+                omega = tsd / tt;
+                HIPCHK(launch_lin3(n, vd, alpha, vp, omega, vs, vd, s));         // d += alpha p + omega s
+                HIPCHK(launch_lin3(n, vs, -omega, vt, 0.0, nullptr, vr, s));      // r = s - omega t
+                double r2 = 0.0;
+                HIPCHK(dot(vr, vr, &r2));
+                if (std::sqrt(r2) <= tol_in || omega == 0.0 || !std::isfinite(r2)) break;
+                rho_old = rho;
+            }
+        }
+        if (khist && it < term.litmax) khist[it] = kend;
+        // x <- x + sigma d, the binary64 residual, the termination rules
+        HIPCHK(launch_update(n, f->tw, MPIR_F64, vd, dx, f->st, 0, s));
         HIPCHK(launch_residual(n, f->A, f->lda, f->tw, f->tr, db, dx, f->r, f->partial, f->nchunks,
                                f->st, 0, s));
         HIPCHK(launch_terminate(f->st, s));

@@ -282,6 +282,9 @@ hipError_t launch_sub_combo(int64_t n, const double *V, int64_t ldv, int nv, con
 hipError_t launch_scale(int64_t n, const double *w, double divisor, double *out, hipStream_t s);
 hipError_t launch_combo(int64_t n, const double *V, int64_t ldv, int nv, const double *y, double *d,
                         hipStream_t s);
+// out = (x + a y) + b z (z may be NULL); out may alias the inputs.
+hipError_t launch_lin3(int64_t n, const double *x, double a, const double *y, double b, const double *z,
+                       double *out, hipStream_t s);
 
 }  // namespace mpir
 

@@ -28,7 +28,7 @@ PROF_GEMM, PROF_PANEL, PROF_TRSV, PROF_GEMV, PROF_DOWNCAST = 0, 1, 2, 3, 4
 
 EXPORTS = [
     "mpir_term_default", "mpir_factor", "mpir_refactor", "mpir_solve", "mpir_ir_solve",
-    "mpir_gmres_ir_solve", "mpir_ir_solve_multi",
+    "mpir_gmres_ir_solve", "mpir_ir_solve_multi", "mpir_bicgstab_ir_solve",
     "mpir_ir_solve_batched", "mpir_destroy", "mpir_status_str", "mpir_downcast",
     "mpir_get_factors", "mpir_residual", "mpir_prof_enable", "mpir_prof_reset", "mpir_prof_get",
     "mpir_batch_create", "mpir_batch_run", "mpir_batch_destroy",
@@ -103,6 +103,8 @@ def lib():
         L.mpir_solve.argtypes = [vp, vp, vp]
         L.mpir_ir_solve.restype = C.c_int
         L.mpir_ir_solve.argtypes = [vp, vp, vp, P(Term), P(Report)]
+        L.mpir_bicgstab_ir_solve.restype = C.c_int
+        L.mpir_bicgstab_ir_solve.argtypes = [vp, vp, vp, P(Term), i32, C.c_double, P(Report), P(i32)]
         L.mpir_ir_solve_multi.restype = C.c_int
         L.mpir_ir_solve_multi.argtypes = [vp, i32, vp, i64, vp, i64, P(Term), P(Report)]
         L.mpir_gmres_ir_solve.restype = C.c_int
@@ -255,6 +257,20 @@ class Factorization:
                                          tp, reps), "mpir_ir_solve_multi", allow)
         return X, list(reps)
 
+    def bicgstab_ir_solve(self, b, x=None, term_parms: Term | None = None, maxit: int = 10,
+                          inner_tol: float = 0.0):
+        """BiCGSTAB-IR (the package's mpblu); returns (x, report, khist)."""
+        torch = _torch()
+        x = torch.empty_like(b) if x is None else x
+        rep = Report()
+        tp = C.byref(term_parms) if term_parms is not None else None
+        litmax = term_parms.litmax if term_parms is not None else 10
+        kh = (C.c_int32 * max(litmax, 1))()
+        _check(lib().mpir_bicgstab_ir_solve(self._h, _dev_ptr(b), _dev_ptr(x), tp, int(maxit),
+                                            float(inner_tol), C.byref(rep), kh),
+               "mpir_bicgstab_ir_solve")
+        return x, rep, [int(kh[i]) for i in range(rep.n_iter)]
+
     def gmres_ir_solve(self, b, x=None, term_parms: Term | None = None, basissize: int = 10,
                        gmres_tol: float = 0.0):
         """GMRES-IR (the package's mpglu); returns (x, report, khist)."""
@@ -308,6 +324,16 @@ def gmres_ir_solve(At, b, tf: int, term_parms: Term | None = None, basissize: in
     f = Factorization(At, tf, F64, stream)
     try:
         return f.gmres_ir_solve(b, term_parms=term_parms, basissize=basissize, gmres_tol=gmres_tol)
+    finally:
+        f.destroy()
+
+
+def bicgstab_ir_solve(At, b, tf: int, term_parms: Term | None = None, maxit: int = 10,
+                      inner_tol: float = 0.0, stream=None):
+    """BiCGSTAB-IR with TW = TR = F64; returns (x, report, khist)."""
+    f = Factorization(At, tf, F64, stream)
+    try:
+        return f.bicgstab_ir_solve(b, term_parms=term_parms, maxit=maxit, inner_tol=inner_tol)
     finally:
         f.destroy()
 
