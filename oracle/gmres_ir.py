@@ -7,11 +7,9 @@ TEST INFRASTRUCTURE ONLY: the tests, the smoke check and the CPU-baseline leg
 of the benchmark are the only callers.  The library under test never imports
 this module, and this module never imports the library.
 
-What it computes, step by step, in binary64 (TW = TR = F64):
+What it computes (the outer loop, TW = F64 or F32 with TR = F64, is the
+one of ``oracle.krylov_ir``):
 
-* A_F = I_W^F(A), LU with partial pivoting in the TF mode of ``oracle.lu``.
-* x = 0, r = b, rhist = [||r||_inf]; the termination rules of Algorithm IR
-  (converged, then litmax, then stagnation ||r_k|| >= Rmax ||r_{k-1}||).
 * Each correction: GMRES on P A d = P r with P = U^{-1} L^{-1} Pi (the
   factors promoted to binary64 and the substitutions done in binary64, the
   paper's on-the-fly solve), x0 = 0, at most ``basissize`` iterations (no
@@ -19,7 +17,6 @@ What it computes, step by step, in binary64 (TW = TR = F64):
   rotations on the Hessenberg matrix; it stops when the estimated
   preconditioned residual is at most ``eta`` ||P r||_2.  The number of
   iterations goes to khist.
-* x = x + d, r = b - A x (binary64, sum in column order), histories.
 
 The paper fixes neither the orthogonalisation nor the inner tolerance; the
 readings (classical Gram-Schmidt twice; eta = 1e-13 by default, the setting
@@ -29,11 +26,9 @@ readings.
 """
 from __future__ import annotations
 
-from dataclasses import dataclass
-
 import numpy as np
 
-from oracle import oracle as O
+from oracle.krylov_ir import KrylovIRResult, krylov_ir_solve
 
 
 def givens(a: float, b: float):
@@ -96,67 +91,15 @@ def gmres(apply_op, rhs: np.ndarray, m: int, eta: float):
     return d, k_end, abs(g[k_end])
 
 
-@dataclass
-class GmresIRResult:
-    x: np.ndarray
-    n_iter: int
-    stop: int
-    rhist: np.ndarray
-    dhist: np.ndarray
-    khist: np.ndarray
-    relres: float
-    info: int
+GmresIRResult = KrylovIRResult
 
 
 def gmres_ir_solve(at: np.ndarray, b: np.ndarray, tf: int, basissize: int = 10,
                    eta: float = 1e-13, Rmax: float = 0.5, litmax: int = 10,
-                   tol_rel: float = 0.0) -> GmresIRResult:
-    """GMRES-IR on A x = b, A given in column-major storage (binary64)."""
-    at = np.ascontiguousarray(at, dtype=np.float64)
-    n = at.shape[1]
-    A = at.T
-    b = np.ascontiguousarray(b, dtype=np.float64)
-    af, _, _ = O.downcast(at, tf)
-    lu_rm, ipiv, info, _ = O.lu(af, O.default_lu_mode(tf))
-    x = np.zeros(n)
-    if info:
-        return GmresIRResult(x, 0, 0, np.array([]), np.array([]), np.array([], dtype=int),
-                             np.nan, info)
-    tol = tol_rel if tol_rel > 0 else 2.0 ** -52
-
-    def prec(v):
-        return O.lu_solve(lu_rm, ipiv, v, O.TS_F64)
-
-    def op(v):
-        return prec(A @ v)
-
-    r = b.copy()
-    bnorm = float(np.abs(b).max())
-    rh, dh, kh = [bnorm], [], []
-    stop = 0
-    if bnorm == 0.0 or bnorm <= tol * bnorm:
-        return GmresIRResult(x, 0, 0, np.array(rh), np.array(dh), np.array(kh), 0.0, 0)
-    it = 0
-    while True:
-        d, k, _ = gmres(op, prec(r), basissize, eta)
-        x = x + d
-        r = O.residual(at, b, x, O.F64)
-        it += 1
-        rn = float(np.abs(r).max())
-        rh.append(rn)
-        dh.append(float(np.abs(d).max()))
-        kh.append(k)
-        if not np.isfinite(rn):
-            stop = 4
-            break
-        if rn <= tol * bnorm:
-            stop = 0
-            break
-        if it >= litmax:
-            stop = 3
-            break
-        if rh[-1] >= Rmax * rh[-2]:
-            stop = 1
-            break
-    return GmresIRResult(x, it, stop, np.array(rh), np.array(dh), np.array(kh, dtype=int),
-                         rh[-1] / bnorm, 0)
+                   tol_rel: float = 0.0) -> KrylovIRResult:
+    """GMRES-IR on A x = b, A given in column-major storage (TW = F64 or
+    F32), TR = F64 (the outer loop of ``oracle.krylov_ir``)."""
+    def inner(op, rhs):
+        d, k, _ = gmres(op, rhs, basissize, eta)
+        return d, k
+    return krylov_ir_solve(at, b, tf, inner, Rmax=Rmax, litmax=litmax, tol_rel=tol_rel)
