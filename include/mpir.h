@@ -153,8 +153,10 @@ mpir_status mpir_ir_solve_multi(mpir_fact f, int32_t nrhs, const void *dB, int64
  * starts from d = 0, runs at most `basissize` iterations (1..64, no restart;
  * the package's default is 10), orthogonalises by classical Gram-Schmidt
  * applied twice and stops once its estimated preconditioned residual is at
- * most gmres_tol * ||P r||_2 (gmres_tol <= 0: 1e-13).  Requires TW = TR =
- * F64 (MPIR_ERR_ARG otherwise).  khist (host, may be NULL): at least
+ * most gmres_tol * ||P r||_2 (gmres_tol <= 0: 1e-13).  Requires TR = F64
+ * (MPIR_ERR_ARG otherwise); TW = F32 keeps x in binary32 (each correction
+ * rounded to binary32 before it is added) and stops by eq. wilkterm, as
+ * mpir_ir_solve does when TR is wider than TW.  khist (host, may be NULL): at least
  * t->litmax entries, the GMRES iterations of each correction; rep as for
  * mpir_ir_solve.  Krylov workspace ((basissize + 5) n binary64 numbers) is
  * allocated in the handle on first use and kept until mpir_destroy. */
@@ -170,8 +172,8 @@ mpir_status mpir_gmres_ir_solve(mpir_fact f, const void *db, void *dx, const mpi
  * `maxit` iterations (1..1000; two preconditioned products each) and stops
  * once the norm of its half-step or full-step residual is at most
  * inner_tol * ||P r||_2 (inner_tol <= 0: 1e-13), or on a zero denominator
- * (keeping the last iterate).  Requires TW = TR = F64 (MPIR_ERR_ARG
- * otherwise).  khist (host, may be NULL): at least t->litmax entries, the
+ * (keeping the last iterate).  Requires TR = F64 (MPIR_ERR_ARG
+ * otherwise); TW = F32 as for mpir_gmres_ir_solve.  khist (host, may be NULL): at least t->litmax entries, the
  * BiCGSTAB iterations of each correction; rep as for mpir_ir_solve.  Nine
  * binary64 n-vectors of workspace are allocated in the handle on first use
  * and kept until mpir_destroy. */

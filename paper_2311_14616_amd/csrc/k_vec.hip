@@ -45,9 +45,10 @@ __device__ __forceinline__ double pow2_ceil(double m) {
 // Thread per RPT consecutive rows (one 8- or 16-byte load per column covers
 // them; a wave reads 64*RPT consecutive entries of a column), 16 columns in
 // flight per thread.
-template <typename TWt, typename TRt, int RPT>
+// (TXt: the type of x, binary64 for the Krylov products with a binary32 A)
+template <typename TWt, typename TRt, int RPT, typename TXt = TWt>
 __global__ __launch_bounds__(256) void k_resid_partial(int64_t n, const TWt *__restrict__ A, int64_t lda,
-                                                       const TWt *__restrict__ x,
+                                                       const TXt *__restrict__ x,
                                                        double *__restrict__ partial,
                                                        const IrState *st, int force) {
     if (!force && st->done) return;
@@ -327,6 +328,24 @@ hipError_t launch_residual(int64_t n, const void *A, int64_t lda, int tw, int tr
     return hipGetLastError();
 }
 
+// r = b - A x with A in TW (binary64 or binary32) and b, x, r in binary64:
+// the products of the Krylov corrections.
+hipError_t launch_residual_x64(int64_t n, const void *A, int64_t lda, int tw, const double *b,
+                               const double *x, double *r, double *partial, int nch, IrState *st,
+                               hipStream_t s) {
+    if (tw == MPIR_F64)
+        return launch_residual(n, A, lda, MPIR_F64, MPIR_F64, b, x, r, partial, nch, st, 1, s);
+    if (n <= 0) return hipSuccess;
+    const bool vec = ((uintptr_t)A % 8 == 0) && (lda % 2 == 0);
+    const int rpt = vec ? 2 : 1;
+    dim3 g1((unsigned)((n + (int64_t)kRowsPerBlock * rpt - 1) / ((int64_t)kRowsPerBlock * rpt)), (unsigned)nch);
+    dim3 g2(blocks_for(n, 256)), b2(256);
+    if (vec) k_resid_partial<float, double, 2, double><<<g1, kRowsPerBlock, 0, s>>>(n, (const float *)A, lda, x, partial, st, 1);
+    else k_resid_partial<float, double, 1, double><<<g1, kRowsPerBlock, 0, s>>>(n, (const float *)A, lda, x, partial, st, 1);
+    k_resid_reduce<double, double><<<g2, b2, 0, s>>>(n, b, x, partial, nch, r, st, 1);
+    return hipGetLastError();
+}
+
 template <typename TWt, typename TRt, int NR>
 void resid_multi_go(bool vec, int64_t n, const TWt *A, int64_t lda, const TWt *x, int64_t ldx,
                     double *partial, int nch, hipStream_t s) {
@@ -404,7 +423,8 @@ hipError_t launch_scale_permute(int64_t n, int tr, int tf, const void *r, const 
 hipError_t launch_update(int64_t n, int tw, int tf, const void *y, void *x, IrState *st, int force,
                          hipStream_t s) {
     dim3 g(blocks_for(n, 256)), bl(256);
-    if (tf == MPIR_F64) k_update<double, double><<<g, bl, 0, s>>>(n, (const double *)y, (double *)x, st, force);
+    if (tf == MPIR_F64 && tw == MPIR_F64) k_update<double, double><<<g, bl, 0, s>>>(n, (const double *)y, (double *)x, st, force);
+    else if (tf == MPIR_F64) k_update<float, double><<<g, bl, 0, s>>>(n, (const double *)y, (float *)x, st, force);
     else if (tw == MPIR_F64) k_update<double, float><<<g, bl, 0, s>>>(n, (const float *)y, (double *)x, st, force);
     else k_update<float, float><<<g, bl, 0, s>>>(n, (const float *)y, (float *)x, st, force);
     return hipGetLastError();

@@ -677,7 +677,7 @@ mpir_status mpir_gmres_ir_solve(mpir_fact f, const void *db, void *dx, const mpi
                                 int32_t basissize, double gmres_tol, mpir_report *rep,
                                 int32_t *khist) {
     if (!f || !db || !dx) return MPIR_ERR_ARG;
-    if (f->tw != MPIR_F64 || f->tr != MPIR_F64) return MPIR_ERR_ARG;
+    if (f->tr != MPIR_F64) return MPIR_ERR_ARG;         // TW = F64, or F32 with TR > TW
     if (basissize < 1 || basissize > kGmresMaxBasis) return MPIR_ERR_ARG;
     mpir_term term;
     if (t) term = *t;
@@ -717,10 +717,10 @@ mpir_status mpir_gmres_ir_solve(mpir_fact f, const void *db, void *dx, const mpi
     IrState h{};
     h.it = -1;
     h.anorm = f->anorm;
-    h.wilk = 0;
+    h.wilk = f->tw != MPIR_F64 ? 1 : 0;                  // TR wider than TW: eq. wilkterm
     h.residterm = term.residterm ? 1 : 0;
     h.litmax = term.litmax;
-    const double uw = std::ldexp(1.0, -52);
+    const double uw = f->tw == MPIR_F64 ? std::ldexp(1.0, -52) : std::ldexp(1.0, -23);
     h.tol_r = term.tol_rel > 0 ? term.tol_rel : term.Cr * uw;
     h.tol_e = term.tol_rel > 0 ? term.tol_rel : term.Ce * uw;
     h.rmax = term.Rmax;
@@ -759,8 +759,8 @@ mpir_status mpir_gmres_ir_solve(mpir_fact f, const void *db, void *dx, const mpi
             for (int k = 0; k < m; ++k) {
                 const double *vk = V + (size_t)k * n;
                 // w = P A v_k (the residual kernel with b = 0 gives -A v_k)
-                HIPCHK(launch_residual(n, f->A, f->lda, MPIR_F64, MPIR_F64, f->kzero, vk, f->kt, f->partial,
-                                       f->nchunks, f->kst, 1, s));
+                HIPCHK(launch_residual_x64(n, f->A, f->lda, f->tw, f->kzero, vk, f->kt, f->partial,
+                                           f->nchunks, f->kst, s));
                 HIPCHK(launch_gather_neg(n, f->kt, f->perm, w, f->ts, s));
                 HIPCHK(launch_trsv(f->tf, MPIR_F64, LU, n, lld, w, f->yw, f->ts, f->flags_d, f->st, 1, s));
                 // classical Gram-Schmidt, twice, then ||w||_2
@@ -844,7 +844,7 @@ mpir_status mpir_gmres_ir_solve(mpir_fact f, const void *db, void *dx, const mpi
 mpir_status mpir_bicgstab_ir_solve(mpir_fact f, const void *db, void *dx, const mpir_term *t,
                                    int32_t maxit, double inner_tol, mpir_report *rep, int32_t *khist) {
     if (!f || !db || !dx) return MPIR_ERR_ARG;
-    if (f->tw != MPIR_F64 || f->tr != MPIR_F64) return MPIR_ERR_ARG;
+    if (f->tr != MPIR_F64) return MPIR_ERR_ARG;         // TW = F64, or F32 with TR > TW
     if (maxit < 1 || maxit > 1000) return MPIR_ERR_ARG;
     mpir_term term;
     if (t) term = *t;
@@ -871,10 +871,10 @@ mpir_status mpir_bicgstab_ir_solve(mpir_fact f, const void *db, void *dx, const 
     IrState h{};
     h.it = -1;
     h.anorm = f->anorm;
-    h.wilk = 0;
+    h.wilk = f->tw != MPIR_F64 ? 1 : 0;                  // TR wider than TW: eq. wilkterm
     h.residterm = term.residterm ? 1 : 0;
     h.litmax = term.litmax;
-    const double uw = std::ldexp(1.0, -52);
+    const double uw = f->tw == MPIR_F64 ? std::ldexp(1.0, -52) : std::ldexp(1.0, -23);
     h.tol_r = term.tol_rel > 0 ? term.tol_rel : term.Cr * uw;
     h.tol_e = term.tol_rel > 0 ? term.tol_rel : term.Ce * uw;
     h.rmax = term.Rmax;
@@ -890,8 +890,8 @@ mpir_status mpir_bicgstab_ir_solve(mpir_fact f, const void *db, void *dx, const 
     // w = P A v: the residual kernel with b = 0 gives -A v, then the
     // permutation (negated) and the binary64 substitutions on the TF factors
     auto op = [&](const double *in, double *out) -> hipError_t {
-        hipError_t e = launch_residual(n, f->A, f->lda, MPIR_F64, MPIR_F64, vzero, in, vtmp, f->partial,
-                                       f->nchunks, f->bst, 1, s);
+        hipError_t e = launch_residual_x64(n, f->A, f->lda, f->tw, vzero, in, vtmp, f->partial,
+                                           f->nchunks, f->bst, s);
         if (e == hipSuccess) e = launch_gather_neg(n, vtmp, f->perm, out, f->ts, s);
         if (e == hipSuccess) e = launch_trsv(f->tf, MPIR_F64, LU, n, f->ld, out, f->yw, f->ts, f->flags_d, f->st, 1, s);
         return e;

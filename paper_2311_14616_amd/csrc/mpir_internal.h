@@ -230,6 +230,10 @@ hipError_t launch_residual(int64_t n, const void *A, int64_t lda, int tw, int tr
                            const void *b, const void *x, void *r, double *partial,
                            int nchunks, IrState *st, int force, hipStream_t s);
 int residual_chunks(int64_t n);
+// r = b - A x with A in TW and b, x, r in binary64 (force = 1).
+hipError_t launch_residual_x64(int64_t n, const void *A, int64_t lda, int tw, const double *b,
+                               const double *x, double *r, double *partial, int nch, IrState *st,
+                               hipStream_t s);
 // The residual of nr <= 4 right-hand sides (columns b + c * ldb, x + c * ldx,
 // r + c * n; states st + c) with one pass over A; partial: nr * nch * n.
 hipError_t launch_residual_multi(int64_t n, const void *A, int64_t lda, int tw, int tr, int nr,

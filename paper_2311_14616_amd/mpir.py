@@ -320,7 +320,7 @@ def ir_solve(At, b, tf: int, tr: int | None = None, term_parms: Term | None = No
 
 def gmres_ir_solve(At, b, tf: int, term_parms: Term | None = None, basissize: int = 10,
                    gmres_tol: float = 0.0, stream=None):
-    """GMRES-IR with TW = TR = F64; returns (x, report, khist)."""
+    """GMRES-IR with TR = F64 (TW from At's dtype); returns (x, report, khist)."""
     f = Factorization(At, tf, F64, stream)
     try:
         return f.gmres_ir_solve(b, term_parms=term_parms, basissize=basissize, gmres_tol=gmres_tol)
@@ -330,7 +330,7 @@ def gmres_ir_solve(At, b, tf: int, term_parms: Term | None = None, basissize: in
 
 def bicgstab_ir_solve(At, b, tf: int, term_parms: Term | None = None, maxit: int = 10,
                       inner_tol: float = 0.0, stream=None):
-    """BiCGSTAB-IR with TW = TR = F64; returns (x, report, khist)."""
+    """BiCGSTAB-IR with TR = F64 (TW from At's dtype); returns (x, report, khist)."""
     f = Factorization(At, tf, F64, stream)
     try:
         return f.bicgstab_ir_solve(b, term_parms=term_parms, maxit=maxit, inner_tol=inner_tol)

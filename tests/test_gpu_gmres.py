@@ -165,7 +165,8 @@ def test_gmres_ir_argument_errors(M):
                 f.gmres_ir_solve(dev(b), basissize=m)
     finally:
         f.destroy()
-    f = M.Factorization(dev(at.astype(np.float32)), M.F16, M.F64)
+    # TR must be F64
+    f = M.Factorization(dev(at.astype(np.float32)), M.F16, M.F32)
     try:
         with pytest.raises(M.MpirError):
             f.gmres_ir_solve(dev(b.astype(np.float32)))
@@ -190,3 +191,70 @@ def test_gmres_ir_full_size(M):
         r -= At[c0:c0 + 4096].t().matmul(x[c0:c0 + 4096])
     assert float(r.abs().max()) / float(b.abs().max()) <= 2e-14
     assert float((x - 1.0).abs().max()) <= 1e-11
+
+
+TW32_CASES = [("gmres", 700, 10.0, "f16"), ("gmres", 1100, 799.0, "f16"), ("gmres", 600, 100.0, "bf16"),
+              ("bicgstab", 700, 10.0, "f16"), ("bicgstab", 1100, 799.0, "f16")]
+
+
+@pytest.mark.parametrize("method,n,alpha,tf", TW32_CASES)
+def test_krylov_ir_tw32_parity(M, orc, method, n, alpha, tf):
+    """TW = F32, TR = F64: x kept in binary32, stop by eq. wilkterm.  Bars:
+    the same stop and first residual, outer counts and the first correction's
+    Krylov count within +-1, the final residual within a factor 3 of the
+    oracle's (both at the binary32 floor), x within two binary32 ulps."""
+    from oracle import bicgstab_ir, gmres_ir
+    say(f"krylov tw=f32 {method} n={n} alpha={alpha} tf={tf}")
+    T = {"f16": M.F16, "bf16": M.BF16}[tf]
+    at = I.gmat_operator(n, alpha).astype(np.float32)
+    b = (at.T.astype(np.float64) @ np.ones(n)).astype(np.float32)
+    tp = M.term(litmax=10)
+    f = M.Factorization(dev(at), T, M.F64)
+    try:
+        if method == "gmres":
+            x, rep, kh = f.gmres_ir_solve(dev(b), term_parms=tp)
+            ref = gmres_ir.gmres_ir_solve(at, b, T, litmax=10)
+        else:
+            x, rep, kh = f.bicgstab_ir_solve(dev(b), term_parms=tp)
+            ref = bicgstab_ir.bicgstab_ir_solve(at, b, T, litmax=10)
+    finally:
+        f.destroy()
+    say(f"  gpu n_iter={rep.n_iter} stop={rep.stop} khist={kh} rfinal={rep.rhist[rep.n_iter]:.2e} | "
+        f"oracle n_iter={ref.n_iter} stop={ref.stop} khist={[int(k) for k in ref.khist]} rfinal={ref.rhist[-1]:.2e}")
+    assert x.dtype == torch.float32
+    assert rep.stop == ref.stop and rep.rhist[0] == ref.rhist[0]
+    assert abs(rep.n_iter - ref.n_iter) <= 1 and abs(kh[0] - ref.khist[0]) <= 1
+    assert 1 / 3 <= rep.rhist[rep.n_iter] / ref.rhist[-1] <= 3
+    xg = x.cpu().numpy()
+    assert np.abs(xg - ref.x).max() <= 2 * 2.0**-23 * np.abs(ref.x).max()
+
+
+def test_printed_krylov_sessions_tw32(M, orc):
+    """The printed IR-GMRES (basis 20) and IR-BiCGSTAB sessions (N = 4096,
+    A = Float32(I - 799 Gmat) on the endpoint grid, binary16 factors,
+    TR = F64) on the GPU: the final residual at the printed binary32 floor
+    and the printed distance to the solution of the promoted problem."""
+    import json
+    import os
+    g = json.load(open(os.path.join(os.path.dirname(__file__), "golden", "paper_examples.json")))["E_krylov_tw32"]
+    n, alpha = g["n"], g["alpha"]
+    say(f"printed krylov sessions tw=f32 n={n}")
+    ad = I.gmat_operator(n, alpha, grid="endpoint")
+    h = 1.0 / (n - 1)
+    xs = np.arange(n) * h
+    a32 = ad.astype(np.float32)
+    b32 = (1.0 - alpha * xs * (1.0 - xs) * 0.5).astype(np.float32)
+    xp, info, _ = orc.solve_f64(a32, b32)
+    f = M.Factorization(dev(a32), M.F16, M.F64)
+    try:
+        xg, rg, khg = f.gmres_ir_solve(dev(b32), term_parms=M.term(litmax=10), basissize=g["gmres_basissize"])
+        xb, rb, khb = f.bicgstab_ir_solve(dev(b32), term_parms=M.term(litmax=10))
+    finally:
+        f.destroy()
+    for x, rep, key in ((xg, rg, "gmres_rhist"), (xb, rb, "bicgstab_rhist")):
+        say(f"  {key}: n_iter={rep.n_iter} stop={rep.stop_name} rfinal={rep.rhist[rep.n_iter]:.5e} "
+            f"(printed {g[key][-1]:.5e}) |x - xp| = {np.abs(x.cpu().numpy() - xp).max():.5e}")
+        assert rep.stop_name == "dstagnated"
+        assert rep.rhist[0] == pytest.approx(g[key][0], rel=1e-5)
+        assert 1 / 1.5 <= rep.rhist[rep.n_iter] / g[key][-1] <= 1.5
+        assert np.abs(x.cpu().numpy() - xp).max() == pytest.approx(g["gmres_sol_minus_promoted_inf"], rel=0.01)
