@@ -251,6 +251,8 @@ class Factorization:
         if n != self.n or B.stride(1) != 1:
             raise ValueError("B must be (nrhs, n) with unit stride along n")
         X = torch.empty_like(B) if X is None else X
+        if tuple(X.shape) != (nrhs, n) or X.stride(1) != 1 or X.dtype != B.dtype:
+            raise ValueError("X must be (nrhs, n) of B's dtype with unit stride along n")
         reps = (Report * nrhs)()
         tp = C.byref(term_parms) if term_parms is not None else None
         _check(lib().mpir_ir_solve_multi(self._h, nrhs, _dev_ptr(B), B.stride(0), _dev_ptr(X), X.stride(0),
