@@ -65,6 +65,9 @@ def test_argument_validation_needs_no_device(M):
     assert h.value in (None, 0) and info.value == 0
     assert L.mpir_solve(None, dummy, dummy) == M.ERR_ARG
     assert L.mpir_ir_solve(None, dummy, dummy, None, None) == M.ERR_ARG
+    assert L.mpir_gmres_ir_solve(None, dummy, dummy, None, 10, 0.0, None, None) == M.ERR_ARG
+    assert L.mpir_bicgstab_ir_solve(None, dummy, dummy, None, 10, 0.0, None, None) == M.ERR_ARG
+    assert L.mpir_ir_solve_multi(None, 2, dummy, 8, dummy, 8, None, None) == M.ERR_ARG
     assert L.mpir_refactor(None, dummy, 8, None) == M.ERR_ARG
     assert L.mpir_get_factors(None, dummy, None) == M.ERR_ARG
     assert L.mpir_prof_get(99, None, None, None) == M.ERR_ARG

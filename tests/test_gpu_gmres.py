@@ -258,3 +258,21 @@ def test_printed_krylov_sessions_tw32(M, orc):
         assert rep.rhist[0] == pytest.approx(g[key][0], rel=1e-5)
         assert 1 / 1.5 <= rep.rhist[rep.n_iter] / g[key][-1] <= 1.5
         assert np.abs(x.cpu().numpy() - xp).max() == pytest.approx(g["gmres_sol_minus_promoted_inf"], rel=0.01)
+
+
+@pytest.mark.parametrize("method,limit", [("gmres", 1), ("gmres", 64), ("bicgstab", 1), ("bicgstab", 1000)])
+def test_krylov_limits(M, method, limit):
+    """The smallest and largest basis / iteration limit: every correction
+    within the limit, the 1e-14 rule met (a one-step basis is IR with a
+    minimal-residual step length)."""
+    say(f"krylov limits {method} {limit}")
+    at = I.gmat_operator(700, 10.0)
+    b = I.rhs_ones(at)
+    tp = M.term(tol_rel=1e-14, litmax=30)
+    if method == "gmres":
+        _, rep, kh = M.gmres_ir_solve(dev(at), dev(b), M.F16, term_parms=tp, basissize=limit)
+    else:
+        _, rep, kh = M.bicgstab_ir_solve(dev(at), dev(b), M.F16, term_parms=tp, maxit=limit)
+    say(f"  n_iter={rep.n_iter} khist={kh} relres={rep.relres:.2e}")
+    assert rep.stop_name == "converged" and rep.relres <= 1e-14
+    assert all(1 <= k <= limit for k in kh)
