@@ -168,7 +168,40 @@ __global__ __launch_bounds__(256) void k_trsv(const Ft *__restrict__ LU, int64_t
     int rsel[16];
 #pragma unroll
     for (int r = 0; r < 16; ++r) rsel[r] = wvs * 16 + r < rows ? wvs * 16 + r : rows - 1;
-    for (int q = 0; q < t - 1 && !timed_out; ++q) {
+    // binary32 solves of one right-hand side take two dependency blocks per
+    // step (both blocks' loads in flight together), so a workgroup that lags
+    // behind the chain catches up faster; the operations and their order
+    // are those of one block at a time
+    int q = 0;
+    if constexpr (sizeof(Yt) == 4 && NR == 1) {
+        for (; q + 1 < t - 1 && !timed_out; q += 2) {
+            const int cb0 = LOWER ? q : nblk - 1 - q;
+            const int cb1 = LOWER ? q + 1 : nblk - 2 - q;
+            const int64_t col0 = (int64_t)cb0 * BS + lane, col1 = (int64_t)cb1 * BS + lane;
+            const bool cv0 = col0 < n, cv1 = col1 < n;
+            const int64_t cc0 = cv0 ? col0 : n - 1, cc1 = cv1 ? col1 : n - 1;
+            Ft lv0[16], lv1[16];
+#pragma unroll
+            for (int r = 0; r < 16; ++r) {
+                lv0[r] = base[(int64_t)rsel[r] * ld + cc0];
+                lv1[r] = base[(int64_t)rsel[r] * ld + cc1];
+            }
+            Yt y0[1], y1[1];
+            get_ys<Yt, 1>(yw, ystride, col0, cv0, epoch, timed_out, y0);
+            get_ys<Yt, 1>(yw, ystride, col1, cv1, epoch, timed_out, y1);
+#pragma unroll
+            for (int r = 0; r < 16; ++r) {
+                const Yt lvr = cv0 ? (Yt)to_d(lv0[r]) : (Yt)0;
+                acc[0][r] = fmadd(lvr, y0[0], acc[0][r]);
+            }
+#pragma unroll
+            for (int r = 0; r < 16; ++r) {
+                const Yt lvr = cv1 ? (Yt)to_d(lv1[r]) : (Yt)0;
+                acc[0][r] = fmadd(lvr, y1[0], acc[0][r]);
+            }
+        }
+    }
+    for (; q < t - 1 && !timed_out; ++q) {
         const int cb = LOWER ? q : nblk - 1 - q;
         const int64_t col = (int64_t)cb * BS + lane;
         const bool cv = col < n;
