@@ -16,8 +16,7 @@
  *  - Precisions: TW in {F64, F32}; TF in {F32, F16, BF16} below TW, or
  *    TF == TW; TR in {TW, F64} (section "Evaluating the residual in extended
  *    precision").  BF16 is the 16-bit format of section "Half Precision"
- *    (binary32 exponent range, 8-bit significand); the batched entry points
- *    take TF in {F32, F16} only.
+ *    (binary32 exponent range, 8-bit significand).
  *  - Every call is ordered on the HIP stream given to mpir_factor (a
  *    hipStream_t passed as void*, NULL = the default stream) and returns
  *    only when its results are in place (it synchronises that stream).
@@ -184,7 +183,7 @@ mpir_status mpir_bicgstab_ir_solve(mpir_fact f, const void *db, void *dx, const 
 /* Batched IR for `batch` independent systems of uneven sizes
  * 1 <= n[k] <= 1024 (host array).  dA[k], db[k], dx[k]: host arrays of
  * device pointers (A column-major, lda[k] >= n[k]); same precisions for
- * every system: TW in {F64, F32}, TF in {F32, F16}, TR = F64 (TW = F32 means
+ * every system: TW in {F64, F32}, TF in {F32, F16, BF16}, TR = F64 (TW = F32 means
  * TR wider than TW: eq. wilkterm).  Every system is factored and refined on
  * the device in one persistent launch (workgroups take the systems from a
  * queue, largest first).  reps: host array of `batch` reports (may be NULL);
@@ -236,7 +235,7 @@ typedef struct {
     double ms[MPIR_TUNE_CLASSES];
 } mpir_batch_tuning;
 
-/* The current table for (tw, tf) (TW in {F64, F32}, TF in {F32, F16}). */
+/* The current table for (tw, tf) (TW in {F64, F32}, TF in {F32, F16, BF16}). */
 mpir_status mpir_batch_get_tuning(mpir_prec tw, mpir_prec tf, mpir_batch_tuning *t);
 /* Replace it (t = NULL restores the built-in defaults); MPIR_ERR_ARG if a
  * field is out of range.  Touches no device. */

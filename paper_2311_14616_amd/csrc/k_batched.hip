@@ -8,7 +8,8 @@
 // update, FP64 residual, the termination rules) and a per-system report.
 //
 // Storage per system: the caller's A (column-major, TW), b and x (TW); a
-// row-major binary32 working array W (n x n; binary16 numbers for TF = F16)
+// row-major binary32 working array W (n x n; binary16 / bfloat16 numbers for
+// TF = F16 / BF16)
 // and the row permutation, both in a workspace owned by the library.
 #include "mpir_internal.h"
 
@@ -33,6 +34,24 @@ namespace {
 
 typedef float floatx16 __attribute__((ext_vector_type(16)));
 typedef _Float16 half8 __attribute__((ext_vector_type(8)));
+typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
+
+// The 16-bit operand type of the factorization's rounding RD (1 binary16,
+// 2 bfloat16), its 8-element vector and the 32x32x16 MFMA on it.
+template <int RD> struct Lo16 {
+    using T = _Float16;
+    using V8 = half8;
+    __device__ static floatx16 mfma(V8 a, V8 b, floatx16 c) {
+        return __builtin_amdgcn_mfma_f32_32x32x16_f16(a, b, c, 0, 0, 0);
+    }
+};
+template <> struct Lo16<2> {
+    using T = __bf16;
+    using V8 = bf16x8;
+    __device__ static floatx16 mfma(V8 a, V8 b, floatx16 c) {
+        return __builtin_amdgcn_mfma_f32_32x32x16_bf16(a, b, c, 0, 0, 0);
+    }
+};
 
 constexpr int NT = 512;             // threads per workgroup
 constexpr int NW = NT / 64;         // waves
@@ -114,7 +133,7 @@ __device__ __forceinline__ double block_max(double v, uint64_t *red) {
     return __longlong_as_double((long long)m);
 }
 
-template <typename TWt, bool F16>
+template <typename TWt, int RD>
 __global__ __launch_bounds__(NT) void k_batched(const BatchSys *__restrict__ sys,
                                                 const int32_t *__restrict__ order, int nsys,
                                                 uint32_t *queue, BatchTerm term,
@@ -202,7 +221,7 @@ __global__ __launch_bounds__(NT) void k_batched(const BatchSys *__restrict__ sys
                     const int i = i0 + r, j = j0 + c;
                     if (i < n && j < n) {
                         const double v = tile[c * TP + r];
-                        const float f = F16 ? d2h_as_float(v) : (float)v;
+                        const float f = RD == 1 ? d2h_as_float(v) : RD == 2 ? d2bf_as_float(v) : (float)v;
                         if (!isfinite(v)) fl |= DF_NONFINITE;
                         else if (isinf(f)) fl |= DF_RANGE;
                         W[(int64_t)i * n + j] = f;
@@ -266,7 +285,7 @@ __global__ __launch_bounds__(NT) void k_batched(const BatchSys *__restrict__ sys
                     const float t = panel[j * PP + c];
                     float pv = panel[p * PP + c];
                     if (p != j) panel[p * PP + c] = t;
-                    if (F16 && c >= j) pv = round_f16(pv);
+                    if (RD && c >= j) pv = round_lo<RD>(pv);
                     panel[j * PP + c] = pv;
                 }
                 __syncthreads();
@@ -276,7 +295,7 @@ __global__ __launch_bounds__(NT) void k_batched(const BatchSys *__restrict__ sys
                 for (int r = j + 1 + tid; r < m; r += NT) {
                     if (pj != 0.0f) {
                         float l = panel[r * PP + j] / pj;
-                        if (F16) l = round_f16(l);
+                        if (RD) l = round_lo<RD>(l);
                         panel[r * PP + j] = l;
                         for (int c = j + 1; c < w; ++c) {
                             const float prod = l * panel[j * PP + c];
@@ -371,7 +390,7 @@ __global__ __launch_bounds__(NT) void k_batched(const BatchSys *__restrict__ sys
                     }
                     for (int t = 0; t < w; ++t) {
                         float xt = xs[t * NT];
-                        if (F16) { xt = round_f16(xt); xs[t * NT] = xt; }
+                        if (RD) { xt = round_lo<RD>(xt); xs[t * NT] = xt; }
                         for (int s2 = t + 1; s2 < w; ++s2) {
                             const float prod = L11[s2][t] * xt;
                             xs[s2 * NT] = xs[s2 * NT] - prod;
@@ -397,14 +416,15 @@ __global__ __launch_bounds__(NT) void k_batched(const BatchSys *__restrict__ sys
                 __syncthreads();
                 for (int bj = wv; bj < nbk; bj += NW) {
                     const int cb = r0 + bj * 32, bc = cb + (lane & 31);
-                    if (F16) {
-                        half8 bh[2];
+                    if constexpr (RD != 0) {
+                        using L16 = Lo16<RD>;
+                        typename L16::V8 bh[2];
 #pragma unroll
                         for (int s2 = 0; s2 < 2; ++s2)
 #pragma unroll
                             for (int q = 0; q < 8; ++q) {
                                 const int kq = 16 * s2 + 8 * (lane >> 5) + q;
-                                bh[s2][q] = (_Float16)((bc < n && kq < w) ? W[(int64_t)(k + kq) * n + bc] : 0.0f);
+                                bh[s2][q] = (typename L16::T)((bc < n && kq < w) ? W[(int64_t)(k + kq) * n + bc] : 0.0f);
                             }
                         // C of the next block row is loaded while this one
                         // is multiplied and stored
@@ -417,13 +437,13 @@ __global__ __launch_bounds__(NT) void k_batched(const BatchSys *__restrict__ sys
                             // entries beyond w are zero in both operands
 #pragma unroll
                             for (int s2 = 0; s2 < 2; ++s2) {
-                                half8 av;
+                                typename L16::V8 av;
 #pragma unroll
                                 for (int q = 0; q < 8; ++q) {
                                     const float pv = panel[lr * PP + 16 * s2 + 8 * (lane >> 5) + q];
-                                    av[q] = (_Float16)(lr < mm ? pv : 0.0f);
+                                    av[q] = (typename L16::T)(lr < mm ? pv : 0.0f);
                                 }
-                                acc = __builtin_amdgcn_mfma_f32_32x32x16_f16(av, bh[s2], acc, 0, 0, 0);
+                                acc = L16::mfma(av, bh[s2], acc);
                             }
                             store_cblock(W, n, rb, bc, lane, cv, acc);
 #pragma unroll
@@ -467,8 +487,9 @@ __global__ __launch_bounds__(NT) void k_batched(const BatchSys *__restrict__ sys
                     // the products
                     float cv[16];
                     floatx16 acc = floatx16{0};
-                    if (F16) {
-                        half8 av[2], bvv[2];
+                    if constexpr (RD != 0) {
+                        using L16 = Lo16<RD>;
+                        typename L16::V8 av[2], bvv[2];
 #pragma unroll
                         for (int s2 = 0; s2 < 2; ++s2)
 #pragma unroll
@@ -477,13 +498,13 @@ __global__ __launch_bounds__(NT) void k_batched(const BatchSys *__restrict__ sys
                                 const bool oka = ar < n && kq < w, okb = bc < n && kq < w;
                                 const float xa = W[(int64_t)(oka ? ar : 0) * n + k + (oka ? kq : 0)];
                                 const float xb = W[(int64_t)(k + (okb ? kq : 0)) * n + (okb ? bc : 0)];
-                                av[s2][q] = (_Float16)(oka ? xa : 0.0f);
-                                bvv[s2][q] = (_Float16)(okb ? xb : 0.0f);
+                                av[s2][q] = (typename L16::T)(oka ? xa : 0.0f);
+                                bvv[s2][q] = (typename L16::T)(okb ? xb : 0.0f);
                             }
                         load_cblock(W, n, rb, bc, lane, true, cv);
 #pragma unroll
                         for (int s2 = 0; s2 < 2; ++s2)
-                            acc = __builtin_amdgcn_mfma_f32_32x32x16_f16(av[s2], bvv[s2], acc, 0, 0, 0);
+                            acc = L16::mfma(av[s2], bvv[s2], acc);
                     } else {
                         float av[16], bvv[16];
 #pragma unroll
@@ -540,7 +561,7 @@ __global__ __launch_bounds__(NT) void k_batched(const BatchSys *__restrict__ sys
                 const double inv = 1.0 / sigma;
                 for (int i = tid; i < n; i += NT) {
                     const double v = vr[perm[i]] * inv;
-                    vy[i] = F16 ? d2h_as_float(v) : (float)v;
+                    vy[i] = RD == 1 ? d2h_as_float(v) : RD == 2 ? d2bf_as_float(v) : (float)v;
                 }
                 __syncthreads();
                 // forward substitution with unit L, 64-row blocks
@@ -746,11 +767,13 @@ hipError_t launch_batched(int tw, int tf, const BatchSys *sys, const int32_t *or
             tick_ms = 0.0;
     }
     if (tw == MPIR_F64) {
-        if (tf == MPIR_F16) k_batched<double, true><<<nwg, NT, 0, s>>>(sys, order, nsys, queue, term, reps, tick_ms);
-        else k_batched<double, false><<<nwg, NT, 0, s>>>(sys, order, nsys, queue, term, reps, tick_ms);
+        if (tf == MPIR_F16) k_batched<double, 1><<<nwg, NT, 0, s>>>(sys, order, nsys, queue, term, reps, tick_ms);
+        else if (tf == MPIR_BF16) k_batched<double, 2><<<nwg, NT, 0, s>>>(sys, order, nsys, queue, term, reps, tick_ms);
+        else k_batched<double, 0><<<nwg, NT, 0, s>>>(sys, order, nsys, queue, term, reps, tick_ms);
     } else {
-        if (tf == MPIR_F16) k_batched<float, true><<<nwg, NT, 0, s>>>(sys, order, nsys, queue, term, reps, tick_ms);
-        else k_batched<float, false><<<nwg, NT, 0, s>>>(sys, order, nsys, queue, term, reps, tick_ms);
+        if (tf == MPIR_F16) k_batched<float, 1><<<nwg, NT, 0, s>>>(sys, order, nsys, queue, term, reps, tick_ms);
+        else if (tf == MPIR_BF16) k_batched<float, 2><<<nwg, NT, 0, s>>>(sys, order, nsys, queue, term, reps, tick_ms);
+        else k_batched<float, 0><<<nwg, NT, 0, s>>>(sys, order, nsys, queue, term, reps, tick_ms);
     }
     return hipGetLastError();
 }

@@ -1294,7 +1294,8 @@ mpir_status batch_create_with(int32_t batch, const int64_t *n, const void *const
                               mpir_batch *out) {
     if (out) *out = nullptr;
     if (!out || batch <= 0 || !n || !dA || !lda || !db || !dx) return MPIR_ERR_ARG;
-    if (!(tw == MPIR_F64 || tw == MPIR_F32) || !(tf == MPIR_F32 || tf == MPIR_F16) || tr != MPIR_F64)
+    if (!(tw == MPIR_F64 || tw == MPIR_F32) || !(tf == MPIR_F32 || tf == MPIR_F16 || tf == MPIR_BF16) ||
+        tr != MPIR_F64)
         return MPIR_ERR_ARG;
     if (tw == MPIR_F32 && tf == MPIR_F32) {
         // TF = TW = F32 with TR = F64 (eq. wilkterm) is allowed

@@ -16,7 +16,7 @@ using namespace mpir;
 namespace {
 
 std::mutex g_tune_mu;
-mpir_batch_tuning g_tune[2][2];   // [tw == F32][tf == F16]
+mpir_batch_tuning g_tune[2][3];   // [tw == F32][tf: F32, F16, BF16]
 bool g_tune_init = false;
 
 void tune_defaults(mpir_batch_tuning *t) {
@@ -31,7 +31,7 @@ void tune_defaults(mpir_batch_tuning *t) {
 }
 
 bool prec_ok(int tw, int tf) {
-    return (tw == MPIR_F64 || tw == MPIR_F32) && (tf == MPIR_F32 || tf == MPIR_F16);
+    return (tw == MPIR_F64 || tw == MPIR_F32) && (tf == MPIR_F32 || tf == MPIR_F16 || tf == MPIR_BF16);
 }
 
 mpir_batch_tuning &slot(int tw, int tf) {
@@ -40,7 +40,7 @@ mpir_batch_tuning &slot(int tw, int tf) {
             for (auto &b : a) tune_defaults(&b);
         g_tune_init = true;
     }
-    return g_tune[tw == MPIR_F32][tf == MPIR_F16];
+    return g_tune[tw == MPIR_F32][tf == MPIR_F32 ? 0 : tf == MPIR_F16 ? 1 : 2];
 }
 
 bool tuning_valid(const mpir_batch_tuning *t) {

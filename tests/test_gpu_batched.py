@@ -61,10 +61,10 @@ CONFIGS = [(None, None), (16, 0), (16, 1), (32, 0), (32, 1)]
 
 
 @pytest.mark.parametrize("cfg", CONFIGS, ids=lambda c: "default" if c[0] is None else f"p{c[0]}u{c[1]}")
-@pytest.mark.parametrize("tf", ["f32", "f16"])
+@pytest.mark.parametrize("tf", ["f32", "f16", "bf16"])
 def test_batched_parity_against_oracle(M, orc, tf, cfg):
     say(f"batched parity tf={tf} cfg={cfg}")
-    T = {"f32": M.F32, "f16": M.F16}[tf]
+    T = {"f32": M.F32, "f16": M.F16, "bf16": M.BF16}[tf]
     if cfg[0] is not None:
         M.batch_set_tuning(M.F64, T, _one_config(M, *cfg))
     try:
@@ -78,14 +78,15 @@ def _parity_run(M, orc, tf):
     As = [dev(at) for _, at, _ in systems]
     bs = [dev(b) for _, _, b in systems]
     xs = [torch.empty_like(b) for b in bs]
-    T = {"f32": M.F32, "f16": M.F16}[tf]
+    T = {"f32": M.F32, "f16": M.F16, "bf16": M.BF16}[tf]
     tp = M.term(tol_rel=1e-14, litmax=20)
     bt = M.Batch(As, bs, xs, T, term_parms=tp, use_graph=False)
     st, reps = bt.run()
     bt.destroy()
     assert st == M.OK
     for (n, at, b), x, rep in zip(systems, xs, reps):
-        ref = orc.ir_solve(at, b, {"f32": orc.F32, "f16": orc.F16}[tf], tol_rel=1e-14, litmax=20)
+        ref = orc.ir_solve(at, b, {"f32": orc.F32, "f16": orc.F16, "bf16": orc.BF16}[tf], tol_rel=1e-14,
+                           litmax=20)
         assert rep.reserved == 0 and rep.info == 0
         assert rep.stop_name == ref.stop_name == "converged", (n, rep.stop_name, ref.stop_name)
         assert abs(rep.n_iter - ref.n_iter) <= 1, (n, rep.n_iter, ref.n_iter)
@@ -186,13 +187,13 @@ def test_batched_full_workload_sampled(M, orc):
         assert np.abs(xs[k].cpu().numpy() - ref.x).max() <= 1e-13
 
 
-@pytest.mark.parametrize("tf", ["f32", "f16"])
+@pytest.mark.parametrize("tf", ["f32", "f16", "bf16"])
 def test_autotune_table_and_cache(M, tmp_path, tf):
     """The autotuner returns a valid table (every class measured, a
     candidate chosen), installs it, writes its cache, and a second call with
     the same cache reads the same table back instead of measuring."""
     say(f"autotune tf={tf}")
-    T = {"f32": M.F32, "f16": M.F16}[tf]
+    T = {"f32": M.F32, "f16": M.F16, "bf16": M.BF16}[tf]
     cache = str(tmp_path / f"tune_{tf}.txt")
     try:
         t1 = M.batch_autotune(M.F64, T, cache)
