@@ -97,7 +97,7 @@ def batched_bench(M, I, torch, dev, tf_name: str, reps: int = 3):
         As.append(at)
         bs.append(at.sum(0))
         xs.append(torch.empty(int(n), dtype=torch.float64, device=dev))
-    tf = {"f32": M.F32, "f16": M.F16}[tf_name]
+    tf = {"f32": M.F32, "f16": M.F16, "bf16": M.BF16}[tf_name]
     # panel width and update form per size class: measured on this device
     # (or read from the cache file) before the batch is created
     t0 = time.perf_counter()
@@ -459,7 +459,7 @@ def main():
         log(f"[bench] FP64 LU solve {fp64_ms:.2f} ms  relres={rn64 / bn:.2e}")
     if not args.no_batched:
         out["batched"] = []
-        for tfn in ("f32", "f16"):
+        for tfn in ("f32", "f16", "bf16"):
             log(f"[bench] batched 4096 uneven systems, TF={tfn}")
             out["batched"].append(batched_bench(M, I, torch, dev, tfn))
             log(f"[bench]   {out['batched'][-1]}")
