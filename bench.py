@@ -316,8 +316,8 @@ def main():
                          "scaling rocprofv3 FETCH_SIZE / WRITE_SIZE counters)")
     args = ap.parse_args()
     if args.gpus != 1:
-        print(json.dumps({"error": "this build runs on one GPU; multi-GPU sharding is "
-                                   "described in DESIGN.md but not built"}))
+        print(json.dumps({"error": "single-GPU benchmark: --gpus must be 1 (sharding the "
+                                   "factorization over several GPUs is not implemented)"}))
         sys.exit(2)
 
     import torch
