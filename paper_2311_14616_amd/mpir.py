@@ -248,15 +248,17 @@ class Factorization:
         (column-major n x nrhs with ldb = B.stride(0)); returns (X, reports)."""
         torch = _torch()
         nrhs, n = B.shape
-        if n != self.n or B.stride(1) != 1:
-            raise ValueError("B must be (nrhs, n) with unit stride along n")
+        if n != self.n or B.stride(1) != 1 or not B.is_cuda or _prec_of_dtype(B.dtype) != self.tw:
+            raise ValueError("B must be a device tensor (nrhs, n) in TW with unit stride along n")
         X = torch.empty_like(B) if X is None else X
-        if tuple(X.shape) != (nrhs, n) or X.stride(1) != 1 or X.dtype != B.dtype:
-            raise ValueError("X must be (nrhs, n) of B's dtype with unit stride along n")
+        if tuple(X.shape) != (nrhs, n) or X.stride(1) != 1 or X.dtype != B.dtype or not X.is_cuda:
+            raise ValueError("X must be a device tensor (nrhs, n) of B's dtype with unit stride along n")
         reps = (Report * nrhs)()
         tp = C.byref(term_parms) if term_parms is not None else None
-        _check(lib().mpir_ir_solve_multi(self._h, nrhs, _dev_ptr(B), B.stride(0), _dev_ptr(X), X.stride(0),
-                                         tp, reps), "mpir_ir_solve_multi", allow)
+        # rows may be strided (ldb, ldx >= n): pass the base pointers as is
+        _check(lib().mpir_ir_solve_multi(self._h, nrhs, C.c_void_p(B.data_ptr()), B.stride(0),
+                                         C.c_void_p(X.data_ptr()), X.stride(0), tp, reps),
+               "mpir_ir_solve_multi", allow)
         return X, list(reps)
 
     def bicgstab_ir_solve(self, b, x=None, term_parms: Term | None = None, maxit: int = 10,

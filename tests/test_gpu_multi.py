@@ -133,3 +133,26 @@ def test_multi_full_size(M):
         say(f"  multi refinement {reps[0].t_ir_ms:.2f} ms for 4 columns, single {rep1.t_ir_ms:.2f} ms")
     finally:
         f.destroy()
+
+
+def test_multi_padded_leading_dimensions(M):
+    """B and X as views of wider arrays (ldb = n + 7, ldx = n + 3): the
+    columns are read and written at their strides and equal the contiguous
+    call bit for bit; the padding is left untouched."""
+    say("multi padded leading dimensions")
+    n, nrhs = 333, 5
+    at = I.gmat_operator(n, 10.0)
+    B = _rhs(at, nrhs, np.float64)
+    Bbig = torch.zeros((nrhs, n + 7), dtype=torch.float64, device=DEV)
+    Bbig[:, :n] = torch.from_numpy(B).to(DEV)
+    Xbig = torch.full((nrhs, n + 3), 7.0, dtype=torch.float64, device=DEV)
+    tp = M.term(tol_rel=1e-14, litmax=20)
+    f = M.Factorization(torch.from_numpy(at).to(DEV), M.F16, M.F64)
+    try:
+        Xv, reps = f.ir_solve_multi(Bbig[:, :n], X=Xbig[:, :n], term_parms=tp)
+        Xc, repc = f.ir_solve_multi(torch.from_numpy(B).to(DEV), term_parms=tp)
+    finally:
+        f.destroy()
+    assert torch.equal(Xbig[:, :n], Xc)
+    assert torch.all(Xbig[:, n:] == 7.0)
+    assert [r.n_iter for r in reps] == [r.n_iter for r in repc]
