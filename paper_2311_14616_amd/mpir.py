@@ -228,10 +228,16 @@ class Factorization:
         _check(st, "mpir_refactor", allow=(OK, ERR_SINGULAR))
         return self
 
+    def _vec(self, v, name):
+        """Device pointer of a contiguous vector of n entries in TW."""
+        if v.numel() != self.n or _prec_of_dtype(v.dtype) != self.tw:
+            raise ValueError(f"{name} must hold n = {self.n} entries in the working precision")
+        return _dev_ptr(v)
+
     def solve(self, b, x=None):
         torch = _torch()
         x = torch.empty_like(b) if x is None else x
-        _check(lib().mpir_solve(self._h, _dev_ptr(b), _dev_ptr(x)), "mpir_solve")
+        _check(lib().mpir_solve(self._h, self._vec(b, "b"), self._vec(x, "x")), "mpir_solve")
         return x
 
     def ir_solve(self, b, x=None, term_parms: Term | None = None):
@@ -239,7 +245,7 @@ class Factorization:
         x = torch.empty_like(b) if x is None else x
         rep = Report()
         tp = C.byref(term_parms) if term_parms is not None else None
-        _check(lib().mpir_ir_solve(self._h, _dev_ptr(b), _dev_ptr(x), tp, C.byref(rep)),
+        _check(lib().mpir_ir_solve(self._h, self._vec(b, "b"), self._vec(x, "x"), tp, C.byref(rep)),
                "mpir_ir_solve")
         return x, rep
 
@@ -270,7 +276,7 @@ class Factorization:
         tp = C.byref(term_parms) if term_parms is not None else None
         litmax = term_parms.litmax if term_parms is not None else 10
         kh = (C.c_int32 * max(litmax, 1))()
-        _check(lib().mpir_bicgstab_ir_solve(self._h, _dev_ptr(b), _dev_ptr(x), tp, int(maxit),
+        _check(lib().mpir_bicgstab_ir_solve(self._h, self._vec(b, "b"), self._vec(x, "x"), tp, int(maxit),
                                             float(inner_tol), C.byref(rep), kh),
                "mpir_bicgstab_ir_solve")
         return x, rep, [int(kh[i]) for i in range(rep.n_iter)]
@@ -284,7 +290,7 @@ class Factorization:
         tp = C.byref(term_parms) if term_parms is not None else None
         litmax = term_parms.litmax if term_parms is not None else 10
         kh = (C.c_int32 * max(litmax, 1))()
-        _check(lib().mpir_gmres_ir_solve(self._h, _dev_ptr(b), _dev_ptr(x), tp, int(basissize),
+        _check(lib().mpir_gmres_ir_solve(self._h, self._vec(b, "b"), self._vec(x, "x"), tp, int(basissize),
                                          float(gmres_tol), C.byref(rep), kh),
                "mpir_gmres_ir_solve")
         return x, rep, [int(kh[i]) for i in range(rep.n_iter)]
