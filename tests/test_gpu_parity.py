@@ -411,3 +411,49 @@ def test_full_size_factorization_and_solve(M, tf):
     # where the summation order alone changes them by their own size
     assert rep.relres <= 1e-14 and rn / float(b.abs().max()) <= 2e-14
     assert float((x - 1.0).abs().max()) <= 1e-11
+
+
+@pytest.mark.parametrize("tf", ["f16", "bf16"])
+@pytest.mark.parametrize("alpha", [1.0, 10.0, 100.0])
+def test_half_precision_sweep_at_scale(M, tf, alpha):
+    """The half-precision configuration at N = 8192 (A = I - alpha Gmat,
+    TW = TR = F64): the refinement either meets the 1e-14 rule or stagnates
+    at the residual floor just above it (eq. stag), never higher; the
+    backward error is at most 1e-14 either way and x* = ones is recovered."""
+    n = 8192
+    say(f"half sweep n={n} alpha={alpha} tf={tf}")
+    At = I.gmat_operator_torch(n, alpha, DEV)
+    b = I.rhs_ones_torch(At)
+    T = {"f16": M.F16, "bf16": M.BF16}[tf]
+    x, rep = M.ir_solve(At, b, T, term_parms=M.term(tol_rel=1e-14, litmax=30))
+    say(f"  n_iter={rep.n_iter} stop={rep.stop_name} relres={rep.relres:.2e} bwd={rep.bwd_err:.2e}")
+    assert rep.stop_name in ("converged", "stagnated")
+    assert rep.relres <= (1e-14 if rep.stop_name == "converged" else 5e-14)
+    assert rep.bwd_err <= 1e-14
+    kappa_bound = {1.0: 2.0, 10.0: 300.0, 100.0: 300.0}[alpha]        # kappa_inf well below these
+    assert float((x - 1.0).abs().max()) <= 1e-12 * kappa_bound
+
+
+@pytest.mark.parametrize("kappa", [1e4, 1e7])
+def test_wilkinson_type_at_scale(M, kappa):
+    """The Wilkinson-type configuration (N = 16384, TW = TF = F32,
+    TR = F64, stop by eq. wilkterm): x agrees with the binary64 LU solve of
+    the same binary32 matrix to the binary32 storage of x (a few units of
+    2^-24), far below the error of a plain binary32 LU solve."""
+    n = 16384
+    say(f"wilkinson n={n} kappa={kappa:.0e}")
+    at32, b32, xstar, _ = I.wilkinson_operator_torch(n, kappa, DEV)
+    x, rep = M.ir_solve(at32, b32, M.F32, tr=M.F64, term_parms=M.term(litmax=20))
+    assert rep.stop_name in ("dstagnated", "litmax")
+    f = M.Factorization(at32.to(torch.float64), M.F64, M.F64)
+    x64 = f.solve(b32.to(torch.float64))
+    f.destroy()
+    xp = torch.empty_like(b32)
+    g = M.Factorization(at32, M.F32, M.F32)
+    g.solve(b32, xp)
+    g.destroy()
+    err = float((x.double() - x64).abs().max()) / float(x64.abs().max())
+    err_plain = float((xp.double() - x64).abs().max()) / float(x64.abs().max())
+    say(f"  n_iter={rep.n_iter} stop={rep.stop_name} ferr vs fp64 {err:.2e} (plain fp32 LU {err_plain:.2e})")
+    assert err <= 4 * 2.0**-24
+    assert err < err_plain
