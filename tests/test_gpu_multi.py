@@ -156,3 +156,30 @@ def test_multi_padded_leading_dimensions(M):
     assert torch.equal(Xbig[:, :n], Xc)
     assert torch.all(Xbig[:, n:] == 7.0)
     assert [r.n_iter for r in reps] == [r.n_iter for r in repc]
+
+
+def test_multi_after_refactor_equals_fresh_handle(M):
+    """mpir_refactor reuses the handle (factors and the several-column
+    workspace): refactoring a BF16 handle with a new matrix and solving three
+    columns gives bit for bit what a fresh handle gives."""
+    say("multi after refactor (bf16)")
+    n = 400
+    a1 = I.gmat_operator(n, 1.0)
+    a2 = I.gmat_operator(n, 10.0)
+    B = torch.from_numpy(_rhs(a2, 3, np.float64)).to(DEV)
+    tp = M.term(tol_rel=1e-14, litmax=30)
+    A1, A2 = torch.from_numpy(a1).to(DEV), torch.from_numpy(a2).to(DEV)
+    f = M.Factorization(A1, M.BF16, M.F64)
+    try:
+        f.ir_solve_multi(torch.from_numpy(_rhs(a1, 3, np.float64)).to(DEV), term_parms=tp)
+        f.refactor(A2)
+        X1, r1 = f.ir_solve_multi(B, term_parms=tp)
+    finally:
+        f.destroy()
+    g = M.Factorization(A2, M.BF16, M.F64)
+    try:
+        X2, r2 = g.ir_solve_multi(B, term_parms=tp)
+    finally:
+        g.destroy()
+    assert torch.equal(X1, X2)
+    assert [r.n_iter for r in r1] == [r.n_iter for r in r2]
