@@ -142,15 +142,23 @@ def apply_pivots(ipiv: np.ndarray, y: np.ndarray):
     return v
 
 
-def residual(at: np.ndarray, b: np.ndarray, x: np.ndarray, tr: int = F64):
-    """r = b - A x in precision tr (sum in increasing column order)."""
+def residual(at: np.ndarray, b: np.ndarray, x: np.ndarray, tr: int = F64,
+             lda: int | None = None):
+    """r = b - A x in precision tr (sum in increasing column order).
+
+    ``at`` holds A column by column: at[j, i] = A[i, j].  With ``lda`` given,
+    ``at`` has shape (n, lda), lda >= n, and entries i >= n of each column
+    are padding that is never read."""
     at = np.ascontiguousarray(at)
     tw = _prec_of(at)
     b = np.ascontiguousarray(b, dtype=_NP[tw])
     x = np.ascontiguousarray(x, dtype=_NP[tw])
-    n = at.shape[1]
+    n = b.size
+    lda = n if lda is None else lda
+    if lda < max(n, 1) or at.size < (n - 1) * lda + n:
+        raise ValueError("A buffer too small for n and lda")
     r = np.empty(n, dtype=np.float64)
-    lib().orc_residual(n, _ptr(at), n, tw, tr, _ptr(b), _ptr(x), _ptr(r))
+    lib().orc_residual(n, _ptr(at), lda, tw, tr, _ptr(b), _ptr(x), _ptr(r))
     return r
 
 
