@@ -21,7 +21,8 @@
  *    hipStream_t passed as void*, NULL = the default stream) and returns
  *    only when its results are in place (it synchronises that stream).
  *  - Errors are returned as mpir_status; nothing aborts.  A failed call
- *    leaves caller-owned outputs unspecified and owned handles valid.
+ *    leaves caller-owned outputs unspecified and owned handles valid, except
+ *    a failed mpir_refactor, which empties its handle (MPIR_ERR_STATE).
  *  - One handle must not be used by two host threads at once.
  */
 #ifndef MPIR_H
@@ -45,6 +46,7 @@ typedef enum {
     MPIR_ERR_HIP = -3,          /* a HIP runtime call failed */
     MPIR_ERR_NONFINITE = -4,    /* NaN or infinity in A or b */
     MPIR_ERR_RANGE = -5,        /* an entry of A overflows in TF (e.g. |a| >= 65520 for F16) */
+    MPIR_ERR_STATE = -6,        /* the handle holds no factorization: its last mpir_refactor failed */
     MPIR_ERR_DEVICE = -7        /* a kernel's bounded inter-workgroup wait expired */
 } mpir_status;
 
@@ -108,13 +110,24 @@ void mpir_term_default(mpir_term *t);
  *    in binary32).  BF16: the same with bfloat16 L and U.
  *  - *out receives the handle also on MPIR_ERR_SINGULAR (*info = first zero
  *    pivot, 1-based, LAPACK semantics: the factorization is completed);
- *    on any other error *out is NULL. */
+ *    on any other error *out is NULL.
+ *  - Size limit: the panel factorization keeps every row of a 32-column
+ *    leaf on chip, one or two rows per thread over at most 64 workgroups of
+ *    512 threads (no more than the device's compute units), so n <= 65536 for TF in {F32, F16, BF16} and n <= 32768
+ *    for TF = F64; a larger n returns MPIR_ERR_ARG.  (An n = 65536 system
+ *    in binary64 is 32 GiB, well inside one GPU's memory: the limit is the
+ *    leaf's, not the memory's.) */
 mpir_status mpir_factor(int64_t n, const void *dA, int64_t lda, mpir_prec tw,
                         mpir_prec tf, mpir_prec tr, void *hip_stream,
                         mpir_fact *out, int64_t *info);
 
 /* mplu!(MPF, B): refactor a matrix of the same size and precisions into an
- * existing handle, reusing its storage.  dA is borrowed as above. */
+ * existing handle, reusing its storage.  dA is borrowed as above.  On any
+ * failure other than MPIR_ERR_SINGULAR (MPIR_ERR_RANGE, MPIR_ERR_NONFINITE,
+ * MPIR_ERR_DEVICE, MPIR_ERR_HIP) the old factors are gone and the handle is
+ * marked empty: mpir_solve, mpir_ir_solve, mpir_ir_solve_multi,
+ * mpir_gmres_ir_solve, mpir_bicgstab_ir_solve and mpir_get_factors return
+ * MPIR_ERR_STATE until a later mpir_refactor succeeds. */
 mpir_status mpir_refactor(mpir_fact f, const void *dA, int64_t lda, int64_t *info);
 
 /* One low-precision solve (eqs. vdlow / promotevd):

@@ -111,6 +111,9 @@ struct mpir_fact_s {
     uint64_t *yw = nullptr;         // epoch-tagged solution words of the solves
     double anorm = 0.0;
     int64_t info = 0;
+    // 1 once a factorization completed (OK or SINGULAR); a failed refactor
+    // clears it, and every solve then refuses the handle
+    int valid = 0;
     double t_factor_ms = 0.0;
     hipStream_t stream2 = nullptr;  // look-ahead: trailing updates
     hipEvent_t evA[2] = {nullptr, nullptr}, evB[2] = {nullptr, nullptr};
@@ -371,8 +374,12 @@ int trailing_cap(int mode) {
     }
     if (env >= 0) return env;
     // measured at N = 32768 (factorization time against the cap, with the
-    // binary32 / binary16 leaves held to 128 registers per lane)
-    return mode == LU_F32 ? 6 : (mode == LU_F16 || mode == LU_BF16) ? 3 : 2;
+    // binary32 / binary16 leaves held to 128 registers per lane): binary32
+    // 6; the 16-bit update 2 (248 ms against 255 at 3 or 4); binary64 2
+    // (680 ms against 708 at 4 or without a cap, although the update alone
+    // then runs at 47 instead of 41 TFLOP/s: the leaves beside it slow down
+    // more than it gains)
+    return mode == LU_F32 ? 6 : 2;
 }
 
 mpir_status getrf(mpir_fact f) {
@@ -430,6 +437,7 @@ __global__ void k_init_perm(int64_t n, int32_t *perm) {
 mpir_status factor_impl(mpir_fact f, int64_t *info) {
     hipStream_t s = f->stream;
     const int64_t n = f->n;
+    f->valid = 0;
     hipEvent_t e0, e1;
     HIPCHK(hipEventCreate(&e0));
     HIPCHK(hipEventCreate(&e1));
@@ -469,6 +477,7 @@ mpir_status factor_impl(mpir_fact f, int64_t *info) {
     f->info = inf;
     if (info) *info = inf;
     if (flags & DF_TIMEOUT) return MPIR_ERR_DEVICE;
+    f->valid = 1;
     return inf ? MPIR_ERR_SINGULAR : MPIR_OK;
 }
 
@@ -502,6 +511,7 @@ const char *mpir_status_str(mpir_status s) {
     case MPIR_ERR_HIP: return "HIP runtime error";
     case MPIR_ERR_NONFINITE: return "non-finite input";
     case MPIR_ERR_RANGE: return "matrix entry overflows the factorization precision";
+    case MPIR_ERR_STATE: return "handle holds no factorization (its last refactor failed)";
     case MPIR_ERR_DEVICE: return "device wait expired";
     }
     return "unknown status";
@@ -547,6 +557,7 @@ void mpir_destroy(mpir_fact f) {
 
 mpir_status mpir_solve(mpir_fact f, const void *db, void *dx) {
     if (!f || !db || !dx) return MPIR_ERR_ARG;
+    if (!f->valid) return MPIR_ERR_STATE;
     if (f->info) return MPIR_ERR_SINGULAR;
     hipStream_t s = f->stream;
     const int64_t n = f->n;
@@ -582,6 +593,7 @@ mpir_status mpir_ir_solve(mpir_fact f, const void *db, void *dx, const mpir_term
         rep->info = f->info;
         rep->t_factor_ms = f->t_factor_ms;
     }
+    if (!f->valid) return MPIR_ERR_STATE;
     if (f->info) return MPIR_ERR_SINGULAR;
     hipStream_t s = f->stream;
     const int64_t n = f->n;
@@ -690,6 +702,7 @@ mpir_status mpir_gmres_ir_solve(mpir_fact f, const void *db, void *dx, const mpi
         rep->info = f->info;
         rep->t_factor_ms = f->t_factor_ms;
     }
+    if (!f->valid) return MPIR_ERR_STATE;
     if (f->info) return MPIR_ERR_SINGULAR;
     hipStream_t s = f->stream;
     const int64_t n = f->n;
@@ -857,6 +870,7 @@ mpir_status mpir_bicgstab_ir_solve(mpir_fact f, const void *db, void *dx, const 
         rep->info = f->info;
         rep->t_factor_ms = f->t_factor_ms;
     }
+    if (!f->valid) return MPIR_ERR_STATE;
     if (f->info) return MPIR_ERR_SINGULAR;
     hipStream_t s = f->stream;
     const int64_t n = f->n;
@@ -1010,6 +1024,7 @@ mpir_status mpir_ir_solve_multi(mpir_fact f, int32_t nrhs, const void *dB, int64
             reps[c].t_factor_ms = f->t_factor_ms;
         }
     }
+    if (!f->valid) return MPIR_ERR_STATE;
     if (f->info) return MPIR_ERR_SINGULAR;
     hipStream_t s = f->stream;
     const int64_t n = f->n;
@@ -1187,6 +1202,7 @@ mpir_status mpir_downcast(int64_t n, const void *dA, int64_t lda, mpir_prec tw, 
 
 mpir_status mpir_get_factors(mpir_fact f, void *dLU, int32_t *ipiv) {
     if (!f || (!dLU && !ipiv)) return MPIR_ERR_ARG;
+    if (!f->valid) return MPIR_ERR_STATE;
     hipStream_t s = f->stream;
     const int64_t n = f->n;
     if (dLU) {
@@ -1243,6 +1259,7 @@ struct mpir_batch_s {
     float *work = nullptr;
     int32_t *perm = nullptr;
     mpir_report *reps_d = nullptr;
+    std::vector<mpir_report> reps_h;   // host copy when the caller passes no reports
     BatchTerm term{};
     int nwg = 0;
     hipGraph_t graph = nullptr;
@@ -1334,6 +1351,7 @@ mpir_status batch_create_with(int32_t batch, const int64_t *n, const void *const
         free_batch(b);
         return MPIR_ERR_ALLOC;
     }
+    b->reps_h.resize(batch);
     std::vector<BatchSys> sys(batch);
     int64_t wo = 0, po = 0;
     for (int32_t k = 0; k < batch; ++k) {
@@ -1388,11 +1406,14 @@ mpir_status mpir_batch_run(mpir_batch b, mpir_report *reps) {
     if (!b) return MPIR_ERR_ARG;
     if (b->exec) HIPCHK(hipGraphLaunch(b->exec, b->stream));
     else HIPCHK(enqueue_batch(b, b->stream));
-    if (reps) HIPCHK(hipMemcpyAsync(reps, b->reps_d, sizeof(mpir_report) * b->batch, hipMemcpyDeviceToHost, b->stream));
+    // the per-system statuses are read whether or not the caller wants the
+    // reports: a failed system leaves its x unwritten, which must not pass
+    // as MPIR_OK
+    mpir_report *h = reps ? reps : b->reps_h.data();
+    HIPCHK(hipMemcpyAsync(h, b->reps_d, sizeof(mpir_report) * b->batch, hipMemcpyDeviceToHost, b->stream));
     HIPCHK(hipStreamSynchronize(b->stream));
-    if (reps)
-        for (int32_t k = 0; k < b->batch; ++k)
-            if (reps[k].reserved != MPIR_OK) return (mpir_status)reps[k].reserved;
+    for (int32_t k = 0; k < b->batch; ++k)
+        if (h[k].reserved != MPIR_OK) return (mpir_status)h[k].reserved;
     return MPIR_OK;
 }
 

@@ -20,8 +20,8 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(HERE, "libmpir.so")
 
 F64, F32, F16, BF16 = 0, 1, 2, 3
-OK, ERR_SINGULAR, ERR_ARG, ERR_ALLOC, ERR_HIP, ERR_NONFINITE, ERR_RANGE, ERR_DEVICE = \
-    0, 1, -1, -2, -3, -4, -5, -7
+OK, ERR_SINGULAR, ERR_ARG, ERR_ALLOC, ERR_HIP, ERR_NONFINITE, ERR_RANGE, ERR_STATE, ERR_DEVICE = \
+    0, 1, -1, -2, -3, -4, -5, -6, -7
 STOP_NAMES = {0: "converged", 1: "stagnated", 2: "dstagnated", 3: "litmax", 4: "nonfinite"}
 HIST_MAX = 64
 PROF_GEMM, PROF_PANEL, PROF_TRSV, PROF_GEMV, PROF_DOWNCAST = 0, 1, 2, 3, 4
@@ -220,10 +220,14 @@ class Factorization:
         self._h = h
 
     def refactor(self, At):
+        """mplu!(MPF, A): factor At into this handle.  On failure (other than a
+        zero pivot) the handle holds no factorization and every solve raises
+        (MPIR_ERR_STATE) until a refactor succeeds."""
         if At.shape != self.At.shape or _prec_of_dtype(At.dtype) != self.tw:
             raise ValueError("refactor needs the same size and precision")
         info = C.c_int64(0)
         st = lib().mpir_refactor(self._h, _dev_ptr(At), At.shape[1], C.byref(info))
+        # the library now borrows At (also after a failure): keep it alive
         self.At, self.status, self.info = At, st, info.value
         _check(st, "mpir_refactor", allow=(OK, ERR_SINGULAR))
         return self

@@ -37,7 +37,7 @@ def test_every_declared_symbol_is_exported(M):
 
 def test_status_strings(M):
     for st in (M.OK, M.ERR_SINGULAR, M.ERR_ARG, M.ERR_ALLOC, M.ERR_HIP, M.ERR_NONFINITE,
-               M.ERR_RANGE, M.ERR_DEVICE):
+               M.ERR_RANGE, M.ERR_STATE, M.ERR_DEVICE):
         assert M.status_str(st) and M.status_str(st) != "unknown status"
     assert M.status_str(12345) == "unknown status"
 
