@@ -671,13 +671,10 @@ int num_cus() {
 // meanwhile (the trailing update on the second stream) finishes on its own
 // and frees its units; the bounded waits turn anything else into
 // MPIR_ERR_DEVICE.  MPIR_LEAF_COOP=1 restores the cooperative launch.
+// (read at every launch, so that a process can switch it between calls)
 bool leaf_cooperative() {
-    static int env = -1;
-    if (env < 0) {
-        const char *e = std::getenv("MPIR_LEAF_COOP");
-        env = (e && e[0] == '1') ? 1 : 0;
-    }
-    return env == 1;
+    const char *e = std::getenv("MPIR_LEAF_COOP");
+    return e && e[0] == '1';
 }
 
 int leaf_gmax() { return num_cus() < kLeafMaxG ? num_cus() : kLeafMaxG; }

@@ -3,11 +3,14 @@
 Bars (written per test):
   - interprecision copy: bit-identical A_F and ||A||_inf (same rounding, same
     summation order);
-  - residual: |r_gpu - r_orc| <= gamma_n(u_d) * sum_j |a_ij x_j| (the two sum
-    in different orders);
-  - LU: identical pivot sequence on matrices without pivot near-ties, factors
-    within the forward error of two backward-stable evaluations, and the
-    componentwise bound of eq. comperr on the GPU factors themselves;
+  - residual: |r_gpu - r_orc| <= 2 gamma_{n+2}(u_R) (sum_j |a_ij x_j| + |b_i|)
+    (each side's error is at most gamma_{n+2} of that sum; they sum in
+    different orders);
+  - LU: identical pivot sequence on matrices without pivot near-ties (binary16
+    random matrices: sequences may part only where both choices are within
+    about one binary16 ulp), factors within the first-order perturbation bound
+    of the two factorizations' measured backward errors, and the componentwise
+    bound of eq. comperr on the GPU factors themselves;
   - one low-precision solve: the oracle's solve applied to the GPU factors,
     within gamma_n(u_s) componentwise;
   - refinement: iteration count within +-1 of the oracle, backward error
@@ -19,6 +22,7 @@ import numpy as np
 import pytest
 
 from paper_2311_14616_amd import inputs as I
+from lu_checks import check_first_pivot_difference, lu_difference_bound
 
 pytestmark = pytest.mark.gpu
 
@@ -167,20 +171,54 @@ def test_factor_parity(M, orc, name, n, tf):
     # of each other.  With binary16 factors a one-ulp difference of a binary32
     # sum (GPU and oracle add in different orders) moves a U entry by one
     # binary16 ulp, enough to flip near-ties of a random matrix; there the
-    # sequences are compared up to the first difference only.
+    # sequences may part, but only at a genuine near-tie: at the first
+    # differing step each side's choice has a multiplier within about one
+    # binary16 ulp of 1 in the other side's factors.
     if tf != "f16" or name == "gmat":
         assert np.array_equal(ipiv, ipiv_o)
     else:
         d = np.nonzero(ipiv != ipiv_o)[0]
-        assert len(d) == 0 or d[0] >= n // 8
+        if len(d):
+            check_first_pivot_difference(af, lu, ipiv, lu_o, ipiv_o, int(d[0]), 2.0**-11, say)
     if np.array_equal(ipiv, ipiv_o):
-        # both factorizations are backward stable, so entrywise they differ
-        # by at most about kappa(A) * gamma_3n(u) relative to the factors
-        a = at.T
-        kappa = np.abs(a).sum(1).max() * np.abs(np.linalg.inv(a)).sum(1).max()
-        u = {"f64": 2.0**-53, "f32": 2.0**-24, "f16": 2.0**-11}[tf]
-        tol = min(0.5, kappa * 3 * n * u)
-        assert np.abs(lu - lu_o).max() <= tol * np.abs(lu_o).max()
+        # Identical pivots: both factorizations are of the same P A_F, with
+        # backward errors E_g = L_g U_g - P A_F and E_o = L_o U_o - P A_F
+        # (measured here in FP64).  To first order the factors then differ by
+        # dL = L_o tril(F), dU = triu(F) U_o with F = L_o^-1 (E_g - E_o) U_o^-1,
+        # so entrywise |dL| <= |L_o| tril(G), |dU| <= triu(G) |U_o| with
+        # G = |L_o^-1| (|E_g| + |E_o|) |U_o^-1|; the factor 2 covers the
+        # second-order term.
+        bound = lu_difference_bound(lu_o, lu, pa)
+        diff = np.abs(lu - lu_o)
+        say(f"  max |LU_gpu - LU_orc| / bound = {(diff / np.maximum(bound, 1e-300)).max():.3e}, "
+            f"max bound / max|LU| = {bound.max() / np.abs(lu_o).max():.2e}")
+        assert np.all(diff <= bound)
+
+
+@pytest.mark.parametrize("tf", ["f32", "f64"])
+def test_cooperative_leaf_launch(M, orc, tf, monkeypatch):
+    """MPIR_LEAF_COOP=1 launches the multi-workgroup leaf cooperatively
+    (every workgroup guaranteed resident) instead of as an ordinary launch:
+    the same kernel, so the same pivots as the oracle and a converged
+    refinement."""
+    say(f"cooperative leaf tf={tf}")
+    monkeypatch.setenv("MPIR_LEAF_COOP", "1")
+    n = 1500                                   # three leaf workgroups
+    at = I.gmat_operator(n, 10.0)
+    b = I.rhs_ones(at)
+    f = M.factor(dev(at), TF[tf])
+    try:
+        lu, ipiv = f.factors()
+        x, rep = f.ir_solve(dev(b), term_parms=M.term(tol_rel=1e-14, litmax=20))
+    finally:
+        f.destroy()
+    af, _, _ = orc.downcast(at, TF[tf])
+    _, ipiv_o, _, _ = orc.lu(af, _lu_mode(orc, tf))
+    assert np.array_equal(ipiv, ipiv_o)
+    ref = orc.ir_solve(at, b, TF[tf], tol_rel=1e-14, litmax=20)
+    _same_stop_or_floor(rep.stop_name, rep.relres, ref.stop_name, ref.relres)
+    _iterations_match(rep.history()[0], ref.rhist, 1e-14)
+    assert rep.bwd_err <= 1e-14
 
 
 def test_singular_matrix_reports_first_zero_pivot(M):
@@ -413,47 +451,137 @@ def test_full_size_factorization_and_solve(M, tf):
     assert float((x - 1.0).abs().max()) <= 1e-11
 
 
+def _scale_ref(key):
+    """The oracle's result for an at-scale case (tests/golden/oracle_scale_refs.json,
+    written by tests/golden/make_scale_refs.py from the oracle alone)."""
+    import json
+    import os
+    path = os.path.join(os.path.dirname(os.path.abspath(__file__)), "golden", "oracle_scale_refs.json")
+    refs = json.load(open(path))
+    if key not in refs or "n_iter" not in refs[key]:
+        pytest.fail(f"no oracle reference {key} in {path}")
+    return refs[key]
+
+
+def _iterations_match(rh_g, rh_o, tol):
+    """Corrections within +-1 of the oracle's.  Near the residual floor the
+    count at the rule is set by rounding noise: when the oracle's last
+    contraction before its stop is weak (its residual fell by less than a
+    factor 4 on either side: the floor of eq. stagterm), the counts are compared where both
+    histories first reach 10 tol instead, a level both pass while still
+    contracting."""
+    rh_g, rh_o = np.asarray(rh_g) / rh_g[0], np.asarray(rh_o) / rh_o[0]
+    n_g, n_o = len(rh_g) - 1, len(rh_o) - 1
+    if abs(n_g - n_o) <= 1:
+        return
+    floor = any(len(rh) >= 3 and rh[-1] > rh[-2] / 4 for rh in (rh_g, rh_o))
+    assert floor, (n_g, n_o, rh_g[-3:], rh_o[-3:])
+
+    def first_below(rh, level):
+        idx = np.nonzero(rh <= level)[0]
+        return int(idx[0]) if len(idx) else len(rh)
+    k_g, k_o = first_below(rh_g, 10 * tol), first_below(rh_o, 10 * tol)
+    say(f"  at the floor: corrections to {10 * tol:.0e}: gpu {k_g}, oracle {k_o}")
+    assert abs(k_g - k_o) <= 1, (k_g, k_o)
+
+
+def _same_stop_or_floor(stop_g, relres_g, stop_o, relres_o):
+    """The same stop reason -- except at the residual floor: when the
+    refinement reaches the floor of eq. stagterm just at the 1e-14 rule, one
+    rounding-level difference decides whether the last residual lands below
+    the rule (converged) or stalls just above it (stagnated).  Both outcomes
+    are then correct, and both sides must have ended at the floor, within a
+    factor 5 of the rule."""
+    if stop_g == stop_o:
+        return
+    assert {stop_g, stop_o} == {"converged", "stagnated"}, (stop_g, stop_o)
+    assert relres_g <= 5e-14 and relres_o <= 5e-14, (relres_g, relres_o)
+
+
+def test_single_precision_at_8192_against_oracle(M):
+    """The headline configuration at N = 8192 (A = I - Gmat, b = A*ones,
+    TW = TR = F64, TF = F32): corrections within +-1 of the oracle's, the
+    same stop, backward error <= 1e-14 and ||x - 1|| within B_fwd."""
+    n = 8192
+    say(f"single n={n}")
+    ref = _scale_ref(f"single_n{n}_f32_alpha1")
+    At = I.gmat_operator_torch(n, 1.0, DEV)
+    b = I.rhs_ones_torch(At)
+    x, rep = M.ir_solve(At, b, M.F32, term_parms=M.term(tol_rel=1e-14, litmax=20))
+    xerr = float((x - 1.0).abs().max())
+    say(f"  gpu n_iter={rep.n_iter} {rep.stop_name} bwd={rep.bwd_err:.2e} |x-1|={xerr:.2e}; "
+        f"oracle {ref['n_iter']} {ref['stop']} |x-1|={ref['xerr_inf']:.2e}")
+    assert rep.stop_name == ref["stop"] == "converged"
+    _iterations_match(rep.history()[0], ref["rhist"], 1e-14)
+    assert rep.rhist[0] == ref["rhist"][0]
+    assert rep.bwd_err <= 1e-14
+    assert xerr <= 1e-12 * 2.0 * (2.0**-53 / 1e-16)       # kappa_inf(I - Gmat) < 2
+
+
 @pytest.mark.parametrize("tf", ["f16", "bf16"])
 @pytest.mark.parametrize("alpha", [1.0, 10.0, 100.0])
 def test_half_precision_sweep_at_scale(M, tf, alpha):
     """The half-precision configuration at N = 8192 (A = I - alpha Gmat,
-    TW = TR = F64): the refinement either meets the 1e-14 rule or stagnates
-    at the residual floor just above it (eq. stag), never higher; the
-    backward error is at most 1e-14 either way and x* = ones is recovered."""
+    TW = TR = F64), against the oracle's refinement of the same system: the
+    same stop reason (or, at the residual floor, converged on one side and
+    stagnated on the other) and corrections within +-1; the refinement either meets
+    the 1e-14 rule or stagnates at the residual floor just above it
+    (eq. stag), never higher; backward error <= 1e-14 and x* = ones
+    recovered within B_fwd."""
     n = 8192
     say(f"half sweep n={n} alpha={alpha} tf={tf}")
+    ref = _scale_ref(f"half_n{n}_{tf}_alpha{alpha:g}")
     At = I.gmat_operator_torch(n, alpha, DEV)
     b = I.rhs_ones_torch(At)
     T = {"f16": M.F16, "bf16": M.BF16}[tf]
     x, rep = M.ir_solve(At, b, T, term_parms=M.term(tol_rel=1e-14, litmax=30))
-    say(f"  n_iter={rep.n_iter} stop={rep.stop_name} relres={rep.relres:.2e} bwd={rep.bwd_err:.2e}")
+    xerr = float((x - 1.0).abs().max())
+    say(f"  gpu n_iter={rep.n_iter} stop={rep.stop_name} relres={rep.relres:.2e} bwd={rep.bwd_err:.2e} "
+        f"|x-1|={xerr:.2e}; oracle {ref['n_iter']} {ref['stop']} relres={ref['relres']:.2e} "
+        f"|x-1|={ref['xerr_inf']:.2e}")
+    _same_stop_or_floor(rep.stop_name, rep.relres, ref["stop"], ref["relres"])
+    say(f"  gpu rhist/rhist0 {['%.2e' % (v / rep.rhist[0]) for v in rep.history()[0]]}")
+    _iterations_match(rep.history()[0], ref["rhist"], 1e-14)
+    assert rep.rhist[0] == ref["rhist"][0]
     assert rep.stop_name in ("converged", "stagnated")
     assert rep.relres <= (1e-14 if rep.stop_name == "converged" else 5e-14)
     assert rep.bwd_err <= 1e-14
     kappa_bound = {1.0: 2.0, 10.0: 300.0, 100.0: 300.0}[alpha]        # kappa_inf well below these
-    assert float((x - 1.0).abs().max()) <= 1e-12 * kappa_bound
+    assert xerr <= 1e-12 * kappa_bound * (2.0**-53 / 1e-16)
 
 
-@pytest.mark.parametrize("kappa", [1e4, 1e7])
+@pytest.mark.parametrize("kappa", [1e4, 1e6, 1e7])
 def test_wilkinson_type_at_scale(M, kappa):
     """The Wilkinson-type configuration (N = 16384, TW = TF = F32,
-    TR = F64, stop by eq. wilkterm): x agrees with the binary64 LU solve of
-    the same binary32 matrix to the binary32 storage of x (a few units of
-    2^-24), far below the error of a plain binary32 LU solve."""
+    TR = F64, stop by eq. wilkterm), against the oracle: the same stop and
+    corrections within +-1, and x within a few units of 2^-24 (the binary32
+    storage of x) of the oracle's binary64 LU solve x_ref of the same
+    binary32 system, on the 1024 stored entries of x_ref; far below the error
+    of a plain binary32 LU solve."""
     n = 16384
     say(f"wilkinson n={n} kappa={kappa:.0e}")
+    ref = _scale_ref(f"wilkinson_n{n}_kappa{kappa:.0e}")
     at32, b32, xstar, _ = I.wilkinson_operator_torch(n, kappa, DEV)
+    fp = ref["input_fingerprint"]
+    for (j, i), h in zip(fp["at_idx"], fp["at_hex"]):
+        assert float(at32[j, i]) == float.fromhex(h)
+    for i, h in zip(fp["b_idx"], fp["b_hex"]):
+        assert float(b32[i]) == float.fromhex(h)
     x, rep = M.ir_solve(at32, b32, M.F32, tr=M.F64, term_parms=M.term(litmax=20))
-    assert rep.stop_name in ("dstagnated", "litmax")
-    f = M.Factorization(at32.to(torch.float64), M.F64, M.F64)
-    x64 = f.solve(b32.to(torch.float64))
-    f.destroy()
+    idx = torch.tensor(ref["sample_idx"], device=DEV)
+    xref = torch.tensor([float.fromhex(h) for h in ref["xref_sample_hex"]], dtype=torch.float64,
+                        device=DEV)
+    err = float((x.double()[idx] - xref).abs().max()) / ref["xref_inf"]
     xp = torch.empty_like(b32)
     g = M.Factorization(at32, M.F32, M.F32)
     g.solve(b32, xp)
     g.destroy()
-    err = float((x.double() - x64).abs().max()) / float(x64.abs().max())
-    err_plain = float((xp.double() - x64).abs().max()) / float(x64.abs().max())
-    say(f"  n_iter={rep.n_iter} stop={rep.stop_name} ferr vs fp64 {err:.2e} (plain fp32 LU {err_plain:.2e})")
+    err_plain = float((xp.double()[idx] - xref).abs().max()) / ref["xref_inf"]
+    say(f"  gpu n_iter={rep.n_iter} stop={rep.stop_name}; oracle {ref['n_iter']} {ref['stop']}; "
+        f"ferr vs oracle x_ref {err:.2e} (oracle's own IR {ref['ferr_vs_xref']:.2e}, "
+        f"plain fp32 LU {err_plain:.2e})")
+    assert rep.stop_name == ref["stop"]
+    assert abs(rep.n_iter - ref["n_iter"]) <= 1
+    assert rep.rhist[0] == ref["rhist"][0]
     assert err <= 4 * 2.0**-24
     assert err < err_plain
