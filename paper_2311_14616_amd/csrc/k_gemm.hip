@@ -13,10 +13,12 @@
 //              (products of two bfloat16 numbers are exact in binary32).
 //   TF = F64 : binary64, v_mfma_f64_16x16x4_f64 (the FP64 comparator).
 //
-// Tiling: a workgroup of four wave64s computes a BM x BN tile of C (binary32:
-// 256 x 128, each wave 128 x 64 = 4 x 2 blocks of 32 x 32; binary64:
-// 128 x 128, each wave 64 x 64 = 4 x 4 blocks of 16 x 16), accumulators in
-// registers.  K is walked in chunks staged through two LDS buffers: while the
+// Tiling: a workgroup of four wave64s computes a BM x BN tile of C,
+// accumulators in registers (the sizes are in Cfg32 / Cfg64 below, chosen by
+// timing the trailing update in the factorization: binary32 64 x 64, each
+// wave one 32 x 32 block; binary16 operands inside the panel 128 x 64;
+// binary64 64 x 64, each wave 2 x 2 blocks of 16 x 16; the packed 16-bit
+// trailing update 128 x 128, each wave 2 x 2 blocks of 32 x 32).  K is walked in chunks staged through two LDS buffers: while the
 // matrix cores work on chunk i, the global loads of chunk i+1 are in flight
 // (16-byte vector loads when every offset is 4-element aligned), so the load
 // latency hides behind the MFMA work of a chunk.  Workgroup ids are remapped
@@ -223,20 +225,40 @@ __global__ __launch_bounds__(256) void k_gemm_32(float *__restrict__ a, int64_t 
         __syncthreads();
         if constexpr (NBUF == 2) buf ^= 1;
     }
-    // epilogue: lane l, register v -> row 8*(v/4) + 4*(l/32) + v%4, col l%32
+    // epilogue: lane l, register v -> row 8*(v/4) + 4*(l/32) + v%4, col l%32.
+    // Binary16 operands (the panel's updates of TF = F16): every C load of a
+    // block is issued before the first store (FP16 factorization 258 ->
+    // 248 ms at N = 32768).  Binary32: one element at a time -- the batched
+    // form raised this instance's registers and cost the FP32
+    // factorization 25% (350 against 443 ms).
 #pragma unroll
     for (int i = 0; i < MI; ++i)
 #pragma unroll
-        for (int j = 0; j < NJ; ++j)
+        for (int j = 0; j < NJ; ++j) {
+            const int64_t col = tn + wn + j * 32 + (lane & 31);
+            if constexpr (HALF) {
+                float cv[16];
 #pragma unroll
-            for (int v = 0; v < 16; ++v) {
-                const int64_t row = tm + wm + i * 32 + 8 * (v >> 2) + 4 * (lane >> 5) + (v & 3);
-                const int64_t col = tn + wn + j * 32 + (lane & 31);
-                if (row < m && col < nc) {
-                    float *p = a + (r0 + row) * ld + c0 + col;
-                    *p = *p - acc[i][j][v];
+                for (int v = 0; v < 16; ++v) {
+                    const int64_t row = tm + wm + i * 32 + 8 * (v >> 2) + 4 * (lane >> 5) + (v & 3);
+                    cv[v] = (row < m && col < nc) ? a[(r0 + row) * ld + c0 + col] : 0.0f;
+                }
+#pragma unroll
+                for (int v = 0; v < 16; ++v) {
+                    const int64_t row = tm + wm + i * 32 + 8 * (v >> 2) + 4 * (lane >> 5) + (v & 3);
+                    if (row < m && col < nc) a[(r0 + row) * ld + c0 + col] = cv[v] - acc[i][j][v];
+                }
+            } else {
+#pragma unroll
+                for (int v = 0; v < 16; ++v) {
+                    const int64_t row = tm + wm + i * 32 + 8 * (v >> 2) + 4 * (lane >> 5) + (v & 3);
+                    if (row < m && col < nc) {
+                        float *p = a + (r0 + row) * ld + c0 + col;
+                        *p = *p - acc[i][j][v];
+                    }
                 }
             }
+        }
 }
 
 // --------------------------------------- 16-bit operands packed per step
@@ -294,50 +316,58 @@ __global__ __launch_bounds__(256) void k_pack_cols_h(const float *__restrict__ a
     }
 }
 
-// C[r0 + i][c0 + j] -= sum_t Ah[i][t] Bt[j][t]: 128 x 128 tiles, four waves
-// in a 2 x 2 grid of 64 x 64 (2 x 2 blocks of the 32x32x16 MFMA of T16),
-// double-buffered LDS stages of BK k; binary32 accumulators.
-template <typename T16, int ROLE, int BK, int MINB>
+// C[r0 + i][c0 + j] -= sum_t Ah[i][t] Bt[j][t]: four waves in a 2 x 2 grid,
+// each (32 WM) x (32 WN) of C in WM x WN blocks of the 32x32x16 MFMA of T16
+// (a wave reads WM + WN 16-byte operand vectors from LDS per WM * WN
+// products), double-buffered LDS stages of BK k, binary32 accumulators.
+// The C tile's read-modify-write issues every load of a block row before
+// its first store (one C element at a time made each load wait for the
+// previous store: 186 against 263 TFLOP/s in the factorization).  Measured
+// at N = 32768: WM = WN = 2 with two workgroups per SIMD-set is fastest;
+// 4 x 2 and 2 x 4 per wave (one workgroup) reach 165-177 TFLOP/s.
+template <typename T16, int WM, int WN, int BK, int MINB>
 __global__ __launch_bounds__(256, MINB) void k_gemm_h16(float *__restrict__ a, int64_t ld, int64_t r0,
                                                         int64_t m, int64_t c0, int64_t nc,
                                                         const T16 *__restrict__ Ah,
                                                         const T16 *__restrict__ Bt, int64_t kp,
                                                         int tiles_n, int nblk) {
     using V8 = typename Vec16<T16>::V8;
+    constexpr int TM = 64 * WM, TN = 64 * WN;         // workgroup tile
     constexpr int P = BK + 8;                         // LDS pitch (16-bit elements)
-    constexpr int NV = BK / 16;                       // 8-element vectors per thread and operand
-    __shared__ __align__(16) T16 As[2][kHT * P];
-    __shared__ __align__(16) T16 Bs[2][kHT * P];
+    constexpr int TPA = 256 / TM, TPB = 256 / TN;     // threads per row of A / of B
+    constexpr int NVA = BK / 8 / TPA, NVB = BK / 8 / TPB;   // 8-element vectors per thread
+    static_assert(TPA >= 1 && TPB >= 1 && NVA >= 1 && NVB >= 1 && TPA * TM == 256 && TPB * TN == 256,
+                  "load split");
+    __shared__ __align__(16) T16 As[2][TM * P];
+    __shared__ __align__(16) T16 Bs[2][TN * P];
     const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
     const int bid = xcd_remap(blockIdx.x, nblk);
     int trow, tcol;
     tile_coords(bid, nblk / tiles_n, tiles_n, trow, tcol);
-    const int64_t tm = (int64_t)trow * kHT, tn = (int64_t)tcol * kHT;
-    const int wm = (wv >> 1) * 64, wn = (wv & 1) * 64;
-    // loads: thread -> row tid / 2, BK/2 consecutive k at (tid % 2) * BK/2
-    const int lr = tid >> 1, lk = (tid & 1) * (BK / 2);
-    const T16 *ap = Ah + (tm + lr) * kp + lk;
-    const T16 *bp = Bt + (tn + lr) * kp + lk;
-    V8 ra[NV], rb[NV];
+    const int64_t tm = (int64_t)trow * TM, tn = (int64_t)tcol * TN;
+    const int wm = (wv >> 1) * (32 * WM), wn = (wv & 1) * (32 * WN);
+    const int la = tid / TPA, lka = (tid % TPA) * (BK / TPA);
+    const int lb = tid / TPB, lkb = (tid % TPB) * (BK / TPB);
+    const T16 *ap = Ah + (tm + la) * kp + lka;
+    const T16 *bp = Bt + (tn + lb) * kp + lkb;
+    V8 ra[NVA], rb[NVB];
     auto load = [&](int64_t kc) {
 #pragma unroll
-        for (int q = 0; q < NV; ++q) {
-            ra[q] = *reinterpret_cast<const V8 *>(ap + kc + 8 * q);
-            rb[q] = *reinterpret_cast<const V8 *>(bp + kc + 8 * q);
-        }
+        for (int q = 0; q < NVA; ++q) ra[q] = *reinterpret_cast<const V8 *>(ap + kc + 8 * q);
+#pragma unroll
+        for (int q = 0; q < NVB; ++q) rb[q] = *reinterpret_cast<const V8 *>(bp + kc + 8 * q);
     };
     auto store = [&](int buf) {
 #pragma unroll
-        for (int q = 0; q < NV; ++q) {
-            *reinterpret_cast<V8 *>(&As[buf][lr * P + lk + 8 * q]) = ra[q];
-            *reinterpret_cast<V8 *>(&Bs[buf][lr * P + lk + 8 * q]) = rb[q];
-        }
+        for (int q = 0; q < NVA; ++q) *reinterpret_cast<V8 *>(&As[buf][la * P + lka + 8 * q]) = ra[q];
+#pragma unroll
+        for (int q = 0; q < NVB; ++q) *reinterpret_cast<V8 *>(&Bs[buf][lb * P + lkb + 8 * q]) = rb[q];
     };
-    floatx16 acc[2][2];
+    floatx16 acc[WM][WN];
 #pragma unroll
-    for (int i = 0; i < 2; ++i)
+    for (int i = 0; i < WM; ++i)
 #pragma unroll
-        for (int j = 0; j < 2; ++j) acc[i][j] = floatx16{0};
+        for (int j = 0; j < WN; ++j) acc[i][j] = floatx16{0};
     load(0);
     store(0);
     __syncthreads();
@@ -348,37 +378,45 @@ __global__ __launch_bounds__(256, MINB) void k_gemm_h16(float *__restrict__ a, i
 #pragma unroll
         for (int s2 = 0; s2 < BK; s2 += 16) {
             const int kb = s2 + 8 * (lane >> 5);
-            V8 af[2], bf[2];
+            V8 af[WM], bf[WN];
 #pragma unroll
-            for (int i = 0; i < 2; ++i)
+            for (int i = 0; i < WM; ++i)
                 af[i] = *reinterpret_cast<const V8 *>(&As[buf][(wm + i * 32 + (lane & 31)) * P + kb]);
 #pragma unroll
-            for (int j = 0; j < 2; ++j)
+            for (int j = 0; j < WN; ++j)
                 bf[j] = *reinterpret_cast<const V8 *>(&Bs[buf][(wn + j * 32 + (lane & 31)) * P + kb]);
 #pragma unroll
-            for (int i = 0; i < 2; ++i)
+            for (int i = 0; i < WM; ++i)
 #pragma unroll
-                for (int j = 0; j < 2; ++j)
+                for (int j = 0; j < WN; ++j)
                     acc[i][j] = Vec16<T16>::mfma(af[i], bf[j], acc[i][j]);
         }
         if (more) store(buf ^ 1);
         __syncthreads();
         buf ^= 1;
     }
-    // epilogue: lane l, register v -> row 8*(v/4) + 4*(l/32) + v%4, col l%32
+    // epilogue: lane l, register v -> row 8*(v/4) + 4*(l/32) + v%4, col l%32;
+    // per block row i all WN*16 loads first, then the subtractions and stores
 #pragma unroll
-    for (int i = 0; i < 2; ++i)
+    for (int i = 0; i < WM; ++i) {
+        float cv[WN][16];
 #pragma unroll
-        for (int j = 0; j < 2; ++j)
+        for (int j = 0; j < WN; ++j)
 #pragma unroll
             for (int v = 0; v < 16; ++v) {
                 const int64_t row = tm + wm + i * 32 + 8 * (v >> 2) + 4 * (lane >> 5) + (v & 3);
                 const int64_t col = tn + wn + j * 32 + (lane & 31);
-                if (row < m && col < nc) {
-                    float *p = a + (r0 + row) * ld + c0 + col;
-                    *p = *p - acc[i][j][v];
-                }
+                cv[j][v] = (row < m && col < nc) ? a[(r0 + row) * ld + c0 + col] : 0.0f;
             }
+#pragma unroll
+        for (int j = 0; j < WN; ++j)
+#pragma unroll
+            for (int v = 0; v < 16; ++v) {
+                const int64_t row = tm + wm + i * 32 + 8 * (v >> 2) + 4 * (lane >> 5) + (v & 3);
+                const int64_t col = tn + wn + j * 32 + (lane & 31);
+                if (row < m && col < nc) a[(r0 + row) * ld + c0 + col] = cv[j][v] - acc[i][j][v];
+            }
+    }
 }
 
 // ---------------------------------------------------------------- binary64
@@ -472,6 +510,8 @@ __global__ __launch_bounds__(256) void k_gemm_f64(double *__restrict__ a, int64_
     }
     // v_mfma_f64_16x16x4f64 output: lane l, register v -> row (l/16) + 4*v,
     // col l%16 (rows interleaved, unlike the binary32 16x16 layout)
+    // (every C load of the tile issued before the first store)
+    double cv[MI][NJ][4];
 #pragma unroll
     for (int i = 0; i < MI; ++i)
 #pragma unroll
@@ -480,10 +520,17 @@ __global__ __launch_bounds__(256) void k_gemm_f64(double *__restrict__ a, int64_
             for (int v = 0; v < 4; ++v) {
                 const int64_t row = tm + wm + i * 16 + (lane >> 4) + 4 * v;
                 const int64_t col = tn + wn + j * 16 + (lane & 15);
-                if (row < m && col < nc) {
-                    double *p = a + (r0 + row) * ld + c0 + col;
-                    *p = *p - acc[i][j][v];
-                }
+                cv[i][j][v] = (row < m && col < nc) ? a[(r0 + row) * ld + c0 + col] : 0.0;
+            }
+#pragma unroll
+    for (int i = 0; i < MI; ++i)
+#pragma unroll
+        for (int j = 0; j < NJ; ++j)
+#pragma unroll
+            for (int v = 0; v < 4; ++v) {
+                const int64_t row = tm + wm + i * 16 + (lane >> 4) + 4 * v;
+                const int64_t col = tn + wn + j * 16 + (lane & 15);
+                if (row < m && col < nc) a[(r0 + row) * ld + c0 + col] = cv[i][j][v] - acc[i][j][v];
             }
 }
 
@@ -525,6 +572,24 @@ void go32(bool vec, float *a, int64_t ld, int64_t r0, int64_t m, int64_t c0, int
     }
 }
 
+template <int BM, int BN, int BK, int ROLE>
+void go64(bool vec, double *a, int64_t ld, int64_t r0, int64_t m, int64_t c0, int64_t nc, int64_t k,
+          int64_t kk, int cap, hipStream_t s) {
+    const int64_t tiles_m = (m + BM - 1) / BM, tiles_n = (nc + BN - 1) / BN;
+    const int64_t nblk = tiles_m * tiles_n;
+    auto kv = k_gemm_f64<true, BM, BN, BK, ROLE>;
+    auto ks = k_gemm_f64<false, BM, BN, BK, ROLE>;
+    static int pad_v[9] = {-1, -1, -1, -1, -1, -1, -1, -1, -1}, pad_s[9] = {-1, -1, -1, -1, -1, -1, -1, -1, -1};
+    const int ci = cap < 0 ? 0 : cap > 8 ? 8 : cap;
+    if (vec) {
+        if (pad_v[ci] < 0) pad_v[ci] = cap_pad((const void *)kv, ci);
+        kv<<<(unsigned)nblk, 256, pad_v[ci], s>>>(a, ld, r0, m, c0, nc, k, kk, (int)tiles_n, (int)nblk);
+    } else {
+        if (pad_s[ci] < 0) pad_s[ci] = cap_pad((const void *)ks, ci);
+        ks<<<(unsigned)nblk, 256, pad_s[ci], s>>>(a, ld, r0, m, c0, nc, k, kk, (int)tiles_n, (int)nblk);
+    }
+}
+
 template <int ROLE>
 hipError_t gemm_go(int mode, void *a, int64_t ld, int64_t r0, int64_t m, int64_t c0,
                    int64_t nc, int64_t k, int64_t kk, int cap, hipStream_t s) {
@@ -534,20 +599,7 @@ hipError_t gemm_go(int mode, void *a, int64_t ld, int64_t r0, int64_t m, int64_t
     const uintptr_t base = (uintptr_t)a;
     if (mode == LU_F64) {
         const bool vec = (ld % 2 == 0) && (k % 2 == 0) && (c0 % 2 == 0) && (base % 16 == 0);
-        using C = Cfg64;
-        const int64_t tiles_m = (m + C::BM - 1) / C::BM, tiles_n = (nc + C::BN - 1) / C::BN;
-        const int64_t nblk = tiles_m * tiles_n;
-        auto kv = k_gemm_f64<true, C::BM, C::BN, C::BK, ROLE>;
-        auto ks = k_gemm_f64<false, C::BM, C::BN, C::BK, ROLE>;
-        static int pad_v[9] = {-1, -1, -1, -1, -1, -1, -1, -1, -1}, pad_s[9] = {-1, -1, -1, -1, -1, -1, -1, -1, -1};
-        const int ci = cap < 0 ? 0 : cap > 8 ? 8 : cap;
-        if (vec) {
-            if (pad_v[ci] < 0) pad_v[ci] = cap_pad((const void *)kv, ci);
-            kv<<<(unsigned)nblk, 256, pad_v[ci], s>>>((double *)a, ld, r0, m, c0, nc, k, kk, (int)tiles_n, (int)nblk);
-        } else {
-            if (pad_s[ci] < 0) pad_s[ci] = cap_pad((const void *)ks, ci);
-            ks<<<(unsigned)nblk, 256, pad_s[ci], s>>>((double *)a, ld, r0, m, c0, nc, k, kk, (int)tiles_n, (int)nblk);
-        }
+        go64<Cfg64::BM, Cfg64::BN, Cfg64::BK, ROLE>(vec, (double *)a, ld, r0, m, c0, nc, k, kk, cap, s);
         return hipGetLastError();
     }
     const bool vec = (ld % 4 == 0) && (k % 4 == 0) && (c0 % 4 == 0) && (base % 16 == 0);
@@ -566,6 +618,8 @@ size_t gemm_h16_ws_halves(int64_t rows, int64_t kk) {
 template <typename T16>
 hipError_t gemm_h16_go(float *a, int64_t ld, int64_t r0, int64_t m, int64_t c0, int64_t nc,
                        int64_t k, int64_t kk, void *wa, void *wb, int cap, hipStream_t s) {
+    // operands packed with zero rows up to the next multiple of the tile
+    // edge kHT, so every workgroup tile reads inside the workspace
     const int64_t mp = (m + kHT - 1) / kHT * kHT, np_ = (nc + kHT - 1) / kHT * kHT;
     const int64_t kp = (kk + kHK - 1) / kHK * kHK;
     const int64_t tiles_m = mp / kHT, tiles_n = np_ / kHT, nblk = tiles_m * tiles_n;
@@ -578,7 +632,8 @@ hipError_t gemm_h16_go(float *a, int64_t ld, int64_t r0, int64_t m, int64_t c0, 
         dim3 gb((unsigned)(np_ / 64), (unsigned)((kp + 63) / 64));
         k_pack_cols_h<T16><<<gb, 256, 0, s>>>(a, ld, k, kk, kp, c0, nc, np_, Bt);
     }
-    auto kv = k_gemm_h16<T16, 0, kHK, 2>;
+    static_assert(64 * 2 == kHT, "the 16-bit update's tile edge");
+    auto kv = k_gemm_h16<T16, 2, 2, kHK, 2>;
     static int pad[9] = {-1, -1, -1, -1, -1, -1, -1, -1, -1};
     const int ci = cap < 0 ? 0 : cap > 8 ? 8 : cap;
     if (pad[ci] < 0) pad[ci] = cap_pad((const void *)kv, ci);
