@@ -66,22 +66,77 @@ def counter_traffic(tf_name: str, n: int):
     return rec.get("hbm_bytes_per_launch"), rec
 
 
+def host_cpu_model() -> str:
+    try:
+        with open("/proc/cpuinfo") as fp:
+            for line in fp:
+                if line.startswith("model name"):
+                    return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return "unknown"
+
+
 def cpu_baseline(n_sample: int, n_full: int):
-    """Time the oracle (plain C, OpenMP) on a bounded sample of the workload
-    and scale it to the full size (LU ~ N^3 dominates)."""
-    import numpy as np
+    """Time the oracle (plain C, OpenMP on the host cores) on a bounded sample
+    of the workload -- the same operator at N = n_sample -- and scale each
+    part by its own order: the downcast and LU (the oracle's factorization
+    alone, timed separately) by (N/n)^3, the refinement loop (whole solve
+    minus the factorization: O(N^2) per correction) by (N/n)^2 at the
+    sample's number of corrections."""
     from oracle import oracle as O
     from paper_2311_14616_amd import inputs as I
     at = I.gmat_operator(n_sample, 1.0)
     b = I.rhs_ones(at)
     t0 = time.perf_counter()
+    af, _, _ = O.downcast(at, O.F32)
+    O.lu(af, O.LU_F32)
+    t_lu = time.perf_counter() - t0
+    del af
+    t0 = time.perf_counter()
     r = O.ir_solve(at, b, O.F32, tol_rel=1e-14, litmax=20)
-    dt = time.perf_counter() - t0
-    scale = (n_full / n_sample) ** 3
-    return {"value": dt * 1e3 * scale, "unit": "ms", "cores": O.num_threads(), "kind": "oracle",
-            "sample": f"full IR solve (emulated FP32 LU + FP64 residual loop) at N={n_sample}, "
-                      f"{dt:.2f} s measured, scaled by (N/{n_sample})^3 = {scale:.0f} to N={n_full}",
-            "sample_n_iter": int(r.n_iter), "sample_s": dt}
+    t_all = time.perf_counter() - t0
+    t_loop = max(t_all - t_lu, 0.0)
+    s3, s2 = (n_full / n_sample) ** 3, (n_full / n_sample) ** 2
+    value_s = t_lu * s3 + t_loop * s2
+    return {"value": round(value_s * 1e3, 1), "unit": "ms", "cores": O.num_threads(), "kind": "oracle",
+            "host_cpu": host_cpu_model(), "host_nproc": os.cpu_count(),
+            "sample": f"oracle IR solve of the same operator at N={n_sample} ({r.n_iter} corrections): "
+                      f"factorization {t_lu:.2f} s x (N/{n_sample})^3, refinement loop {t_loop:.2f} s "
+                      f"x (N/{n_sample})^2, to N={n_full}",
+            "sample_n_iter": int(r.n_iter), "sample_factor_s": round(t_lu, 3),
+            "sample_solve_s": round(t_all, 3)}
+
+
+def gmat_kappa_inf(n: int, alpha: float, anorm: float):
+    """kappa_inf(A) for A = I - alpha*G (interior grid, 0 < alpha below the
+    smallest eigenvalue of T): G is the inverse of T = h^-2 tridiag(-1, 2, -1),
+    so A^-1 = I + alpha (T - alpha I)^-1; T - alpha I is a nonsingular
+    M-matrix with a nonnegative inverse, hence ||A^-1||_inf = max_i
+    (1 + alpha y_i) with (T - alpha I) y = ones, one tridiagonal solve."""
+    import numpy as np
+    from scipy.linalg import solve_banded
+    h = 1.0 / (n + 1)
+    lam_min = 4.0 / h**2 * np.sin(np.pi * h / 2) ** 2
+    if not (0.0 < alpha < lam_min):
+        return None
+    ab = np.zeros((3, n))
+    ab[0, 1:] = -1.0 / h**2
+    ab[1, :] = 2.0 / h**2 - alpha
+    ab[2, :-1] = -1.0 / h**2
+    y = solve_banded((1, 1), ab, np.ones(n))
+    return anorm * float(np.max(1.0 + alpha * y))
+
+
+def accuracy(x, rep, kappa):
+    """Forward error of x against x* = ones and against the bound
+    B_fwd = 1e-12 kappa_inf(A) (u_d / 1e-16), u_d = 2^-53."""
+    ferr = float((x - 1.0).abs().max())          # ||x*||_inf = 1
+    out = {"ferr_vs_ones": ferr}
+    if kappa is not None:
+        bf = 1e-12 * kappa * (2.0**-53 / 1e-16)
+        out.update({"kappa_inf": kappa, "b_fwd": bf, "ferr_over_b_fwd": ferr / bf})
+    return out
 
 
 def batched_bench(M, I, torch, dev, tf_name: str, reps: int = 3):
@@ -304,7 +359,7 @@ def main():
     ap.add_argument("--alpha", type=float, default=1.0)
     ap.add_argument("--tf", choices=["f32", "f16"], default="f32")
     ap.add_argument("--fp64-runs", type=int, default=1)
-    ap.add_argument("--cpu-sample", type=int, default=10240)
+    ap.add_argument("--cpu-sample", type=int, default=8192)
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--no-fp64", action="store_true")
     ap.add_argument("--no-batched", action="store_true")
@@ -381,6 +436,7 @@ def main():
     gemv_gbs = v_bytes / (v_ms * 1e-3) / 1e9 if v_ms > 0 else 0.0
     trsv_bytes_per = (4 if args.tf == "f32" else 2) * n * n
     trsv_gbs = trsv_bytes_per * t_cnt / (t_ms * 1e-3) / 1e9 if t_ms > 0 else 0.0
+    kappa = gmat_kappa_inf(n, args.alpha, rep.anorm_inf)
     log(f"[bench] IR step {ms_step:.2f} ms  n_iter={rep.n_iter} stop={rep.stop_name} "
         f"bwd={rep.bwd_err:.2e}  gemm {gemm_tflops:.1f} TF/s  panel {p_ms / args.steps:.1f} ms/step")
 
@@ -394,7 +450,8 @@ def main():
                                f"tol ||r||/||b|| <= 1e-14, litmax 20",
                    "n": n, "alpha": args.alpha, "tw": "f64", "tf": args.tf, "tr": "f64"},
         "ir": {"n_iter": rep.n_iter, "stop": rep.stop_name, "bwd_err": rep.bwd_err,
-               "relres": rep.relres, "t_factor_ms": rep.t_factor_ms, "t_ir_ms": rep.t_ir_ms},
+               "relres": rep.relres, "t_factor_ms": rep.t_factor_ms, "t_ir_ms": rep.t_ir_ms,
+               **accuracy(x, rep, kappa)},
         "roofline": {"bound": "mfma", "achieved": round(gemm_tflops, 2), "peak": PEAK[args.tf],
                      "unit": "TFLOP/s", "frac": round(gemm_tflops / PEAK[args.tf], 4),
                      "traffic": traffic, "kernel": f"trailing-update GEMM ({args.tf} MFMA)",
@@ -430,7 +487,8 @@ def main():
             hms = (time.perf_counter() - t0) * 1e3
             out[key] = {"ms": round(hms, 3), "n_iter": rh.n_iter, "stop": rh.stop_name,
                         "bwd_err": rh.bwd_err, "relres": rh.relres,
-                        "t_factor_ms": rh.t_factor_ms, "t_ir_ms": rh.t_ir_ms}
+                        "t_factor_ms": rh.t_factor_ms, "t_ir_ms": rh.t_ir_ms,
+                        **accuracy(xh, rh, kappa)}
             log(f"[bench] {key}: {hms:.2f} ms, n_iter={rh.n_iter}, bwd={rh.bwd_err:.2e}")
     if not args.no_fp64:
         log("[bench] FP64 LU comparator")
@@ -456,6 +514,7 @@ def main():
             if key in out:
                 out[key]["speedup_vs_fp64_lu"] = round(fp64_ms / out[key]["ms"], 3)
         out["fp64_lu_relres"] = rn64 / bn
+        out["fp64_lu_ferr_vs_ones"] = float((xs - 1.0).abs().max())
         log(f"[bench] FP64 LU solve {fp64_ms:.2f} ms  relres={rn64 / bn:.2e}")
     if not args.no_batched:
         out["batched"] = []
