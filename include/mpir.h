@@ -292,6 +292,22 @@ mpir_status mpir_residual(int64_t n, const void *dA, int64_t lda, mpir_prec tw,
                           mpir_prec tr, const void *db, const void *dx, void *dr,
                           double *rnorm, void *hip_stream);
 
+/* For callers that cannot allocate device memory (code under HIP graph
+ * capture, allocation-free serving loops, harnesses that forbid hipMalloc):
+ * mpir_residual with its scratch -- the norm accumulators and the binary64
+ * partial sums of each 256-column chunk -- in a fixed device array of the
+ * library (about 8 MiB, held on each GPU the library runs on until the
+ * process ends) instead of memory allocated per call.  Same arguments,
+ * results and rounding as mpir_residual; n <= MPIR_RESIDUAL_NOALLOC_MAX_N
+ * (MPIR_ERR_ARG beyond).  It calls no hipMalloc or hipFree.  Every call on
+ * one GPU uses the same array: calls that overlap on one GPU (two streams,
+ * two host threads) race and must be serialised by the caller.  Synchronises
+ * hip_stream before it returns. */
+#define MPIR_RESIDUAL_NOALLOC_MAX_N 16384
+mpir_status mpir_residual_noalloc(int64_t n, const void *dA, int64_t lda, mpir_prec tw,
+                                  mpir_prec tr, const void *db, const void *dx, void *dr,
+                                  double *rnorm, void *hip_stream);
+
 /* Per-kernel timing with HIP events recorded around each launch, on the
  * stream that launch uses.  kind: 0 = trailing-update GEMM (A22 -= L21 U12),
  * 1 = panel factorization (leaves and in-panel updates), 2 = triangular

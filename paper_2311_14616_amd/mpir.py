@@ -30,7 +30,7 @@ EXPORTS = [
     "mpir_term_default", "mpir_factor", "mpir_refactor", "mpir_solve", "mpir_ir_solve",
     "mpir_gmres_ir_solve", "mpir_ir_solve_multi", "mpir_bicgstab_ir_solve",
     "mpir_ir_solve_batched", "mpir_destroy", "mpir_status_str", "mpir_downcast",
-    "mpir_get_factors", "mpir_residual", "mpir_prof_enable", "mpir_prof_reset", "mpir_prof_get",
+    "mpir_get_factors", "mpir_residual", "mpir_residual_noalloc", "mpir_prof_enable", "mpir_prof_reset", "mpir_prof_get",
     "mpir_batch_create", "mpir_batch_run", "mpir_batch_destroy",
     "mpir_batch_get_tuning", "mpir_batch_set_tuning", "mpir_batch_autotune",
 ]
@@ -121,6 +121,8 @@ def lib():
         L.mpir_get_factors.argtypes = [vp, vp, vp]
         L.mpir_residual.restype = C.c_int
         L.mpir_residual.argtypes = [i64, vp, i64, C.c_int, C.c_int, vp, vp, vp, P(d), vp]
+        L.mpir_residual_noalloc.restype = C.c_int
+        L.mpir_residual_noalloc.argtypes = [i64, vp, i64, C.c_int, C.c_int, vp, vp, vp, P(d), vp]
         L.mpir_batch_create.restype = C.c_int
         L.mpir_batch_create.argtypes = [i32, P(i64), P(vp), P(i64), P(vp), P(vp), C.c_int, C.c_int,
                                         C.c_int, P(Term), i32, vp, P(vp)]
@@ -373,6 +375,23 @@ def residual(At, b, x, tr: int = F64, stream=None):
                                _dev_ptr(x), _dev_ptr(r), C.byref(rn), _stream_ptr(stream)),
            "mpir_residual")
     return r, rn.value
+
+
+RESIDUAL_NOALLOC_MAX_N = 16384
+
+
+def residual_noalloc(At, b, x, r, tr: int = F64, stream=None):
+    """mpir_residual_noalloc: r = b - A x in precision tr into the caller's r,
+    with the library's fixed device scratch (no device allocation); returns
+    ||r||_inf."""
+    n, lda = At.shape
+    if r.numel() != n or _prec_of_dtype(r.dtype) != tr:
+        raise ValueError("r must hold n entries in precision tr")
+    rn = C.c_double(0.0)
+    _check(lib().mpir_residual_noalloc(n, _dev_ptr(At), lda, _prec_of_dtype(At.dtype), tr, _dev_ptr(b),
+                                       _dev_ptr(x), _dev_ptr(r), C.byref(rn), _stream_ptr(stream)),
+           "mpir_residual_noalloc")
+    return rn.value
 
 
 class Batch:
