@@ -4,18 +4,22 @@
 // Layout: A is column-major in TW (lda); A_F is the row-major working array
 // of the factorization (binary32 for TF in {F32, F16, BF16}, binary64 for
 // F64).
-// One workgroup owns a strip of 64 rows and walks the column tiles from left
+// One workgroup owns a strip of TR rows and walks the column tiles from left
 // to right, so each row sum of |a_ij| is accumulated in increasing j (the
 // same order as a plain loop, hence bit-identical to it).  Reads are
 // coalesced along columns, the tile is transposed through LDS and written
-// coalesced along rows.
+// coalesced along rows.  The next tile's loads are issued into registers
+// before the current tile's row sums and stores, so two tiles per workgroup
+// are in flight (one tile at a time, with the loads issued a few at a time,
+// reached 2.2 TB/s).
 #include "mpir_internal.h"
 
 namespace mpir {
 namespace {
 
-constexpr int TR = 64;   // rows per strip
+constexpr int TR = 32;   // rows per strip
 constexpr int TC = 64;   // columns per tile
+constexpr int LPT = TR * TC / 256;   // elements per thread and tile
 
 template <typename TWt, typename Wt, int TF>
 __global__ __launch_bounds__(256) void k_downcast(int64_t n, const TWt *__restrict__ A,
@@ -24,23 +28,26 @@ __global__ __launch_bounds__(256) void k_downcast(int64_t n, const TWt *__restri
     __shared__ double tile[TC][TR + 1];
     const int t = threadIdx.x;
     const int64_t i0 = (int64_t)blockIdx.x * TR;
+    // load mapping: thread -> row (t % TR), columns (t / TR) + (256 / TR) s
+    const int lr = t % TR, lc = t / TR;
+    constexpr int LCS = 256 / TR;
+    const int64_t li = i0 + lr;
+    double v[LPT];
+    auto load = [&](int64_t j0) {
+#pragma unroll
+        for (int q = 0; q < LPT; ++q) {
+            const int64_t j = j0 + lc + LCS * q;
+            v[q] = (li < n && j < n) ? (double)A[li + j * lda] : 0.0;
+        }
+    };
     double rs = 0.0;
     uint32_t fl = 0;
+    load(0);
     for (int64_t j0 = 0; j0 < n; j0 += TC) {
-        // load: thread -> row (t % 64), columns (t / 64) + 4 s
-        {
-            const int r = t % TR;
-            const int64_t i = i0 + r;
-#pragma unroll 4
-            for (int s = 0; s < TC / 4; ++s) {
-                const int c = t / TR + 4 * s;
-                const int64_t j = j0 + c;
-                double v = 0.0;
-                if (i < n && j < n) v = (double)A[i + j * lda];
-                tile[c][r] = v;
-            }
-        }
+#pragma unroll
+        for (int q = 0; q < LPT; ++q) tile[lc + LCS * q][lr] = v[q];
         __syncthreads();
+        if (j0 + TC < n) load(j0 + TC);
         if (t < TR) {
             // row sum in increasing column order (one thread per row)
             const int64_t i = i0 + t;
@@ -49,22 +56,22 @@ __global__ __launch_bounds__(256) void k_downcast(int64_t n, const TWt *__restri
                 for (int c = 0; c < cmax; ++c) rs = rs + fabs(tile[c][t]);
             }
         }
-        // store: thread -> column (t % 64), rows (t / 64) + 4 s
+        // store: thread -> column (t % TC), rows (t / TC) + 4 s
         {
             const int c = t % TC;
             const int64_t j = j0 + c;
-#pragma unroll 4
+#pragma unroll
             for (int s = 0; s < TR / 4; ++s) {
                 const int r = t / TC + 4 * s;
                 const int64_t i = i0 + r;
                 if (i < n && j < n) {
-                    const double v = tile[c][r];
+                    const double x = tile[c][r];
                     Wt w;
-                    if (TF == MPIR_F64) w = (Wt)v;
-                    else if (TF == MPIR_F32) w = (Wt)(float)v;
-                    else if (TF == MPIR_BF16) w = (Wt)d2bf_as_float(v);
-                    else w = (Wt)d2h_as_float(v);
-                    if (!isfinite(v)) fl |= DF_NONFINITE;
+                    if (TF == MPIR_F64) w = (Wt)x;
+                    else if (TF == MPIR_F32) w = (Wt)(float)x;
+                    else if (TF == MPIR_BF16) w = (Wt)d2bf_as_float(x);
+                    else w = (Wt)d2h_as_float(x);
+                    if (!isfinite(x)) fl |= DF_NONFINITE;
                     else if (isinf((double)w)) fl |= DF_RANGE;
                     AF[i * ldf + j] = w;
                 }
