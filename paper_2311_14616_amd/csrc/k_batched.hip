@@ -660,9 +660,17 @@ __global__ __launch_bounds__(NT) void k_batched(const BatchSys *__restrict__ sys
 #pragma unroll
                             for (int c = 0; c < 64; ++c) drow[c] = 1.0f;
                         }
+                        // the lane's own diagonal entry, inverted before
+                        // the chain of 64 dependent steps (a division in
+                        // each step would lengthen it several times)
+                        float ul = drow[0];
+#pragma unroll
+                        for (int c = 1; c < 64; ++c)
+                            if (lane == c) ul = drow[c];
+                        const float rinv = 1.0f / ul;
 #pragma unroll
                         for (int jj = 63; jj >= 0; --jj) {
-                            if (lane == jj && lane < rows) z = z / drow[jj];
+                            if (lane == jj && lane < rows) z = z * rinv;
                             const float yj = __int_as_float(__builtin_amdgcn_readlane(__float_as_int(z), jj));
                             if (lane < jj) z -= drow[jj] * yj;
                         }
