@@ -99,13 +99,20 @@ def cpu_baseline(n_sample: int, n_full: int):
     t_loop = max(t_all - t_lu, 0.0)
     s3, s2 = (n_full / n_sample) ** 3, (n_full / n_sample) ** 2
     value_s = t_lu * s3 + t_loop * s2
-    return {"value": round(value_s * 1e3, 1), "unit": "ms", "cores": O.num_threads(), "kind": "oracle",
-            "host_cpu": host_cpu_model(), "host_nproc": os.cpu_count(),
-            "sample": f"oracle IR solve of the same operator at N={n_sample} ({r.n_iter} corrections): "
-                      f"factorization {t_lu:.2f} s x (N/{n_sample})^3, refinement loop {t_loop:.2f} s "
-                      f"x (N/{n_sample})^2, to N={n_full}",
-            "sample_n_iter": int(r.n_iter), "sample_factor_s": round(t_lu, 3),
-            "sample_solve_s": round(t_all, 3)}
+    out = {"value": round(value_s * 1e3, 1), "unit": "ms", "cores": O.num_threads(), "kind": "oracle",
+           "host_cpu": host_cpu_model(), "host_nproc": os.cpu_count(),
+           "sample": f"oracle IR solve of the same operator at N={n_sample} ({r.n_iter} corrections): "
+                     f"factorization {t_lu:.2f} s x (N/{n_sample})^3, refinement loop {t_loop:.2f} s "
+                     f"x (N/{n_sample})^2, to N={n_full}",
+           "sample_n_iter": int(r.n_iter), "sample_factor_s": round(t_lu, 3),
+           "sample_solve_s": round(t_all, 3)}
+    # the one full-size run of the oracle on a GPU machine's host, if recorded
+    # (oracle/time_full_size.py)
+    full = os.path.join(ROOT, "oracle", f"cpu_time_n{n_full}.json")
+    if os.path.exists(full):
+        with open(full) as fp:
+            out["measured_full_size"] = json.load(fp)
+    return out
 
 
 def gmat_kappa_inf(n: int, alpha: float, anorm: float):

@@ -60,6 +60,7 @@
  */
 #include <math.h>
 #include <stdint.h>
+#include <stdio.h>
 #include <stdlib.h>
 #include <string.h>
 #ifdef _OPENMP
@@ -203,9 +204,27 @@ static int64_t pivot_d(const double *a, int64_t n, int64_t k)
     return p;
 }
 
+/* Progress lines on stderr every 1024 columns when ORC_PROGRESS is set (a
+ * long factorization then shows that it is alive); no effect on results. */
+static int progress_on(void)
+{
+    const char *e = getenv("ORC_PROGRESS");
+    return e && e[0] == '1';
+}
+
+static void progress(int on, int64_t k, int64_t n)
+{
+    if (on && (k & 1023) == 0) {
+        fprintf(stderr, "[oracle] lu column %lld of %lld\n", (long long)k, (long long)n);
+        fflush(stderr);
+    }
+}
+
 static void lu_f64(double *a, int64_t n, int32_t *ipiv, int64_t *info)
 {
+    const int prog = progress_on();
     for (int64_t k = 0; k < n; ++k) {
+        progress(prog, k, n);
         int64_t p = pivot_d(a, n, k);
         ipiv[k] = (int32_t)p;
         if (a[p * n + k] == 0.0) {          /* exact zero pivot: record, skip */
@@ -235,7 +254,9 @@ static void lu_f64(double *a, int64_t n, int32_t *ipiv, int64_t *info)
  * a holds binary32 numbers (binary16 / bfloat16 values for the half modes). */
 static void lu_f32(float *a, int64_t n, int mode, int32_t *ipiv, int64_t *info)
 {
+    const int prog = progress_on();
     for (int64_t k = 0; k < n; ++k) {
+        progress(prog, k, n);
         int64_t p = pivot_f(a, n, k);
         ipiv[k] = (int32_t)p;
         if (p != k && a[p * n + k] != 0.0f)
