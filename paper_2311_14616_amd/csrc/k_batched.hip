@@ -374,29 +374,35 @@ __global__ __launch_bounds__(NT) void k_batched(const BatchSys *__restrict__ sys
                 L11[r][c] = W[(int64_t)(k + r) * n + k + c];
             }
             __syncthreads();
-            // one thread per column; the column lives in LDS (the panel
-            // buffer is free here), L11 is read from LDS by broadcast
+            // one thread per column, the column in registers (fully
+            // unrolled over the panel width; a column kept in LDS made every
+            // step an LDS read-modify-write on the dependence chain), L11
+            // read from LDS by broadcast
             for (int c0 = k + w; c0 < n; c0 += NT) {
                 const int c = c0 + tid;
-                float *xs = panel + tid;                    // xs[t * NT]
                 if (c < n) {
-                    {
-                        float xv[PB];
+                    float xv[PB];
 #pragma unroll
-                        for (int t = 0; t < PB; ++t) xv[t] = W[(int64_t)(k + (t < w ? t : 0)) * n + c];
+                    for (int t = 0; t < PB; ++t) xv[t] = W[(int64_t)(k + (t < w ? t : 0)) * n + c];
 #pragma unroll
-                        for (int t = 0; t < PB; ++t)
-                            if (t < w) xs[t * NT] = xv[t];
-                    }
-                    for (int t = 0; t < w; ++t) {
-                        float xt = xs[t * NT];
-                        if (RD) { xt = round_lo<RD>(xt); xs[t * NT] = xt; }
-                        for (int s2 = t + 1; s2 < w; ++s2) {
-                            const float prod = L11[s2][t] * xt;
-                            xs[s2 * NT] = xs[s2 * NT] - prod;
+                    for (int t = 0; t < PB; ++t) {
+                        if (t < w) {
+                            float xt = xv[t];
+                            if (RD) { xt = round_lo<RD>(xt); xv[t] = xt; }
+#pragma unroll
+                            for (int s2 = t + 1; s2 < PB; ++s2)
+                                if (s2 < w) {
+                                    const float prod = L11[s2][t] * xt;
+                                    xv[s2] = xv[s2] - prod;
+                                }
                         }
+                        // keep column t's L11 reads in this step (hoisting
+                        // all 496 of them spilled registers)
+                        __asm__ volatile("" ::: "memory");
                     }
-                    for (int t = 0; t < w; ++t) W[(int64_t)(k + t) * n + c] = xs[t * NT];
+#pragma unroll
+                    for (int t = 0; t < PB; ++t)
+                        if (t < w) W[(int64_t)(k + t) * n + c] = xv[t];
                 }
             }
             __syncthreads();
