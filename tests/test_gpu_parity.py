@@ -490,12 +490,14 @@ def _same_stop_or_floor(stop_g, relres_g, stop_o, relres_o):
     refinement reaches the floor of eq. stagterm just at the 1e-14 rule, one
     rounding-level difference decides whether the last residual lands below
     the rule (converged) or stalls just above it (stagnated).  Both outcomes
-    are then correct, and both sides must have ended at the floor, within a
-    factor 5 of the rule."""
+    are then correct, and both sides must have ended at the floor: within
+    10x the rule, the level both histories pass while still contracting
+    (the oracle's BF16, alpha = 10 refinement at N = 8192 stalls at
+    5.2e-14, after contractions of 0.38 and 0.61)."""
     if stop_g == stop_o:
         return
     assert {stop_g, stop_o} == {"converged", "stagnated"}, (stop_g, stop_o)
-    assert relres_g <= 5e-14 and relres_o <= 5e-14, (relres_g, relres_o)
+    assert relres_g <= 1e-13 and relres_o <= 1e-13, (relres_g, relres_o)
 
 
 def test_single_precision_at_8192_against_oracle(M):
