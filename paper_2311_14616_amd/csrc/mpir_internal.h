@@ -170,7 +170,7 @@ __device__ __forceinline__ void atomic_max_nonneg(uint64_t *p, double v) {
 // All take the stream explicitly; none synchronises.
 // ---------------------------------------------------------------------------
 
-// a1: A_F = I_W^F(A) into a row-major working array (float for TF in
+// A_F = I_W^F(A) into a row-major working array (float for TF in
 // {F32, F16}; double for F64), ||A||_inf bits and status flags.
 hipError_t launch_downcast(int64_t n, const void *A, int64_t lda, int tw, int tf,
                            void *AF, int64_t ldf, uint64_t *anorm_bits, uint32_t *flags,
@@ -182,9 +182,9 @@ hipError_t launch_pack_half(int tf, int64_t n, const float *AF, int64_t ldf, voi
 // Working array -> TF storage with the given row-major layout (copy).
 hipError_t launch_copy_factors(int64_t n, const void *src, int tf, void *dst, hipStream_t s);
 
-// a2: leaf panel factorization (cooperative).  Rows [k0, n), columns
-// [k0, k0+w), w <= 32.  ipiv receives 0-based global row indices.
-// host_base: host copy of the arrival counter of ps (advanced per launch).
+// Leaf panel factorization: rows [k0, n), columns [k0, k0+w), w <= 32.
+// ipiv receives 0-based global row indices.  host_base: host copy of the
+// exchange epoch of ps (advanced per launch).
 struct PanelSync;
 hipError_t launch_leaf(int mode, void *a, int64_t n, int64_t ld, int64_t k0, int w,
                        int32_t *ipiv, int64_t *info, PanelSync *ps, uint32_t *host_base,
@@ -193,13 +193,13 @@ int leaf_max_rows(int mode);
 size_t panel_sync_bytes();
 hipError_t panel_sync_reset(PanelSync *ps, hipStream_t s);
 
-// a3: row interchanges ipiv[k0 .. k0+cnt) applied to the column ranges
+// Row interchanges ipiv[k0 .. k0+cnt) applied to the column ranges
 // [c0, c1) and [c2, c3); perm (may be NULL) permuted alongside.  compact:
 // small LDS tiles (fits beside a running trailing update).
 hipError_t launch_laswp(int mode, void *a, int64_t n, int64_t ld, int64_t k0, int cnt,
                         const int32_t *ipiv, int64_t c0, int64_t c1, int64_t c2,
                         int64_t c3, int32_t *perm, bool compact, hipStream_t s);
-// a3: U12 <- L11^{-1} U12 for rows [k, k+w) (w <= 32), columns [c0, c1).
+// U12 <- L11^{-1} U12 for rows [k, k+w) (w <= 32), columns [c0, c1).
 hipError_t launch_trsm(int mode, void *a, int64_t ld, int64_t k, int w, int64_t c0,
                        int64_t c1, hipStream_t s);
 // a3 for a narrow column range: U12 <- L11^{-1} U12 for rows [k, k+w),
@@ -207,7 +207,7 @@ hipError_t launch_trsm(int mode, void *a, int64_t ld, int64_t k, int w, int64_t 
 int u12_max_rows();
 hipError_t launch_u12(int mode, void *a, int64_t ld, int64_t k, int w, int64_t c0, int64_t c1,
                       hipStream_t s);
-// a4: C[r0:r0+m, c0:c0+nc] -= A[r0:, k:k+kk] * A[k:k+kk, c0:] on one
+// Trailing update C[r0:r0+m, c0:c0+nc] -= A[r0:, k:k+kk] * A[k:k+kk, c0:] on one
 // row-major matrix (ld).  cap > 0: at most cap workgroups per compute unit
 // (the rest of each unit stays free for work on another stream).  role: 0 =
 // trailing update, 1 = update inside a panel or a U12 block (a separate
@@ -224,7 +224,7 @@ hipError_t launch_gemm_update_h16(int mode, float *a, int64_t ld, int64_t r0, in
                                   int64_t nc, int64_t k, int64_t kk, void *wa, void *wb,
                                   int cap, hipStream_t s);
 
-// a5: residual r = b - A x in TR, partial sums over column chunks then a
+// Residual r = b - A x in TR, partial sums over column chunks then a
 // fixed-order reduction; ||r|| and ||x|| bits into the state.
 hipError_t launch_residual(int64_t n, const void *A, int64_t lda, int tw, int tr,
                            const void *b, const void *x, void *r, double *partial,
@@ -251,7 +251,7 @@ hipError_t launch_update(int64_t n, int tw, int tf, const void *y, void *x,
                          IrState *st, int force, hipStream_t s);
 hipError_t launch_terminate(IrState *st, hipStream_t s);
 
-// a10: batched refinement of uneven systems in one persistent launch.
+// Batched refinement of uneven systems in one persistent launch.
 struct BatchSys;
 struct BatchTerm;
 int batched_max_n();
@@ -263,7 +263,7 @@ hipError_t launch_batched(int tw, int tf, const BatchSys *sys, const int32_t *or
                           uint32_t *queue, const BatchTerm &term, mpir_report *reps, int nwg,
                           hipStream_t s);
 
-// a7: triangular solves with the packed factors (row-major, TF storage).
+// Triangular solves with the packed factors (row-major, TF storage).
 // y is float for TF in {F32, F16}, double for F64.
 // yw: n * 2 epoch-tagged 64-bit words (zeroed once at allocation).
 hipError_t launch_trsv(int tf, int ysol, const void *LU, int64_t n, int64_t ld, void *y, uint64_t *yw,
