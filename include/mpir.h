@@ -233,7 +233,11 @@ void mpir_batch_destroy(mpir_batch b);
  *  - update[k]: 0 = every 32 x 32 block of A22 -= L21 U12 reads both of its
  *    operands from memory (good load balance on small trailing matrices),
  *    1 = L21 staged in LDS once per panel and each wave keeping one column
- *    block of U12 in registers while it sweeps the block rows.
+ *    block of U12 in registers while it sweeps the block rows;
+ *    2 (panel 32 only) = panels in pairs: the first panel of a pair updates
+ *    only the second's columns, and after the second one update of rank 64
+ *    (form 1 with both panels' L21, staged 512 rows at a time) brings the
+ *    rest of the trailing matrix up to date, passing over it half as often.
  * The library keeps one table per (TW, TF) pair for the whole process; it is
  * applied when a batch is created (mpir_batch_create, mpir_ir_solve_batched).
  * ms[k]: the measured time of the chosen configuration on the tuning batch

@@ -97,6 +97,32 @@ __device__ __forceinline__ void store_cblock(GMEM float *W, int n, int r0, int b
     }
 }
 
+// The same with the block's rows limited to < rlim and columns to < clim.
+__device__ __forceinline__ void load_cblock_lim(const GMEM float *W, int n, int r0, int bc, int lane,
+                                                int rlim, int clim, float (&c)[16]) {
+#pragma unroll
+    for (int v = 0; v < 16; ++v) {
+        const int row = r0 + 8 * (v >> 2) + 4 * (lane >> 5) + (v & 3);
+        const bool ok = row < rlim && bc < clim;
+        const float x = W[(int64_t)(ok ? row : 0) * n + (ok ? bc : 0)];
+        c[v] = ok ? x : 0.0f;
+    }
+}
+__device__ __forceinline__ void store_cblock_lim(GMEM float *W, int n, int r0, int bc, int lane,
+                                                 int rlim, int clim, const float (&c)[16],
+                                                 const floatx16 &acc) {
+#pragma unroll
+    for (int v = 0; v < 16; ++v) {
+        const int row = r0 + 8 * (v >> 2) + 4 * (lane >> 5) + (v & 3);
+        if (row < rlim && bc < clim) W[(int64_t)row * n + bc] = c[v] - acc[v];
+    }
+}
+
+// Rows of the rank-64 update's A panel staged in LDS at a time (pitch kWP).
+constexpr int kWP = 65;
+constexpr int kWideRows = 512;
+static_assert(kWideRows * kWP <= PANEL_FLOATS, "wide update chunk fits the panel buffer");
+
 // dst(e) = src(e) for e = tid, tid + NT, ... < N, with U loads in flight per
 // thread (all U issued before the first is stored; src(e) must accept any
 // e < N, and is called with e0 in place of an out-of-range e).
@@ -250,6 +276,146 @@ __global__ __launch_bounds__(NT) void k_batched(const BatchSys *__restrict__ sys
             continue;
         }
 
+        // C[r0 .. r0+nr) x [c0 .. c0+nc) -= W[., kk0 .. kk0+kw) W[kk0 .. kk0+kw, .)
+        // (kw <= 32), every 32 x 32 block on its own, both operands from
+        // memory (unconditional loads: out-of-range entries read an in-range
+        // word and are zeroed)
+        auto upd_blocks = [&](int r0, int nr, int c0, int nc, int kk0, int kw) {
+            const int nbr = (nr + 31) / 32, nbc = (nc + 31) / 32;
+            const int rlim = r0 + nr, clim = c0 + nc;
+            for (int blk = wv; blk < nbr * nbc; blk += NW) {
+                const int bi = blk / nbc, bj = blk - bi * nbc;
+                const int rb = r0 + bi * 32, cb = c0 + bj * 32;
+                const int ar = rb + (lane & 31), bc = cb + (lane & 31);
+                float cv[16];
+                floatx16 acc = floatx16{0};
+                if constexpr (RD != 0) {
+                    using L16 = Lo16<RD>;
+                    typename L16::V8 av[2], bvv[2];
+#pragma unroll
+                    for (int s2 = 0; s2 < 2; ++s2)
+#pragma unroll
+                        for (int q = 0; q < 8; ++q) {
+                            const int kq = 16 * s2 + 8 * (lane >> 5) + q;
+                            const bool oka = ar < rlim && kq < kw, okb = bc < clim && kq < kw;
+                            const float xa = W[(int64_t)(oka ? ar : 0) * n + kk0 + (oka ? kq : 0)];
+                            const float xb = W[(int64_t)(kk0 + (okb ? kq : 0)) * n + (okb ? bc : 0)];
+                            av[s2][q] = (typename L16::T)(oka ? xa : 0.0f);
+                            bvv[s2][q] = (typename L16::T)(okb ? xb : 0.0f);
+                        }
+                    load_cblock_lim(W, n, rb, bc, lane, rlim, clim, cv);
+#pragma unroll
+                    for (int s2 = 0; s2 < 2; ++s2) acc = L16::mfma(av[s2], bvv[s2], acc);
+                } else {
+                    float av[16], bvv[16];
+#pragma unroll
+                    for (int s1 = 0; s1 < 16; ++s1) {
+                        const int kq = 2 * s1 + (lane >> 5);
+                        const bool oka = ar < rlim && kq < kw, okb = bc < clim && kq < kw;
+                        const float xa = W[(int64_t)(oka ? ar : 0) * n + kk0 + (oka ? kq : 0)];
+                        const float xb = W[(int64_t)(kk0 + (okb ? kq : 0)) * n + (okb ? bc : 0)];
+                        av[s1] = oka ? xa : 0.0f;
+                        bvv[s1] = okb ? xb : 0.0f;
+                    }
+                    load_cblock_lim(W, n, rb, bc, lane, rlim, clim, cv);
+#pragma unroll
+                    for (int s1 = 0; s1 < 16; ++s1)
+                        acc = __builtin_amdgcn_mfma_f32_32x32x2f32(av[s1], bvv[s1], acc, 0, 0, 0);
+                }
+                store_cblock_lim(W, n, rb, bc, lane, rlim, clim, cv, acc);
+            }
+        };
+        // rows and columns [r0, n) -= W[., kk0 .. kk0+kw) W[kk0 .. kk0+kw, .)
+        // (kw <= 64): the A panel staged in LDS in chunks of up to kWideRows
+        // rows; wave wv takes block columns bj = wv, wv + NW, ..., holds that
+        // column's B block in registers and sweeps the chunk's block rows,
+        // the next block row's C loads in flight
+        auto upd_wide = [&](int r0, int kk0, int kw) {
+            const int mm = n - r0;
+            const int nbc = (mm + 31) / 32;
+            for (int q0 = 0; q0 < mm; q0 += kWideRows) {
+                const int cr = (mm - q0) < kWideRows ? (mm - q0) : kWideRows;
+                const int nbr = (cr + 31) / 32;
+                __syncthreads();
+                staged_copy<8>(cr * 64,
+                    [&](int e) {
+                        const int r = e >> 6, c = e & 63;
+                        return W[(int64_t)(r0 + q0 + r) * n + kk0 + (c < kw ? c : 0)];
+                    },
+                    [&](int e, float v) { panel[(e >> 6) * kWP + (e & 63)] = (e & 63) < kw ? v : 0.0f; });
+                __syncthreads();
+                for (int bj = wv; bj < nbc; bj += NW) {
+                    const int cb = r0 + bj * 32, bc = cb + (lane & 31);
+                    const int rb0 = r0 + q0;
+                    if constexpr (RD != 0) {
+                        using L16 = Lo16<RD>;
+                        typename L16::V8 bh[4];
+#pragma unroll
+                        for (int s2 = 0; s2 < 4; ++s2)
+#pragma unroll
+                            for (int q = 0; q < 8; ++q) {
+                                const int kq = 16 * s2 + 8 * (lane >> 5) + q;
+                                const bool ok = bc < n && kq < kw;
+                                const float xb = W[(int64_t)(kk0 + (ok ? kq : 0)) * n + (ok ? bc : 0)];
+                                bh[s2][q] = (typename L16::T)(ok ? xb : 0.0f);
+                            }
+                        float cv[16], cn[16];
+                        load_cblock(W, n, rb0, bc, lane, true, cv);
+                        for (int bi = 0; bi < nbr; ++bi) {
+                            const int rb = rb0 + bi * 32, lr = bi * 32 + (lane & 31);
+                            load_cblock(W, n, rb + 32, bc, lane, bi + 1 < nbr, cn);
+                            floatx16 acc = floatx16{0};
+#pragma unroll
+                            for (int s2 = 0; s2 < 4; ++s2) {
+                                typename L16::V8 av;
+#pragma unroll
+                                for (int q = 0; q < 8; ++q) {
+                                    const float pv = panel[lr * kWP + 16 * s2 + 8 * (lane >> 5) + q];
+                                    av[q] = (typename L16::T)(lr < cr ? pv : 0.0f);
+                                }
+                                acc = L16::mfma(av, bh[s2], acc);
+                            }
+                            store_cblock(W, n, rb, bc, lane, cv, acc);
+#pragma unroll
+                            for (int v = 0; v < 16; ++v) cv[v] = cn[v];
+                        }
+                    } else {
+                        float bf[32];
+#pragma unroll
+                        for (int s1 = 0; s1 < 32; ++s1) {
+                            const int kq = 2 * s1 + (lane >> 5);
+                            bf[s1] = (bc < n && kq < kw) ? W[(int64_t)(kk0 + kq) * n + bc] : 0.0f;
+                        }
+                        float cv[16], cn[16];
+                        load_cblock(W, n, rb0, bc, lane, true, cv);
+                        for (int bi = 0; bi < nbr; ++bi) {
+                            const int rb = rb0 + bi * 32, lr = bi * 32 + (lane & 31);
+                            load_cblock(W, n, rb + 32, bc, lane, bi + 1 < nbr, cn);
+                            floatx16 acc = floatx16{0};
+#pragma unroll
+                            for (int s1 = 0; s1 < 32; ++s1) {
+                                const float pv = panel[lr * kWP + 2 * s1 + (lane >> 5)];
+                                acc = __builtin_amdgcn_mfma_f32_32x32x2f32(lr < cr ? pv : 0.0f, bf[s1], acc, 0, 0, 0);
+                            }
+                            store_cblock(W, n, rb, bc, lane, cv, acc);
+#pragma unroll
+                            for (int v = 0; v < 16; ++v) cv[v] = cn[v];
+                        }
+                    }
+                }
+            }
+        };
+        // update form 2: panels in pairs.  The first panel of a pair updates
+        // only the second's columns (after its U rows for every column to
+        // the right); the second panel, after its own interchanges, applies
+        // the first's update to its 32 rows right of it, forms its U rows,
+        // and one update of rank 64 (both panels' L columns) brings the rest
+        // of the matrix up to date -- half the trailing matrix's memory
+        // traffic of two rank-32 updates.  Row interchanges of the second
+        // panel are applied to whole rows, so they meet the deferred update
+        // consistently.
+        const bool pairs = upd == 2 && pb == PB;
+
         // ---------------- blocked LU with partial pivoting ----------------
         for (int k = 0; k < n; k += pb) {
             const int w = (n - k) < pb ? (n - k) : pb;
@@ -368,6 +534,13 @@ __global__ __launch_bounds__(NT) void k_batched(const BatchSys *__restrict__ sys
                 for (int q = tid; q < np; q += NT) perm[k + pdst[q]] = pst[q];
             }
             if (k + w >= n) break;
+            const bool second = pairs && ((k / PB) & 1);
+            const bool first = pairs && !second;
+            if (second) {
+                // the first panel's update of this panel's rows right of it
+                upd_blocks(k, w, k + w, n - k - w, k - PB, PB);
+                __syncthreads();
+            }
             // U12 = L11^{-1} A12 for rows [k, k+w), columns [k+w, n)
             for (int e = tid; e < w * w; e += NT) {
                 const int r = e / w, c = e - r * w;
@@ -406,6 +579,13 @@ __global__ __launch_bounds__(NT) void k_batched(const BatchSys *__restrict__ sys
                 }
             }
             __syncthreads();
+            if (first) {
+                // only the next panel's columns
+                const int w2 = (n - k - w) < PB ? (n - k - w) : PB;
+                upd_blocks(k + w, n - k - w, k + w, w2, k, w);
+            } else if (second) {
+                upd_wide(k + w, k - PB, PB + w);
+            } else
             // trailing update A22 -= L21 U12 (K = w <= 32) in 32 x 32 blocks
             if (upd == 1) {
                 // L21 staged in LDS once; wave wv takes block columns bj =

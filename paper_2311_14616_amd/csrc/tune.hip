@@ -49,7 +49,8 @@ bool tuning_valid(const mpir_batch_tuning *t) {
         if (t->nmax[k] < 1 || t->nmax[k] > batched_max_n()) return false;
         if (k > 0 && t->nmax[k] <= t->nmax[k - 1]) return false;
         if (t->panel[k] != 16 && t->panel[k] != 32) return false;
-        if (t->update[k] != 0 && t->update[k] != 1) return false;
+        if (t->update[k] < 0 || t->update[k] > 2) return false;
+        if (t->update[k] == 2 && t->panel[k] != 32) return false;
     }
     return t->nmax[t->nclass - 1] == batched_max_n();
 }
@@ -179,7 +180,7 @@ mpir_status mpir_batch_autotune(mpir_prec tw, mpir_prec tf, const char *cache_pa
     tune_defaults(&res);
     const int count = 2 * (cus > 0 ? cus : 64);     // two systems per compute unit
     const size_t esz = tw == MPIR_F64 ? 8 : 4;
-    const int cand_panel[] = {16, 32}, cand_upd[] = {0, 1};
+    const int cand_panel[] = {16, 32}, cand_upd[] = {0, 1, 2};
     mpir_status st = MPIR_OK;
     for (int k = 0; k < res.nclass && st == MPIR_OK; ++k) {
         const int lo = k ? res.nmax[k - 1] : 0;
@@ -203,6 +204,7 @@ mpir_status mpir_batch_autotune(mpir_prec tw, mpir_prec tf, const char *cache_pa
         double best = -1.0;
         for (int pw : cand_panel)
             for (int up : cand_upd) {
+                if (up == 2 && pw != 32) continue;      // panels in pairs: 32-column panels
                 mpir_batch_tuning one;
                 std::memset(&one, 0, sizeof one);
                 one.nclass = 1;

@@ -95,7 +95,11 @@ def test_batch_tuning_table_host_logic():
     assert (c0["panel"], c0["update"]) == (16, 1)
     # other precision pairs keep their own table
     assert M.batch_get_tuning(M.F64, M.F32).as_dict()["classes"][0]["panel"] == d0["classes"][0]["panel"]
-    for bad in ({"panel": 8}, {"update": 2}, {"nmax_last": 512}, {"nclass": 0}, {"nclass": 9}):
+    # panels in pairs (update form 2) need 32-column panels
+    t.panel[0], t.update[0] = 32, 2
+    M.batch_set_tuning(M.F64, M.F16, t)
+    for bad in ({"panel": 8}, {"update": 3}, {"update": -1}, {"panel": 16, "update": 2},
+                {"nmax_last": 512}, {"nclass": 0}, {"nclass": 9}):
         u = M.batch_get_tuning(M.F64, M.F16)
         if "panel" in bad:
             u.panel[1] = bad["panel"]

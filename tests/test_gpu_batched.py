@@ -57,7 +57,7 @@ def _one_config(M, panel, update):
 
 
 # every configuration the autotuner can pick: panel width x update form
-CONFIGS = [(None, None), (16, 0), (16, 1), (32, 0), (32, 1)]
+CONFIGS = [(None, None), (16, 0), (16, 1), (32, 0), (32, 1), (32, 2)]
 
 
 @pytest.mark.parametrize("cfg", CONFIGS, ids=lambda c: "default" if c[0] is None else f"p{c[0]}u{c[1]}")
@@ -201,7 +201,8 @@ def test_autotune_table_and_cache(M, tmp_path, tf):
         say(d1)
         assert not d1["from_cache"] and d1["classes"][-1]["nmax"] == 1024
         for c in d1["classes"]:
-            assert c["panel"] in (16, 32) and c["update"] in (0, 1) and c["ms"] > 0
+            assert c["panel"] in (16, 32) and c["update"] in (0, 1, 2) and c["ms"] > 0
+            assert c["update"] != 2 or c["panel"] == 32
         assert M.batch_get_tuning(M.F64, T).as_dict()["classes"] == d1["classes"]
         t2 = M.batch_autotune(M.F64, T, cache)
         d2 = t2.as_dict()
