@@ -324,6 +324,21 @@ void mpir_prof_enable(int32_t on);
 void mpir_prof_reset(void);
 mpir_status mpir_prof_get(int32_t kind, double *ms, int64_t *launches, double *work);
 
+/* Device-side phase times of the batched kernel (mpir_ir_solve_batched,
+ * mpir_batch_run, the autotuner), summed over its workgroups and over every
+ * launch on the current device since the last reset.  ms (host, 7 doubles)
+ * receives milliseconds of workgroup time per phase: 0 = the copy
+ * A_F = fl_F(A) and ||A||_inf, 1 = panel factorizations, 2 = row interchanges
+ * outside the panels, 3 = U rows (U12 = L11^{-1} A12, and in update form 2
+ * the first panel's update of the second's rows), 4 = trailing updates, 5 =
+ * scaling of the residual and the two triangular solves, 6 = the update of
+ * x, the binary64 residual and the termination tests.  Dividing a phase by
+ * the number of workgroups (one per compute unit) gives its share of the
+ * launch's duration.  reset != 0 clears the counters after reading them (ms
+ * may then be NULL).  Synchronises the device. */
+#define MPIR_BATCH_PHASES 7
+mpir_status mpir_batch_phase_times(double *ms, int32_t reset);
+
 #ifdef __cplusplus
 }
 #endif

@@ -15,6 +15,10 @@
 
 namespace mpir {
 
+// Device time of each phase of the batched kernel, summed over its
+// workgroups since the last reset (wall-clock ticks; see mpir_batch_phase_times).
+__device__ unsigned long long g_batch_phase[kBatchPhases];
+
 struct BatchSys {
     int64_t n, lda;
     const void *A;
@@ -192,6 +196,19 @@ __global__ __launch_bounds__(NT) void k_batched(const BatchSys *__restrict__ sys
         const int si = s_sys;
         if (si < 0) break;
         const long long t_start = wall_clock64();
+        // phase timer: thread 0 adds the ticks since the previous mark.  (A
+        // macro, not a lambda: with the lambda the compiler's allocation of
+        // the binary32 kernel spilled 180 registers instead of 47, and the
+        // batch ran 10% slower.)
+        long long t_ph = t_start;
+#define MARK(ph)                                                                        \
+    do {                                                                                \
+        if (tid == 0) {                                                                 \
+            const long long t_ = wall_clock64();                                        \
+            atomicAdd(&g_batch_phase[ph], (unsigned long long)(t_ - t_ph));             \
+            t_ph = t_;                                                                  \
+        }                                                                               \
+    } while (0)
         const BatchSys S = sys[si];
         const int n = (int)S.n;
         const int64_t lda = S.lda;
@@ -416,8 +433,10 @@ __global__ __launch_bounds__(NT) void k_batched(const BatchSys *__restrict__ sys
         // consistently.
         const bool pairs = upd == 2 && pb == PB;
 
+        MARK(0);
         // ---------------- blocked LU with partial pivoting ----------------
         for (int k = 0; k < n; k += pb) {
+            if (k > 0) { __syncthreads(); MARK(4); }
             const int w = (n - k) < pb ? (n - k) : pb;
             const int m = n - k;
             __syncthreads();
@@ -463,7 +482,23 @@ __global__ __launch_bounds__(NT) void k_batched(const BatchSys *__restrict__ sys
                         float l = panel[r * PP + j] / pj;
                         if (RD) l = round_lo<RD>(l);
                         panel[r * PP + j] = l;
-                        for (int c = j + 1; c < w; ++c) {
+                        // eight columns per step: their LDS reads in flight
+                        // together (one column at a time waited for each read)
+                        int c = j + 1;
+                        for (; c + 8 <= w; c += 8) {
+                            float pr[8], x[8];
+#pragma unroll
+                            for (int u = 0; u < 8; ++u) {
+                                pr[u] = panel[j * PP + c + u];
+                                x[u] = panel[r * PP + c + u];
+                            }
+#pragma unroll
+                            for (int u = 0; u < 8; ++u) {
+                                const float prod = l * pr[u];
+                                panel[r * PP + c + u] = x[u] - prod;
+                            }
+                        }
+                        for (; c < w; ++c) {
                             const float prod = l * panel[j * PP + c];
                             panel[r * PP + c] = panel[r * PP + c] - prod;
                         }
@@ -481,6 +516,7 @@ __global__ __launch_bounds__(NT) void k_batched(const BatchSys *__restrict__ sys
                 const int r = e / w, c = e - r * w;
                 W[(int64_t)(k + r) * n + k + c] = panel[r * PP + c];
             }
+            MARK(1);
             // composed row permutation of this panel (positions >= k)
             if (tid == 0) s_extra = 0;
             __syncthreads();
@@ -533,6 +569,7 @@ __global__ __launch_bounds__(NT) void k_batched(const BatchSys *__restrict__ sys
                 __syncthreads();
                 for (int q = tid; q < np; q += NT) perm[k + pdst[q]] = pst[q];
             }
+            MARK(2);
             if (k + w >= n) break;
             const bool second = pairs && ((k / PB) & 1);
             const bool first = pairs && !second;
@@ -579,6 +616,7 @@ __global__ __launch_bounds__(NT) void k_batched(const BatchSys *__restrict__ sys
                 }
             }
             __syncthreads();
+            MARK(3);
             if (first) {
                 // only the next panel's columns
                 const int w2 = (n - k - w) < PB ? (n - k - w) : PB;
@@ -712,6 +750,7 @@ __global__ __launch_bounds__(NT) void k_batched(const BatchSys *__restrict__ sys
             }
         }
         __syncthreads();
+        MARK(4);
         const int info = s_info;
         const long long t_lu = wall_clock64();
 
@@ -864,6 +903,7 @@ __global__ __launch_bounds__(NT) void k_batched(const BatchSys *__restrict__ sys
                     }
                     __syncthreads();
                 }
+                MARK(5);
                 // d = sigma * y, x <- fl_W(x + d)
                 double dm = 0.0;
                 for (int i = tid; i < n; i += NT) {
@@ -898,6 +938,7 @@ __global__ __launch_bounds__(NT) void k_batched(const BatchSys *__restrict__ sys
                 }
                 rnorm = block_max(rm, redb);
                 xnorm = block_max(xm, redb);
+                MARK(6);
                 ++it;
                 if (tid == 0) { hist_r[it] = rnorm; hist_d[it - 1] = dnorm; }
                 // every thread holds the same norms: the tests need no barrier
@@ -920,6 +961,7 @@ __global__ __launch_bounds__(NT) void k_batched(const BatchSys *__restrict__ sys
             }
         }
         __syncthreads();
+        MARK(6);
         // ---------------- report ----------------
         if (tid == 0) {
             mpir_report &R = reps[si];
@@ -946,6 +988,13 @@ __global__ __launch_bounds__(NT) void k_batched(const BatchSys *__restrict__ sys
 }  // namespace
 
 int batched_max_n() { return NMAX; }
+
+hipError_t batched_phase_ticks(unsigned long long *out, bool reset) {
+    hipError_t e = hipMemcpyFromSymbol(out, HIP_SYMBOL(g_batch_phase), sizeof(unsigned long long) * kBatchPhases);
+    if (e != hipSuccess || !reset) return e;
+    const unsigned long long zero[kBatchPhases] = {};
+    return hipMemcpyToSymbol(HIP_SYMBOL(g_batch_phase), zero, sizeof zero);
+}
 
 hipError_t launch_batched(int tw, int tf, const BatchSys *sys, const int32_t *order, int nsys,
                           uint32_t *queue, const BatchTerm &term, mpir_report *reps, int nwg,

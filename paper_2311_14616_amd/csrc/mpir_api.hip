@@ -1450,6 +1450,21 @@ void mpir_prof_reset(void) {
     for (auto &v : g_prof.recs) v.clear();
 }
 
+mpir_status mpir_batch_phase_times(double *ms, int32_t reset) {
+    static_assert(MPIR_BATCH_PHASES == mpir::kBatchPhases, "phase count of the batched kernel");
+    if (!ms && !reset) return MPIR_ERR_ARG;
+    int dev = 0, khz = 0;
+    HIPCHK(hipGetDevice(&dev));
+    HIPCHK(hipDeviceGetAttribute(&khz, hipDeviceAttributeWallClockRate, dev));
+    if (khz <= 0) return MPIR_ERR_HIP;
+    HIPCHK(hipDeviceSynchronize());
+    unsigned long long t[mpir::kBatchPhases];
+    HIPCHK(mpir::batched_phase_ticks(t, reset != 0));
+    if (ms)
+        for (int k = 0; k < mpir::kBatchPhases; ++k) ms[k] = (double)t[k] / (double)khz;
+    return MPIR_OK;
+}
+
 mpir_status mpir_prof_get(int32_t kind, double *ms, int64_t *launches, double *work) {
     if (kind < 0 || kind >= 6) return MPIR_ERR_ARG;
     std::lock_guard<std::mutex> g(g_prof.mu);

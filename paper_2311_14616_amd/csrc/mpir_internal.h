@@ -255,6 +255,12 @@ hipError_t launch_terminate(IrState *st, hipStream_t s);
 struct BatchSys;
 struct BatchTerm;
 int batched_max_n();
+// Phases of the batched kernel with device timers: downcast, panel
+// factorization, interchanges, U rows, trailing update, substitutions,
+// residual and update of x.  batched_phase_ticks copies the accumulated
+// wall-clock ticks (summed over workgroups) and optionally resets them.
+constexpr int kBatchPhases = 7;
+hipError_t batched_phase_ticks(unsigned long long *out, bool reset);
 // Per-system configuration word of the batched kernel for a system of size n
 // (panel width | update form << 8) from the tuning table tab, or from the
 // process-wide table for (tw, tf) when tab is NULL.

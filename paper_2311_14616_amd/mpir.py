@@ -25,6 +25,7 @@ OK, ERR_SINGULAR, ERR_ARG, ERR_ALLOC, ERR_HIP, ERR_NONFINITE, ERR_RANGE, ERR_STA
 STOP_NAMES = {0: "converged", 1: "stagnated", 2: "dstagnated", 3: "litmax", 4: "nonfinite"}
 HIST_MAX = 64
 PROF_GEMM, PROF_PANEL, PROF_TRSV, PROF_GEMV, PROF_DOWNCAST = 0, 1, 2, 3, 4
+BATCH_PHASES = ("downcast", "panel", "interchanges", "u_rows", "update", "solves", "residual")
 
 EXPORTS = [
     "mpir_term_default", "mpir_factor", "mpir_refactor", "mpir_solve", "mpir_ir_solve",
@@ -33,6 +34,7 @@ EXPORTS = [
     "mpir_get_factors", "mpir_residual", "mpir_residual_noalloc", "mpir_prof_enable", "mpir_prof_reset", "mpir_prof_get",
     "mpir_batch_create", "mpir_batch_run", "mpir_batch_destroy",
     "mpir_batch_get_tuning", "mpir_batch_set_tuning", "mpir_batch_autotune",
+    "mpir_batch_phase_times",
 ]
 
 
@@ -138,6 +140,8 @@ def lib():
         L.mpir_prof_enable.argtypes = [i32]
         L.mpir_prof_get.restype = C.c_int
         L.mpir_prof_get.argtypes = [i32, P(d), P(i64), P(d)]
+        L.mpir_batch_phase_times.restype = C.c_int
+        L.mpir_batch_phase_times.argtypes = [P(d), i32]
         _lib = L
     return _lib
 
@@ -485,3 +489,11 @@ def prof_get(kind: int):
     ms, cnt, work = C.c_double(0), C.c_int64(0), C.c_double(0)
     _check(lib().mpir_prof_get(kind, C.byref(ms), C.byref(cnt), C.byref(work)), "mpir_prof_get")
     return ms.value, cnt.value, work.value
+
+
+def batch_phase_times(reset: bool = False) -> dict:
+    """Workgroup milliseconds of each phase of the batched kernel since the
+    last reset, summed over workgroups and launches on the current device."""
+    ms = (C.c_double * len(BATCH_PHASES))()
+    _check(lib().mpir_batch_phase_times(ms, 1 if reset else 0), "mpir_batch_phase_times")
+    return dict(zip(BATCH_PHASES, list(ms)))

@@ -71,6 +71,7 @@ def test_argument_validation_needs_no_device(M):
     assert L.mpir_refactor(None, dummy, 8, None) == M.ERR_ARG
     assert L.mpir_get_factors(None, dummy, None) == M.ERR_ARG
     assert L.mpir_prof_get(99, None, None, None) == M.ERR_ARG
+    assert L.mpir_batch_phase_times(None, 0) == M.ERR_ARG
     L.mpir_destroy(None)
 
 

@@ -142,6 +142,34 @@ def test_batched_graph_replays_match_eager(M):
     g.destroy()
 
 
+def test_batched_phase_times(M):
+    # the kernel's per-phase device timers cover each system from its first
+    # step to its report: their sum over phases matches the per-system
+    # factor + refinement times of the reports
+    say("batched phase times")
+    systems = _systems(seed=5, count=10)
+    As = [dev(at) for _, at, _ in systems]
+    bs = [dev(b) for _, _, b in systems]
+    xs = [torch.empty_like(b) for b in bs]
+    M.batch_phase_times(reset=True)
+    assert sum(M.batch_phase_times().values()) == 0.0
+    bt = M.Batch(As, bs, xs, M.F32, term_parms=M.term(tol_rel=1e-14, litmax=20), use_graph=False)
+    st, reps = bt.run()
+    bt.destroy()
+    assert st == M.OK
+    ph = M.batch_phase_times(reset=True)
+    assert set(ph) == set(M.BATCH_PHASES)
+    assert all(v >= 0.0 for v in ph.values())
+    for k in ("downcast", "panel", "interchanges", "u_rows", "update", "solves", "residual"):
+        assert ph[k] > 0.0, k
+    tot = sum(ph.values())
+    rep_tot = sum(r.t_factor_ms + r.t_ir_ms for r in reps)
+    lu = sum(ph[k] for k in ("downcast", "panel", "interchanges", "u_rows", "update"))
+    assert abs(tot - rep_tot) <= 0.02 * rep_tot + 1e-3, (tot, rep_tot)
+    assert abs(lu - sum(r.t_factor_ms for r in reps)) <= 0.02 * lu + 1e-3
+    assert sum(M.batch_phase_times().values()) == 0.0
+
+
 def test_batched_per_system_failures(M):
     say("batched failures")
     good = I.batched_system(40, 1.0, np.zeros(40))
