@@ -228,9 +228,14 @@ __global__ __launch_bounds__(256) void k_gemm_32(float *__restrict__ a, int64_t 
     // epilogue: lane l, register v -> row 8*(v/4) + 4*(l/32) + v%4, col l%32.
     // Binary16 operands (the panel's updates of TF = F16): every C load of a
     // block is issued before the first store (FP16 factorization 258 ->
-    // 248 ms at N = 32768).  Binary32: one element at a time -- the batched
-    // form raised this instance's registers and cost the FP32
-    // factorization 25% (350 against 443 ms).
+    // 248 ms at N = 32768).  Binary32 trailing update (role 0): c + (-acc)
+    // by a no-return atomic add at the L2, which rounds as the subtraction
+    // does (IEEE, subnormals kept) and leaves no load round trip in the
+    // wave (FP32 factorization about 1.5% faster at N = 32768); every C
+    // element is added to once per launch, so nothing races.  Binary32
+    // in-panel updates (role 1): one element at a time -- the batched form
+    // raised the registers and cost the FP32 factorization 25% (350
+    // against 443 ms), the atomic form slowed the panel stream.
 #pragma unroll
     for (int i = 0; i < MI; ++i)
 #pragma unroll
@@ -254,7 +259,10 @@ __global__ __launch_bounds__(256) void k_gemm_32(float *__restrict__ a, int64_t 
                     const int64_t row = tm + wm + i * 32 + 8 * (v >> 2) + 4 * (lane >> 5) + (v & 3);
                     if (row < m && col < nc) {
                         float *p = a + (r0 + row) * ld + c0 + col;
-                        *p = *p - acc[i][j][v];
+                        if constexpr (ROLE == 0)
+                            __hip_atomic_fetch_add(p, -acc[i][j][v], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+                        else
+                            *p = *p - acc[i][j][v];
                     }
                 }
             }
@@ -509,8 +517,26 @@ __global__ __launch_bounds__(256) void k_gemm_f64(double *__restrict__ a, int64_
         buf ^= 1;
     }
     // v_mfma_f64_16x16x4f64 output: lane l, register v -> row (l/16) + 4*v,
-    // col l%16 (rows interleaved, unlike the binary32 16x16 layout)
-    // (every C load of the tile issued before the first store)
+    // col l%16 (rows interleaved, unlike the binary32 16x16 layout).
+    // Trailing update (role 0): c + (-acc) by a no-return atomic add at the
+    // L2 (IEEE rounding, subnormals kept; FP64 factorization 677 -> 659 ms
+    // at N = 32768).  In-panel updates: every C load of the tile issued
+    // before the first store (the atomic form slowed the panel stream).
+    if constexpr (ROLE == 0) {
+#pragma unroll
+        for (int i = 0; i < MI; ++i)
+#pragma unroll
+            for (int j = 0; j < NJ; ++j)
+#pragma unroll
+                for (int v = 0; v < 4; ++v) {
+                    const int64_t row = tm + wm + i * 16 + (lane >> 4) + 4 * v;
+                    const int64_t col = tn + wn + j * 16 + (lane & 15);
+                    if (row < m && col < nc)
+                        __hip_atomic_fetch_add(a + (r0 + row) * ld + c0 + col, -acc[i][j][v], __ATOMIC_RELAXED,
+                                               __HIP_MEMORY_SCOPE_AGENT);
+                }
+        return;
+    }
     double cv[MI][NJ][4];
 #pragma unroll
     for (int i = 0; i < MI; ++i)

@@ -1,0 +1,73 @@
+"""Exact factorizations: a matrix built as A = L U with L unit lower
+triangular (off-diagonal entries 0, +-1/4, +-1/2), U upper triangular with
+integer entries and |u_jj| >= 40, scaled by a power of two.  Partial
+pivoting then keeps every row in place (after j elimination steps column j
+holds l_ij u_jj below u_jj, and |l_ij| <= 1/2), each multiplier is l_ij
+exactly, and every product and sum of the elimination is a multiple of
+2^(s-2) below 2^(s+8): exact in binary32 and binary64.  So the factors of
+an IEEE implementation of the factorization step of Algorithm IR are L and
+2^s U bit for bit, whatever order the trailing updates sum in.  The scale
+puts the entries in and around the subnormal range of TF, where a unit that
+flushed subnormal operands or results to zero would show."""
+import sys
+
+import numpy as np
+import pytest
+
+pytestmark = pytest.mark.gpu
+torch = pytest.importorskip("torch")
+DEV = "cuda:0"
+
+
+def say(*a):
+    print(*a, flush=True)
+    sys.stdout.flush()
+
+
+@pytest.fixture(scope="module")
+def M():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    from paper_2311_14616_amd import mpir
+    mpir.lib()
+    return mpir
+
+
+def exact_lu(n, seed):
+    rng = np.random.default_rng(seed)
+    mask = rng.random((n, n)) < 0.05
+    vals = rng.choice([-0.5, -0.25, 0.25, 0.5], size=(n, n))
+    L = np.eye(n) + np.tril(mask * vals, -1)
+    U = np.triu(rng.integers(-8, 9, size=(n, n)).astype(np.float64), 1)
+    U[np.diag_indices(n)] = rng.choice([-64.0, -48.0, -40.0, 40.0, 48.0, 64.0], size=n)
+    A = L @ U                       # exact: multiples of 1/4 well below 2^53
+    assert np.abs(A).max() < 2.0**8
+    return L, U, A
+
+
+# (TF, scale exponent s): binary32 subnormals lie below 2^-126, binary64
+# below 2^-1022; the entries span 2^(s-2) .. 2^(s+7), so with s = -128
+# (-1024) about a third of the entries of A and of U are subnormal
+CASES = [("f32", -128), ("f64", -1024), ("f32", 0), ("f64", 0)]
+
+
+@pytest.mark.parametrize("tfname,s", CASES, ids=[f"{t}_s{s}" for t, s in CASES])
+def test_exact_factors(M, tfname, s):
+    n = 1600        # several 512-column panels: leaves, in-panel and trailing updates
+    say(f"exact LU tf={tfname} n={n} scale=2^{s}")
+    L, U, A = exact_lu(n, seed=11)
+    As = A * 2.0**s
+    assert np.array_equal(As / 2.0**s, A)            # the scaling is exact in binary64
+    tf = {"f32": M.F32, "f64": M.F64}[tfname]
+    At = torch.from_numpy(np.ascontiguousarray(As.T)).to(DEV)   # column-major A
+    f = M.Factorization(At, tf, M.F64)
+    assert f.info == 0
+    lu, ipiv = f.factors()
+    f.destroy()
+    assert np.array_equal(ipiv, np.arange(n, dtype=np.int32))
+    dt = np.float32 if tfname == "f32" else np.float64
+    want = (np.tril(L, -1) + U * 2.0**s).astype(dt)
+    assert np.array_equal(want.astype(np.float64), (np.tril(L, -1) + U * 2.0**s))   # representable in TF
+    got = lu.cpu().numpy()
+    bad = np.argwhere(got != want)
+    assert bad.size == 0, (len(bad), bad[:5].tolist(), [(float(got[i, j]), float(want[i, j])) for i, j in bad[:5]])
