@@ -103,7 +103,12 @@ void mpir_term_default(mpir_term *t);
  * right-looking LU with partial pivoting of A_F in TF.
  *  - The handle BORROWS dA: it must stay allocated and unchanged until
  *    mpir_refactor or mpir_destroy (the residual reads it).
- *  - The handle OWNS the TF copy, the pivots and all workspace.
+ *  - The handle OWNS the TF copy, the pivots and all workspace.  One part
+ *    of it, the panel factorization's exchange area (about 205 KB), is
+ *    uncached device memory taken from a per-device pool of the library:
+ *    mpir_destroy returns it to the pool, not to the runtime, so the pool
+ *    holds as many areas as handles were ever alive at once on that device,
+ *    until the process ends.
  *  - F16 factorization: binary16 L and U, binary32 trailing matrix (each U
  *    row rounded to binary16 when it becomes final, each multiplier rounded
  *    to binary16 when formed; MFMA products of binary16 operands accumulate
