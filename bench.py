@@ -77,13 +77,20 @@ def host_cpu_model() -> str:
     return "unknown"
 
 
-def cpu_baseline(n_sample: int, n_full: int):
+def cpu_baseline(n_sample: int, n_full: int, at_full=None):
     """Time the oracle (plain C, OpenMP on the host cores) on a bounded sample
-    of the workload -- the same operator at N = n_sample -- and scale each
-    part by its own order: the downcast and LU by (N/n)^3, one correction
-    (the FP64 residual and the substitutions with the factors, timed on
-    their own) by (N/n)^2, times the sample's number of corrections.  The
-    whole Algorithm IR solve of the sample is timed too, for reference."""
+    of the workload and scale it to the full size N: the downcast and LU of
+    the same operator at N = n_sample by (N/n)^3, and one correction (the
+    FP64 residual and the substitutions with the factors) times the sample's
+    number of corrections.  With the full matrix given (at_full, a device
+    tensor in column-major storage) the correction is timed at the full size
+    itself -- its O(N^2) work takes seconds -- because a correction timed at
+    a power-of-two sample size does not scale by (N/n)^2: the oracle's
+    strided column accesses make its cache behaviour depend on the size
+    (5.3 s at N = 8192 against 0.09 s at N = 8000 on the same host).  The
+    substitutions there run on the operator's own triangles with the
+    identity permutation: the same work as with the factors.  The whole
+    Algorithm IR solve of the sample is timed too, for reference."""
     from oracle import oracle as O
     from paper_2311_14616_amd import inputs as I
     import numpy as np
@@ -97,22 +104,36 @@ def cpu_baseline(n_sample: int, n_full: int):
     t0 = time.perf_counter()
     r = O.ir_solve(at, b, O.F32, tol_rel=1e-14, litmax=20)
     t_all = time.perf_counter() - t0
-    x = np.zeros(n_sample)
-    t_corr = float("inf")
-    for _ in range(2):
-        t0 = time.perf_counter()
-        res = O.residual(at, b, x)
-        O.lu_solve(lu_rm, ipiv, res, O.default_ts(O.F32))
-        t_corr = min(t_corr, time.perf_counter() - t0)
     s3, s2 = (n_full / n_sample) ** 3, (n_full / n_sample) ** 2
-    value_s = t_lu * s3 + r.n_iter * t_corr * s2
+    if at_full is not None:
+        ah = at_full.cpu().numpy()
+        bh = ah.sum(axis=0)                      # A * ones (A in column-major storage)
+        t0 = time.perf_counter()
+        res = O.residual(ah, bh, np.zeros(n_full))
+        O.lu_solve(ah, np.arange(n_full, dtype=np.int32), res, O.default_ts(O.F32))
+        t_corr = time.perf_counter() - t0
+        del ah, bh, res
+        corr_scale, corr_at = 1.0, n_full
+    else:
+        x = np.zeros(n_sample)
+        t_corr = float("inf")
+        for _ in range(2):
+            t0 = time.perf_counter()
+            res = O.residual(at, b, x)
+            O.lu_solve(lu_rm, ipiv, res, O.default_ts(O.F32))
+            t_corr = min(t_corr, time.perf_counter() - t0)
+        corr_scale, corr_at = s2, n_sample
+    value_s = t_lu * s3 + r.n_iter * t_corr * corr_scale
+    corr_txt = (f"{r.n_iter} corrections of {t_corr:.3f} s (FP64 residual + substitutions, timed at N={n_full})"
+                if corr_at == n_full else
+                f"{r.n_iter} corrections of {t_corr:.3f} s (FP64 residual + substitutions) x (N/{n_sample})^2")
     out = {"value": round(value_s * 1e3, 1), "unit": "ms", "cores": O.num_threads(), "kind": "oracle",
            "host_cpu": host_cpu_model(), "host_nproc": os.cpu_count(),
-           "sample": f"oracle at N={n_sample} on the same operator: downcast + LU {t_lu:.2f} s x (N/{n_sample})^3, "
-                     f"{r.n_iter} corrections of {t_corr:.3f} s (FP64 residual + substitutions) x (N/{n_sample})^2, "
-                     f"to N={n_full}",
+           "sample": f"oracle on the same operator: downcast + LU at N={n_sample} {t_lu:.2f} s x (N/{n_sample})^3, "
+                     f"{corr_txt}, to N={n_full}",
            "sample_n_iter": int(r.n_iter), "sample_factor_s": round(t_lu, 3),
-           "sample_correction_s": round(t_corr, 4), "sample_ir_solve_s": round(t_all, 3)}
+           "sample_correction_s": round(t_corr, 4), "correction_timed_at_n": int(corr_at),
+           "sample_ir_solve_s": round(t_all, 3)}
     # the one full-size run of the oracle on a GPU machine's host, if recorded
     # (oracle/time_full_size.py)
     full = os.path.join(ROOT, "oracle", f"cpu_time_n{n_full}.json")
@@ -538,7 +559,7 @@ def main():
             log(f"[bench]   {out['batched'][-1]}")
     if not args.no_cpu:
         log(f"[bench] CPU oracle sample N={args.cpu_sample}")
-        out["cpu_baseline"] = cpu_baseline(args.cpu_sample, n)
+        out["cpu_baseline"] = cpu_baseline(args.cpu_sample, n, At if args.alpha == 1.0 else None)
     print(json.dumps(out), flush=True)
 
 
