@@ -199,7 +199,11 @@ hipError_t ps_acquire(PanelSync **out, int *dev) {
                 return hipSuccess;
             }
     }
-    return hipExtMallocWithFlags((void **)out, panel_sync_bytes(), hipDeviceMallocUncached);
+    e = hipExtMallocWithFlags((void **)out, panel_sync_bytes(), hipDeviceMallocUncached);
+    if (e == hipSuccess) return e;
+    // a device without uncached allocations: ordinary memory (pooled the same way)
+    (void)hipGetLastError();
+    return hipMalloc((void **)out, panel_sync_bytes());
 }
 
 void ps_release(PanelSync *ps, int dev) {

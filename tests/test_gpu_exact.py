@@ -71,3 +71,31 @@ def test_exact_factors(M, tfname, s):
     got = lu.cpu().numpy()
     bad = np.argwhere(got != want)
     assert bad.size == 0, (len(bad), bad[:5].tolist(), [(float(got[i, j]), float(want[i, j])) for i, j in bad[:5]])
+
+
+def test_handles_alive_together(M):
+    # each handle owns its leaf exchange area (a pooled area comes back only
+    # when its handle is destroyed): factorizations of handles alive at the
+    # same time, and of a handle created after one of them was destroyed,
+    # stay exact
+    n = 1100
+    say(f"exact LU, several handles alive, n={n}")
+    cases = [exact_lu(n, seed) for seed in (21, 22, 23, 24)]
+    def make(k):
+        L, U, A = cases[k]
+        At = torch.from_numpy(np.ascontiguousarray(A.T)).to(DEV)
+        return M.Factorization(At, M.F32, M.F64), (np.tril(L, -1) + U).astype(np.float32)
+    def check(f, want):
+        lu, ipiv = f.factors()
+        assert np.array_equal(ipiv, np.arange(n, dtype=np.int32))
+        assert np.array_equal(lu.cpu().numpy(), want)
+    hs = [make(k) for k in range(3)]
+    for f, want in hs:
+        check(f, want)
+    hs[1][0].destroy()
+    h3 = make(3)
+    check(h3[0], h3[1])
+    for f, want in (hs[0], hs[2]):
+        check(f, want)
+        f.destroy()
+    h3[0].destroy()
