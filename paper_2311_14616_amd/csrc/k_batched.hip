@@ -1026,6 +1026,7 @@ __global__ __launch_bounds__(NT) void k_batched(const BatchSys *__restrict__ sys
         __syncthreads();
     }
 }
+#undef MARK
 
 }  // namespace
 
