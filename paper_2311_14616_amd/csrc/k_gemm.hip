@@ -229,10 +229,11 @@ __global__ __launch_bounds__(256) void k_gemm_32(float *__restrict__ a, int64_t 
     // Binary16 operands (the panel's updates of TF = F16): every C load of a
     // block is issued before the first store (FP16 factorization 258 ->
     // 248 ms at N = 32768).  Binary32 trailing update (role 0): c + (-acc)
-    // by a no-return atomic add at the L2, which rounds as the subtraction
-    // does (IEEE, subnormals kept) and leaves no load round trip in the
-    // wave (FP32 factorization about 1.5% faster at N = 32768); every C
-    // element is added to once per launch, so nothing races.  Binary32
+    // by a no-return atomic add, carried out in the memory system beyond the
+    // L2, which rounds as the subtraction does (IEEE, subnormals kept) and
+    // leaves no load round trip in the wave (FP32 factorization about 1.5%
+    // faster at N = 32768); every C element is added to once per launch,
+    // and no other kernel touches those columns meanwhile.  Binary32
     // in-panel updates (role 1): one element at a time -- the batched form
     // raised the registers and cost the FP32 factorization 25% (350
     // against 443 ms), the atomic form slowed the panel stream.
@@ -518,9 +519,9 @@ __global__ __launch_bounds__(256) void k_gemm_f64(double *__restrict__ a, int64_
     }
     // v_mfma_f64_16x16x4f64 output: lane l, register v -> row (l/16) + 4*v,
     // col l%16 (rows interleaved, unlike the binary32 16x16 layout).
-    // Trailing update (role 0): c + (-acc) by a no-return atomic add at the
-    // L2 (IEEE rounding, subnormals kept; FP64 factorization 677 -> 659 ms
-    // at N = 32768).  In-panel updates: every C load of the tile issued
+    // Trailing update (role 0): c + (-acc) by a no-return atomic add, as in
+    // the binary32 kernel (IEEE rounding, subnormals kept; FP64
+    // factorization 677 -> 659 ms at N = 32768).  In-panel updates: every C load of the tile issued
     // before the first store (the atomic form slowed the panel stream).
     if constexpr (ROLE == 0) {
 #pragma unroll
