@@ -116,6 +116,32 @@ def test_batched_extended_residual(M, orc):
         assert np.abs(x.cpu().numpy().astype(np.float64) - xp).max() / np.abs(xp).max() <= 4 * 2.0**-24
 
 
+@pytest.mark.parametrize("cfg", CONFIGS[1:], ids=lambda c: f"p{c[0]}u{c[1]}")
+def test_batched_extended_residual_every_form(M, orc, cfg):
+    # TW = F32 with TR = F64 (stop by eq. wilkterm) through every tuned panel
+    # width and update form, on sizes that span several panels and pairs
+    say(f"batched tw=f32 tr=f64 cfg={cfg}")
+    M.batch_set_tuning(M.F32, M.F32, _one_config(M, *cfg))
+    try:
+        ns = [33, 100, 257, 513, 700]
+        sysl = [I.wilkinson_operator(n, 1e4, seed=200 + n) for n in ns]
+        As = [dev(s[0]) for s in sysl]
+        bs = [dev(s[1]) for s in sysl]
+        xs = [torch.empty_like(b) for b in bs]
+        bt = M.Batch(As, bs, xs, M.F32, term_parms=M.term(litmax=20), use_graph=False)
+        st, reps = bt.run()
+        bt.destroy()
+        assert st == M.OK
+        for (at, b, _, _), x, rep in zip(sysl, xs, reps):
+            ref = orc.ir_solve(at, b, orc.F32, tr=orc.F64, litmax=20)
+            assert rep.stop_name == ref.stop_name
+            assert abs(rep.n_iter - ref.n_iter) <= 1
+            xp, _, _ = orc.solve_f64(at, b)
+            assert np.abs(x.cpu().numpy().astype(np.float64) - xp).max() / np.abs(xp).max() <= 4 * 2.0**-24
+    finally:
+        M.batch_set_tuning(M.F32, M.F32, None)
+
+
 def test_batched_graph_replays_match_eager(M):
     say("batched graph replay")
     systems = _systems(seed=3, count=12)
