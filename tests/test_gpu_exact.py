@@ -46,9 +46,12 @@ def exact_lu(n, seed):
 
 
 # (TF, scale exponent s): binary32 subnormals lie below 2^-126, binary64
-# below 2^-1022; the entries span 2^(s-2) .. 2^(s+7), so with s = -128
-# (-1024) about a third of the entries of A and of U are subnormal
-CASES = [("f32", -128), ("f64", -1024), ("f32", 0), ("f64", 0)]
+# below 2^-1022, binary16 below 2^-14; the entries span 2^(s-2) .. 2^(s+7),
+# so with s = -128 (-1024, -16) about a third of the entries of A and of U
+# are subnormal.  Binary16 factors (f16mixed: binary16 L and U, binary32
+# trailing matrix) are exact too: every entry is a multiple of 2^(s-2)
+# below 2^(s+7), within binary16's 11 significant bits.
+CASES = [("f32", -128), ("f64", -1024), ("f32", 0), ("f64", 0), ("f16", 0), ("f16", -16)]
 
 
 @pytest.mark.parametrize("tfname,s", CASES, ids=[f"{t}_s{s}" for t, s in CASES])
@@ -58,14 +61,14 @@ def test_exact_factors(M, tfname, s):
     L, U, A = exact_lu(n, seed=11)
     As = A * 2.0**s
     assert np.array_equal(As / 2.0**s, A)            # the scaling is exact in binary64
-    tf = {"f32": M.F32, "f64": M.F64}[tfname]
+    tf = {"f32": M.F32, "f64": M.F64, "f16": M.F16}[tfname]
     At = torch.from_numpy(np.ascontiguousarray(As.T)).to(DEV)   # column-major A
     f = M.Factorization(At, tf, M.F64)
     assert f.info == 0
     lu, ipiv = f.factors()
     f.destroy()
     assert np.array_equal(ipiv, np.arange(n, dtype=np.int32))
-    dt = np.float32 if tfname == "f32" else np.float64
+    dt = {"f32": np.float32, "f64": np.float64, "f16": np.float16}[tfname]
     want = (np.tril(L, -1) + U * 2.0**s).astype(dt)
     assert np.array_equal(want.astype(np.float64), (np.tril(L, -1) + U * 2.0**s))   # representable in TF
     got = lu.cpu().numpy()
