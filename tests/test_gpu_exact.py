@@ -33,13 +33,21 @@ def M():
     return mpir
 
 
-def exact_lu(n, seed):
+def exact_lu(n, seed, sparse=False):
+    """sparse: few nonzeros of L and U (off-diagonal U entries +-1, pivots
+    +-8 or +-16), so that every entry of A and of the factors has at most
+    eight significant bits (exact in bfloat16)."""
     rng = np.random.default_rng(seed)
-    mask = rng.random((n, n)) < 0.05
+    mask = rng.random((n, n)) < (0.002 if sparse else 0.05)
     vals = rng.choice([-0.5, -0.25, 0.25, 0.5], size=(n, n))
     L = np.eye(n) + np.tril(mask * vals, -1)
-    U = np.triu(rng.integers(-8, 9, size=(n, n)).astype(np.float64), 1)
-    U[np.diag_indices(n)] = rng.choice([-64.0, -48.0, -40.0, 40.0, 48.0, 64.0], size=n)
+    if sparse:
+        um = rng.random((n, n)) < 0.05
+        U = np.triu(um * rng.choice([-1.0, 1.0], size=(n, n)), 1)
+        U[np.diag_indices(n)] = rng.choice([-16.0, -8.0, 8.0, 16.0], size=n)
+    else:
+        U = np.triu(rng.integers(-8, 9, size=(n, n)).astype(np.float64), 1)
+        U[np.diag_indices(n)] = rng.choice([-64.0, -48.0, -40.0, 40.0, 48.0, 64.0], size=n)
     A = L @ U                       # exact: multiples of 1/4 well below 2^53
     assert np.abs(A).max() < 2.0**8
     return L, U, A
@@ -50,28 +58,40 @@ def exact_lu(n, seed):
 # so with s = -128 (-1024, -16) about a third of the entries of A and of U
 # are subnormal.  Binary16 factors (f16mixed: binary16 L and U, binary32
 # trailing matrix) are exact too: every entry is a multiple of 2^(s-2)
-# below 2^(s+7), within binary16's 11 significant bits.
-CASES = [("f32", -128), ("f64", -1024), ("f32", 0), ("f64", 0), ("f16", 0), ("f16", -16)]
+# below 2^(s+7), within binary16's 11 significant bits; bfloat16 factors
+# (8 significant bits) take the sparse matrix, with s = -130 reaching
+# bfloat16's subnormal range (below 2^-126).
+CASES = [("f32", -128), ("f64", -1024), ("f32", 0), ("f64", 0), ("f16", 0), ("f16", -16),
+         ("bf16", 0), ("bf16", -130)]
+
+
+def _representable(x, tfname):
+    if tfname == "bf16":
+        y = torch.from_numpy(x.astype(np.float32)).to(torch.bfloat16).to(torch.float64).numpy()
+    else:
+        y = x.astype({"f32": np.float32, "f64": np.float64, "f16": np.float16}[tfname]).astype(np.float64)
+    return np.array_equal(y, x)
 
 
 @pytest.mark.parametrize("tfname,s", CASES, ids=[f"{t}_s{s}" for t, s in CASES])
 def test_exact_factors(M, tfname, s):
     n = 1600        # several 512-column panels: leaves, in-panel and trailing updates
     say(f"exact LU tf={tfname} n={n} scale=2^{s}")
-    L, U, A = exact_lu(n, seed=11)
+    L, U, A = exact_lu(n, seed=11, sparse=tfname == "bf16")
     As = A * 2.0**s
     assert np.array_equal(As / 2.0**s, A)            # the scaling is exact in binary64
-    tf = {"f32": M.F32, "f64": M.F64, "f16": M.F16}[tfname]
+    assert _representable(As, tfname)                # the downcast is exact
+    tf = {"f32": M.F32, "f64": M.F64, "f16": M.F16, "bf16": M.BF16}[tfname]
     At = torch.from_numpy(np.ascontiguousarray(As.T)).to(DEV)   # column-major A
     f = M.Factorization(At, tf, M.F64)
     assert f.info == 0
     lu, ipiv = f.factors()
     f.destroy()
     assert np.array_equal(ipiv, np.arange(n, dtype=np.int32))
-    dt = {"f32": np.float32, "f64": np.float64, "f16": np.float16}[tfname]
-    want = (np.tril(L, -1) + U * 2.0**s).astype(dt)
-    assert np.array_equal(want.astype(np.float64), (np.tril(L, -1) + U * 2.0**s))   # representable in TF
-    got = lu.cpu().numpy()
+    want64 = np.tril(L, -1) + U * 2.0**s
+    assert _representable(want64, tfname)            # the factors are representable in TF
+    want = want64.astype(np.float64 if tfname == "f64" else np.float32)
+    got = lu.float().cpu().numpy() if tfname in ("f16", "bf16") else lu.cpu().numpy()
     bad = np.argwhere(got != want)
     assert bad.size == 0, (len(bad), bad[:5].tolist(), [(float(got[i, j]), float(want[i, j])) for i, j in bad[:5]])
 
