@@ -134,7 +134,7 @@ def cpu_baseline(n_sample: int, n_full: int, at_full=None):
            "sample_n_iter": int(r.n_iter), "sample_factor_s": round(t_lu, 3),
            "sample_correction_s": round(t_corr, 4), "correction_timed_at_n": int(corr_at),
            "sample_ir_solve_s": round(t_all, 3)}
-    # the one full-size run of the oracle on a GPU machine's host, if recorded
+    # the one full-size run of the oracle on a GPU host's CPU, if recorded
     # (oracle/time_full_size.py)
     full = os.path.join(ROOT, "oracle", f"cpu_time_n{n_full}.json")
     if os.path.exists(full):
